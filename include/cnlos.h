@@ -1,0 +1,248 @@
+/*
+ * cnlos.h — C ABI of the MI355X (gfx950) curvature-regularized confocal NLOS
+ * reconstruction library.
+ *
+ * The library implements the ADMM solvers of Ding et al., "Curvature
+ * regularization for non-line-of-sight imaging from under-sampled data"
+ * (arXiv 2301.00406): the object-domain model (Section 3, Algorithm 1) and the
+ * dual signal/object-domain model (Section 4.1, Algorithm 2), on top of the
+ * light-cone-transform forward operator A = R_t^{-1} H R_z of Section 2,
+ * eq. (3), restricted to the measured scan points (A_D = D A, Section 3.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Volumes are C-order float32 arrays [nx][ny][nt] with the time/depth axis
+ *   fastest.  The hidden albedo u and the transient signal tau share this
+ *   layout: index (i, j) is a scan point on the wall, k a depth bin for u and
+ *   a time bin for tau.
+ * - The scan mask is uint8 [nx][ny] in HOST memory, 1 = measured.
+ * - "_dev" pointers are device pointers on the device that owns the
+ *   workspace; the caller owns them and the library keeps none of them after a
+ *   call returns (the mask and the measurement are copied into the workspace).
+ * - All device work is enqueued on the HIP stream given to cnlos_create (NULL
+ *   = the legacy default stream).  cnlos_apply_A / cnlos_apply_AT /
+ *   cnlos_get_* / cnlos_set_* are asynchronous with respect to the host;
+ *   cnlos_create, cnlos_set_measurement, cnlos_run and cnlos_get_info
+ *   synchronize the stream before they return.
+ * - Every function returns a cnlos_status and never aborts; no C++ exception
+ *   crosses the ABI.  cnlos_last_error() gives a thread-local message for the
+ *   last failing call on the calling thread.
+ * - Validation of the configuration, the mask and the workspace size happens
+ *   before any HIP call, so it needs no GPU.
+ * - After a HIP failure (CNLOS_EHIP) the handle is poisoned: every later call
+ *   except cnlos_destroy returns CNLOS_ESTATE.
+ * - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef CNLOS_H
+#define CNLOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CNLOS_VERSION_MAJOR 1
+#define CNLOS_VERSION_MINOR 0
+
+typedef enum {
+  CNLOS_OK = 0,
+  CNLOS_EINVAL = 1,        /* bad argument, configuration, mask or workspace size   */
+  CNLOS_EUNSUPPORTED = 2,  /* valid in the paper's terms but outside the supported sizes */
+  CNLOS_ENOMEM = 3,        /* host allocation failed                                 */
+  CNLOS_EHIP = 4,          /* a HIP runtime call or kernel launch failed              */
+  CNLOS_ESTATE = 5,        /* poisoned handle, or call out of order                  */
+  CNLOS_EBACKTRACK = 6,    /* backtracking found no acceptable step within bt_max_trials */
+  CNLOS_ENONFINITE = 7     /* a residual/energy reduction or the measurement is not finite */
+} cnlos_status;
+
+typedef enum {
+  CNLOS_MODEL_OPERATOR = 0, /* operator only: apply_A / apply_AT, no ADMM state      */
+  CNLOS_MODEL_OBJECT = 1,   /* Algorithm 1, object-domain curvature model eq. (4)   */
+  CNLOS_MODEL_DUAL = 2      /* Algorithm 2, dual-domain model eq. (13), warm-started by Algorithm 1 */
+} cnlos_model;
+
+typedef enum {               /* curvature weight phi(kappa), Section 3              */
+  CNLOS_PHI_TSC = 0,         /* a + b kappa^2   (total squared curvature; default)  */
+  CNLOS_PHI_TAC = 1,         /* a + b |kappa|   (total absolute curvature)          */
+  CNLOS_PHI_TRV = 2          /* sqrt(a + b kappa^2) (total roto-translation variation) */
+} cnlos_phi;
+
+typedef enum {
+  /* R_t^{-1} without its radiometric weight; the measurement is instead
+   * multiplied by rhat_k^3, rhat_k = (k + 1/2)/nt, masked and normalized to a
+   * unit maximum by cnlos_set_measurement.  Default for reconstruction.      */
+  CNLOS_FALLOFF_COMPENSATED = 0,
+  /* R_t^{-1} with the weight rhat_k^{-3} of eq. (3) taken literally (the
+   * measurement is only masked and normalized to a unit maximum).             */
+  CNLOS_FALLOFF_LITERAL = 1
+} cnlos_falloff;
+
+/* Problem description.  Fill with cnlos_config_default() and override. */
+typedef struct cnlos_config {
+  int32_t nx, ny, nt;         /* scan grid and bins; nx == ny in {8..128}, nt in {16..2048}, powers of two */
+  int32_t model;              /* cnlos_model                                                  */
+  double wall_w_m, wall_h_m;  /* scanned wall extent in metres (x, y)                         */
+  double bin_ps;              /* time-bin width in picoseconds; c = 299792458 m/s             */
+  int32_t phi;                /* cnlos_phi                                                    */
+  int32_t falloff;            /* cnlos_falloff                                                */
+  double a_u, b_u;            /* object-domain phi weights (Algorithm 1; Algorithm 2's u term) */
+  double a_tau, b_tau;        /* signal-domain phi weights (Algorithm 2)                      */
+  double warm_a, warm_b;      /* Algorithm-1 warm start of Algorithm 2; < 0: use a_u, b_u     */
+  double mu;                  /* Algorithm-1 penalty mu (also the warm start's)               */
+  double mu1, mu2, mu3;       /* Algorithm-2 penalties (paper: 1, 800, 2)                     */
+  double lambda;              /* Algorithm-2 fidelity weight                                  */
+  double eta_curv;            /* curvature regularizer eta in grad u / sqrt(|grad u|^2+eta^2) */
+  int32_t max_iters;          /* ADMM iterations T_max (Algorithm 2's, for the dual model)    */
+  int32_t init_iters;         /* dual model: Algorithm-1 warm-start iterations                */
+  double eps_stop;            /* relative energy change stop; 0 = fixed iteration count       */
+  int32_t backtracking;       /* 1 = Beck-Teboulle backtracking on L                          */
+  int32_t bt_max_trials;      /* rejections allowed per iteration before CNLOS_EBACKTRACK     */
+  double L0;                  /* initial step constant; <= 0: 2 * power-iteration estimate of ||A_D||^2 */
+  double L0_dual;             /* dual model: Algorithm-2 step constant; <= 0: 2 * estimate of ||A||^2 */
+  double bt_factor;           /* L <- bt_factor * L on rejection (> 1)                         */
+  int32_t power_iters;        /* power-iteration steps for the estimate (from the ones vector) */
+  int32_t reserved0;
+} cnlos_config;
+
+/* Fields of the ADMM state, for checkpoint/resume and inspection.
+ * Three-component fields (V, LAM, W, LAM2) are [3][nx][ny][nt] (x, y, t).   */
+typedef enum {
+  CNLOS_FIELD_U = 0,        /* u^k                                          */
+  CNLOS_FIELD_UBAR = 1,     /* extrapolated ubar^k                          */
+  CNLOS_FIELD_V = 2,        /* splitting variable v = grad u                */
+  CNLOS_FIELD_LAM = 3,      /* multiplier Lambda (Lambda_1)                 */
+  CNLOS_FIELD_PHI = 4,      /* curvature weight phi(kappa(u))               */
+  CNLOS_FIELD_AU = 5,       /* A u^k (unmasked)                             */
+  CNLOS_FIELD_AU_PREV = 6,  /* A u^{k-1} (unmasked)                         */
+  CNLOS_FIELD_TAU0 = 7,     /* normalized measurement (read-only)           */
+  CNLOS_FIELD_TAU = 8,      /* dual model: tau^k                            */
+  CNLOS_FIELD_TAUBAR = 9,   /* dual model: extrapolated taubar^k            */
+  CNLOS_FIELD_W = 10,       /* dual model: w = grad tau                     */
+  CNLOS_FIELD_LAM2 = 11,    /* dual model: Lambda_2                         */
+  CNLOS_FIELD_F = 12,       /* dual model: f = tau                          */
+  CNLOS_FIELD_LAM3 = 13,    /* dual model: Lambda_3                         */
+  CNLOS_FIELD_PHI_TAU = 14, /* dual model: phi(kappa(tau))                  */
+  CNLOS_FIELD_COUNT = 15
+} cnlos_field;
+
+typedef struct cnlos_problem cnlos_problem;  /* opaque */
+
+typedef struct cnlos_report {
+  int32_t iters_done;       /* iterations accepted in this call                 */
+  int32_t total_iters;      /* iterations accepted since create/reset           */
+  int32_t stopped_early;    /* 1 if the eps_stop rule fired                     */
+  int32_t bt_rejects;       /* rejected backtracking trials in this call        */
+  double L_final;           /* step constant after the call                     */
+  double energy;            /* E(u) (object) or E(u, tau) (dual) after the call */
+  double primal_res;        /* ||v - grad u||                                   */
+  double dual_res;          /* mu ||grad(u^{k+1} - u^k)||                       */
+} cnlos_report;
+
+typedef struct cnlos_info {
+  double L0_obj;            /* step constant used by Algorithm 1 (and the warm start) */
+  double L0_dual;           /* step constant used by Algorithm 2                      */
+  double L;                 /* current step constant                                  */
+  double t;                 /* current FISTA t_k                                      */
+  double beta;              /* extrapolation weight that produced ubar^k              */
+  double meas_scale;        /* normalization s of the measurement                     */
+  double energy_prev;       /* last energy (NaN before the first iteration)           */
+  int32_t iter;             /* accepted iterations since create/reset                 */
+  int32_t stage;            /* 1 = Algorithm 1 (or warm start), 2 = Algorithm 2       */
+  int32_t bt_rejects;       /* rejected trials since create/reset                     */
+  int32_t has_measurement;  /* cnlos_set_measurement has been called                  */
+} cnlos_info;
+
+/* Library version string "major.minor". */
+const char* cnlos_version(void);
+
+/* Defaults: 16x16x128, 1 m wall, 32 ps, object model, TSC, compensated
+ * falloff, a = b = 5e-5, mu = 0.1 (the Bowling parameters printed with the
+ * full-sampling comparison of Section 5.2.1), mu1..3 = 1, 800, 2 (Section
+ * 5.1), lambda = 200, eta = 1e-3, 50 iterations, 50 warm-start iterations,
+ * eps = 0, backtracking on with factor 2 and 20 trials, L0 from 15 power
+ * iterations.  cfg must not be NULL. */
+void cnlos_config_default(cnlos_config* cfg);
+
+/* Check a configuration (and, if mask_host is not NULL, the mask: at least one
+ * measured point).  Touches no device.  Returns CNLOS_OK, CNLOS_EINVAL or
+ * CNLOS_EUNSUPPORTED. */
+cnlos_status cnlos_validate(const cnlos_config* cfg, const uint8_t* mask_host);
+
+/* Device workspace bytes that cnlos_create needs for cfg (validates cfg).
+ * Touches no device. */
+cnlos_status cnlos_workspace_bytes(const cnlos_config* cfg, uint64_t* bytes);
+
+/* Create a problem in a caller-owned device workspace of at least
+ * cnlos_workspace_bytes(cfg) bytes, 256-byte aligned.  Builds the resampling
+ * tables and the kernel spectrum H^ (eq. (3)), and, for the solver models,
+ * the step constants L0 = 2 * estimate of ||A_D||^2 (Section 3.1, the choice
+ * of L after eq. (10); the dual model also estimates ||A||^2 for its
+ * unmasked u-step).  Synchronizes the stream.  The workspace must outlive the
+ * handle; the library never frees it. */
+cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host,
+                          void* workspace_dev, uint64_t workspace_bytes,
+                          void* hip_stream, cnlos_problem** out);
+
+/* Load a raw measurement tau0_dev [nx][ny][nt] (photon counts, any finite
+ * non-negative scale).  Forms the normalized data of the selected falloff
+ * (see cnlos_falloff) masked by D; CNLOS_ENONFINITE if it has a non-finite
+ * value, CNLOS_EINVAL if it has no positive value on a measured point.
+ * Synchronizes the stream. */
+cnlos_status cnlos_set_measurement(cnlos_problem* p, const float* tau0_dev);
+
+/* tau = A u, or D A u when masked != 0 (eq. (3); A_D of Section 3.1).
+ * u_dev and tau_dev are [nx][ny][nt]; they may not alias.  Asynchronous. */
+cnlos_status cnlos_apply_A(cnlos_problem* p, const float* u_dev, float* tau_dev, int32_t masked);
+
+/* u = A^T tau, or A^T D tau when masked != 0 (the adjoint used in the gradient
+ * of the data term, Section 3.1).  May not alias.  Asynchronous. */
+cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev, int32_t masked);
+
+/* Run ADMM iterations: iters > 0 runs that many more (counting warm-start
+ * iterations of the dual model), iters <= 0 runs to completion
+ * (max_iters, plus init_iters for the dual model).  Resumable: two calls of
+ * T1 and T2 iterations equal one call of T1 + T2.  Stops early when eps_stop > 0
+ * and the relative energy change falls to eps_stop.  Requires a measurement.
+ * Fills *out if it is not NULL.  Synchronizes the stream. */
+cnlos_status cnlos_run(cnlos_problem* p, int32_t iters, cnlos_report* out);
+
+/* Zero the ADMM state (u = ubar = 0, multipliers 0, phi = a, t = 1, L = L0),
+ * keeping H^, the step constants and the measurement.  Asynchronous. */
+cnlos_status cnlos_reset(cnlos_problem* p);
+
+/* Copy the current volume u [nx][ny][nt] to u_dev.  Asynchronous. */
+cnlos_status cnlos_get_volume(cnlos_problem* p, float* u_dev);
+
+/* Dual model: copy the current signal estimate tau [nx][ny][nt].  Asynchronous. */
+cnlos_status cnlos_get_signal(cnlos_problem* p, float* tau_dev);
+
+/* Copy a state field out / in (checkpoint and resume).  Sizes per cnlos_field.
+ * CNLOS_FIELD_TAU0 is read-only; dual-model fields need the dual model.
+ * Asynchronous. */
+cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev);
+cnlos_status cnlos_set_field(cnlos_problem* p, int32_t field, const float* src_dev);
+
+/* Scalars of the run (synchronizes the stream), and their restore for resume
+ * (sets L, t, beta, energy_prev, iter, stage, bt_rejects; the step constants
+ * and meas_scale are ignored).  */
+cnlos_status cnlos_get_info(cnlos_problem* p, cnlos_info* out);
+cnlos_status cnlos_set_info(cnlos_problem* p, const cnlos_info* in);
+
+/* Per-iteration log, oldest first, up to cap rows of 6 doubles:
+ * (energy, primal_res, dual_res, L, rejected trials, relative energy change).
+ * The library keeps the last 4096 iterations.  *n receives the row count.
+ * Synchronizes the stream. */
+cnlos_status cnlos_get_log(cnlos_problem* p, double* host, int32_t cap, int32_t* n);
+
+/* Release the handle (the workspace stays the caller's).  NULL is accepted. */
+cnlos_status cnlos_destroy(cnlos_problem* p);
+
+/* Thread-local message for the last failing call on this thread ("" if none). */
+const char* cnlos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNLOS_H */

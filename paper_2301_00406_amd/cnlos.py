@@ -1,0 +1,274 @@
+"""Python binding of libcnlos (ctypes).  Argument marshalling only: every step
+of the reconstruction runs in the HIP library; PyTorch provides device memory
+and the stream.  The library must be built (``build_lib.build()``); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_int32, c_uint8, c_uint64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcnlos.so")
+
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ESTATE, EBACKTRACK, ENONFINITE = range(8)
+MODEL_OPERATOR, MODEL_OBJECT, MODEL_DUAL = 0, 1, 2
+PHI_TSC, PHI_TAC, PHI_TRV = 0, 1, 2
+FALLOFF_COMPENSATED, FALLOFF_LITERAL = 0, 1
+(FIELD_U, FIELD_UBAR, FIELD_V, FIELD_LAM, FIELD_PHI, FIELD_AU, FIELD_AU_PREV, FIELD_TAU0,
+ FIELD_TAU, FIELD_TAUBAR, FIELD_W, FIELD_LAM2, FIELD_F, FIELD_LAM3, FIELD_PHI_TAU) = range(15)
+VECTOR_FIELDS = {FIELD_V, FIELD_LAM, FIELD_W, FIELD_LAM2}
+
+_STATUS_NAMES = {OK: "CNLOS_OK", EINVAL: "CNLOS_EINVAL", EUNSUPPORTED: "CNLOS_EUNSUPPORTED",
+                 ENOMEM: "CNLOS_ENOMEM", EHIP: "CNLOS_EHIP", ESTATE: "CNLOS_ESTATE",
+                 EBACKTRACK: "CNLOS_EBACKTRACK", ENONFINITE: "CNLOS_ENONFINITE"}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32), ("nt", c_int32), ("model", c_int32),
+        ("wall_w_m", c_double), ("wall_h_m", c_double), ("bin_ps", c_double),
+        ("phi", c_int32), ("falloff", c_int32),
+        ("a_u", c_double), ("b_u", c_double), ("a_tau", c_double), ("b_tau", c_double),
+        ("warm_a", c_double), ("warm_b", c_double), ("mu", c_double),
+        ("mu1", c_double), ("mu2", c_double), ("mu3", c_double), ("lambda_", c_double),
+        ("eta_curv", c_double),
+        ("max_iters", c_int32), ("init_iters", c_int32),
+        ("eps_stop", c_double),
+        ("backtracking", c_int32), ("bt_max_trials", c_int32),
+        ("L0", c_double), ("L0_dual", c_double), ("bt_factor", c_double),
+        ("power_iters", c_int32), ("reserved0", c_int32),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iters_done", c_int32), ("total_iters", c_int32), ("stopped_early", c_int32),
+                ("bt_rejects", c_int32), ("L_final", c_double), ("energy", c_double),
+                ("primal_res", c_double), ("dual_res", c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("L0_obj", c_double), ("L0_dual", c_double), ("L", c_double), ("t", c_double),
+                ("beta", c_double), ("meas_scale", c_double), ("energy_prev", c_double),
+                ("iter", c_int32), ("stage", c_int32), ("bt_rejects", c_int32),
+                ("has_measurement", c_int32)]
+
+
+class CnlosError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libcnlos.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "paper_2301_00406_amd.build_lib.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "cnlos_version": ([], ctypes.c_char_p),
+        "cnlos_last_error": ([], ctypes.c_char_p),
+        "cnlos_config_default": ([POINTER(Config)], None),
+        "cnlos_validate": ([POINTER(Config), POINTER(c_uint8)], c_int32),
+        "cnlos_workspace_bytes": ([POINTER(Config), POINTER(c_uint64)], c_int32),
+        "cnlos_create": ([POINTER(Config), POINTER(c_uint8), P, c_uint64, P, POINTER(P)], c_int32),
+        "cnlos_set_measurement": ([P, P], c_int32),
+        "cnlos_apply_A": ([P, P, P, c_int32], c_int32),
+        "cnlos_apply_AT": ([P, P, P, c_int32], c_int32),
+        "cnlos_run": ([P, c_int32, POINTER(Report)], c_int32),
+        "cnlos_reset": ([P], c_int32),
+        "cnlos_get_volume": ([P, P], c_int32),
+        "cnlos_get_signal": ([P, P], c_int32),
+        "cnlos_get_field": ([P, c_int32, P], c_int32),
+        "cnlos_set_field": ([P, c_int32, P], c_int32),
+        "cnlos_get_info": ([P, POINTER(Info)], c_int32),
+        "cnlos_set_info": ([P, POINTER(Info)], c_int32),
+        "cnlos_get_log": ([P, POINTER(c_double), c_int32, POINTER(c_int32)], c_int32),
+        "cnlos_destroy": ([P], c_int32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().cnlos_last_error().decode()
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise CnlosError(status, last_error())
+
+
+def default_config(**overrides) -> Config:
+    cfg = Config()
+    load().cnlos_config_default(byref(cfg))
+    for k, v in overrides.items():
+        key = "lambda_" if k == "lam" else k
+        if not hasattr(cfg, key):
+            raise AttributeError(k)
+        setattr(cfg, key, v)
+    return cfg
+
+
+def validate(cfg: Config, mask=None) -> int:
+    lib = load()
+    if mask is None:
+        return lib.cnlos_validate(byref(cfg), None)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return lib.cnlos_validate(byref(cfg), m.ctypes.data_as(POINTER(c_uint8)))
+
+
+def workspace_bytes(cfg: Config) -> int:
+    n = c_uint64()
+    check(load().cnlos_workspace_bytes(byref(cfg), byref(n)))
+    return int(n.value)
+
+
+def _dev_f32(t, shape, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype != torch.float32 or t.device != device or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous float32 tensor on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One reconstruction problem in a device workspace owned by this object."""
+
+    def __init__(self, cfg: Config, mask, device=None, stream=None, workspace=None):
+        import torch
+        self._lib = load()
+        self.cfg = cfg
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.shape = (cfg.nx, cfg.ny, cfg.nt)
+        nbytes = workspace_bytes(cfg)
+        if workspace is None:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        elif workspace.numel() < nbytes:
+            raise ValueError("workspace too small")
+        self.workspace = workspace
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        if m.shape != (cfg.nx, cfg.ny):
+            raise ValueError(f"mask must be {(cfg.nx, cfg.ny)}")
+        self.mask = m
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._lib.cnlos_create(byref(cfg), m.ctypes.data_as(POINTER(c_uint8)),
+                                        c_void_p(workspace.data_ptr()), c_uint64(nbytes),
+                                        c_void_p(self.stream.cuda_stream), byref(h))
+        self._h = h
+        if st != OK:
+            msg = last_error()
+            self.close()
+            raise CnlosError(st, msg)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            self._lib.cnlos_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vol(self, t):
+        return _dev_f32(t, self.shape, self.device)
+
+    def _empty(self, shape=None):
+        import torch
+        return torch.empty(shape or self.shape, dtype=torch.float32, device=self.device)
+
+    # -- operator
+    def set_measurement(self, tau0):
+        check(self._lib.cnlos_set_measurement(self._h, self._vol(tau0)))
+
+    def apply_A(self, u, masked=False, out=None):
+        out = self._empty() if out is None else out
+        check(self._lib.cnlos_apply_A(self._h, self._vol(u), self._vol(out), int(bool(masked))))
+        return out
+
+    def apply_AT(self, tau, masked=False, out=None):
+        out = self._empty() if out is None else out
+        check(self._lib.cnlos_apply_AT(self._h, self._vol(tau), self._vol(out), int(bool(masked))))
+        return out
+
+    # -- solver
+    def run(self, iters=0):
+        rep = Report()
+        st = self._lib.cnlos_run(self._h, int(iters), byref(rep))
+        if st != OK:
+            raise CnlosError(st, last_error())
+        return {f: getattr(rep, f) for f, _ in Report._fields_}
+
+    def run_status(self, iters=0):
+        """Like run() but returns (status, report) instead of raising."""
+        rep = Report()
+        st = self._lib.cnlos_run(self._h, int(iters), byref(rep))
+        return st, {f: getattr(rep, f) for f, _ in Report._fields_}
+
+    def reset(self):
+        check(self._lib.cnlos_reset(self._h))
+
+    def volume(self):
+        out = self._empty()
+        check(self._lib.cnlos_get_volume(self._h, self._vol(out)))
+        return out
+
+    def signal(self):
+        out = self._empty()
+        check(self._lib.cnlos_get_signal(self._h, self._vol(out)))
+        return out
+
+    def _field_shape(self, field):
+        return ((3,) + self.shape) if field in VECTOR_FIELDS else self.shape
+
+    def get_field(self, field):
+        shp = self._field_shape(field)
+        out = self._empty(shp)
+        check(self._lib.cnlos_get_field(self._h, int(field), _dev_f32(out, shp, self.device)))
+        return out
+
+    def set_field(self, field, src):
+        shp = self._field_shape(field)
+        check(self._lib.cnlos_set_field(self._h, int(field), _dev_f32(src, shp, self.device)))
+
+    def info(self):
+        inf = Info()
+        check(self._lib.cnlos_get_info(self._h, byref(inf)))
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def set_info(self, d):
+        inf = Info()
+        for f, _ in Info._fields_:
+            if f in d:
+                setattr(inf, f, d[f])
+        check(self._lib.cnlos_set_info(self._h, byref(inf)))
+
+    def log(self, cap=4096):
+        buf = np.zeros((cap, 6), dtype=np.float64)
+        n = c_int32()
+        check(self._lib.cnlos_get_log(self._h, buf.ctypes.data_as(POINTER(c_double)), cap, byref(n)))
+        return buf[: n.value].copy()

@@ -1,0 +1,966 @@
+// Host side of the C ABI: validation, workspace carving, table construction,
+// problem set-up (H^, step constants) and the ADMM driver of Algorithms 1 and 2.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cnlos.h"
+#include "cnlos_internal.h"
+
+using namespace cnlos;
+
+namespace {
+
+constexpr double kC = 299792458.0;
+thread_local std::string g_err;
+
+cnlos_status fail(cnlos_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+bool finite_nonneg(double x) { return isfinite(x) && x >= 0.0; }
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+// Workspace carving.  With base == nullptr only the size is computed.
+struct Carver {
+  uint8_t* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct cnlos_problem {
+  cnlos_config cfg;
+  int logn = 0, logm = 0;
+  size_t V = 0;
+  int nn = 0;
+  hipStream_t st = nullptr;
+  uint8_t* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  bool poisoned = false;
+  bool has_meas = false;
+  int iter_host = 0;
+  DevCtl* ctl = nullptr;
+  DevCtl* ctl_host = nullptr;   // pinned mirror
+  double* partials = nullptr;
+  double* logbuf = nullptr;
+  float2* spec = nullptr;
+  float2* hq = nullptr;
+  float2* tw_t = nullptr;
+  float2* tw_xy = nullptr;
+  int4* srows = nullptr;
+  float* srvals = nullptr;
+  int4* scols = nullptr;
+  float* scvals = nullptr;
+  float* wk = nullptr;
+  float* r3 = nullptr;
+  float* sig_xy = nullptr;
+  float* sig_t = nullptr;
+  uint8_t* mask = nullptr;
+  float* tau0 = nullptr;
+  float* U[2] = {nullptr, nullptr};
+  float* ubar = nullptr;
+  float* v = nullptr;
+  float* lam = nullptr;
+  float* phi = nullptr;
+  float* AU[3] = {nullptr, nullptr, nullptr};
+  float* gf = nullptr;
+  float* T[2] = {nullptr, nullptr};
+  float* taubar = nullptr;
+  float* w = nullptr;
+  float* lam2 = nullptr;
+  float* f = nullptr;
+  float* lam3 = nullptr;
+  float* phi_tau = nullptr;
+  Tables tb;
+  int nb_conv = 0, nb_sten = 0;
+  int nnz_r = 0;
+};
+
+namespace {
+
+int resample_nnz(int m) {
+  // counted exactly when the tables are built; this bound sizes the buffer
+  return 3 * m + 64;
+}
+
+size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
+  Carver cv{base};
+  const int n = c.nx, m = c.nt;
+  const size_t V = (size_t)n * n * m;
+  const size_t nn = (size_t)n * n;
+  const size_t nspec = (size_t)(m + 1) * nn;
+  const size_t nhq = (size_t)(m + 1) * (n + 1) * (n + 1);
+  DevCtl* ctl = cv.take<DevCtl>(1);
+  double* partials = cv.take<double>((size_t)SL_COUNT * kMaxBlocks);
+  double* logbuf = cv.take<double>((size_t)kLogRows * kLogCols);
+  float2* spec = cv.take<float2>(nspec);
+  float2* hq = cv.take<float2>(nhq);
+  float2* tw_t = cv.take<float2>(m);
+  float2* tw_xy = cv.take<float2>(n);
+  int4* srows = cv.take<int4>(m);
+  float* srvals = cv.take<float>(resample_nnz(m));
+  int4* scols = cv.take<int4>(m);
+  float* scvals = cv.take<float>(resample_nnz(m));
+  float* wk = cv.take<float>(m);
+  float* r3 = cv.take<float>(m);
+  float* sig_xy = cv.take<float>(n);
+  float* sig_t = cv.take<float>(m / 2 + 1);
+  uint8_t* mask = cv.take<uint8_t>(nn);
+  if (p) {
+    p->ctl = ctl;
+    p->partials = partials;
+    p->logbuf = logbuf;
+    p->spec = spec;
+    p->hq = hq;
+    p->tw_t = tw_t;
+    p->tw_xy = tw_xy;
+    p->srows = srows;
+    p->srvals = srvals;
+    p->scols = scols;
+    p->scvals = scvals;
+    p->wk = wk;
+    p->r3 = r3;
+    p->sig_xy = sig_xy;
+    p->sig_t = sig_t;
+    p->mask = mask;
+  }
+  if (c.model == CNLOS_MODEL_OPERATOR) return align_up(cv.off);
+  float* tau0 = cv.take<float>(V);
+  float* U0 = cv.take<float>(V);
+  float* U1 = cv.take<float>(V);
+  float* ubar = cv.take<float>(V);
+  float* v = cv.take<float>(3 * V);
+  float* lam = cv.take<float>(3 * V);
+  float* phi = cv.take<float>(V);
+  float* A0 = cv.take<float>(V);
+  float* A1 = cv.take<float>(V);
+  float* A2 = cv.take<float>(V);
+  float* gf = cv.take<float>(V);
+  if (p) {
+    p->tau0 = tau0;
+    p->U[0] = U0;
+    p->U[1] = U1;
+    p->ubar = ubar;
+    p->v = v;
+    p->lam = lam;
+    p->phi = phi;
+    p->AU[0] = A0;
+    p->AU[1] = A1;
+    p->AU[2] = A2;
+    p->gf = gf;
+  }
+  if (c.model == CNLOS_MODEL_DUAL) {
+    float* T0 = cv.take<float>(V);
+    float* T1 = cv.take<float>(V);
+    float* taubar = cv.take<float>(V);
+    float* w = cv.take<float>(3 * V);
+    float* lam2 = cv.take<float>(3 * V);
+    float* f = cv.take<float>(V);
+    float* lam3 = cv.take<float>(V);
+    float* phi_tau = cv.take<float>(V);
+    if (p) {
+      p->T[0] = T0;
+      p->T[1] = T1;
+      p->taubar = taubar;
+      p->w = w;
+      p->lam2 = lam2;
+      p->f = f;
+      p->lam3 = lam3;
+      p->phi_tau = phi_tau;
+    }
+  }
+  return align_up(cv.off);
+}
+
+cnlos_status validate_cfg(const cnlos_config* c) {
+  if (!c) return fail(CNLOS_EINVAL, "config is NULL");
+  if (c->nx <= 0 || c->ny <= 0 || c->nt <= 0) return fail(CNLOS_EINVAL, "nx, ny, nt must be positive");
+  if (c->nx != c->ny) return fail(CNLOS_EUNSUPPORTED, "only square scan grids (nx == ny) are supported");
+  if (!is_pow2(c->nx) || c->nx < 8 || c->nx > 128)
+    return fail(CNLOS_EUNSUPPORTED, "nx must be a power of two in [8, 128]");
+  if (!is_pow2(c->nt) || c->nt < 16 || c->nt > 2048)
+    return fail(CNLOS_EUNSUPPORTED, "nt must be a power of two in [16, 2048]");
+  if (!finite_pos(c->wall_w_m) || !finite_pos(c->wall_h_m)) return fail(CNLOS_EINVAL, "wall extent must be positive");
+  if (!finite_pos(c->bin_ps)) return fail(CNLOS_EINVAL, "bin_ps must be positive");
+  if (c->model < 0 || c->model > 2) return fail(CNLOS_EINVAL, "unknown model");
+  if (c->phi < 0 || c->phi > 2) return fail(CNLOS_EINVAL, "unknown phi kind");
+  if (c->falloff < 0 || c->falloff > 1) return fail(CNLOS_EINVAL, "unknown falloff mode");
+  if (c->model == CNLOS_MODEL_OPERATOR) return CNLOS_OK;
+  if (!finite_nonneg(c->a_u) || !finite_nonneg(c->b_u)) return fail(CNLOS_EINVAL, "a_u, b_u must be >= 0");
+  if (!finite_pos(c->mu)) return fail(CNLOS_EINVAL, "mu must be > 0");
+  if (!finite_pos(c->eta_curv)) return fail(CNLOS_EINVAL, "eta_curv must be > 0");
+  if (c->max_iters < 0 || c->init_iters < 0) return fail(CNLOS_EINVAL, "iteration counts must be >= 0");
+  if (!finite_nonneg(c->eps_stop)) return fail(CNLOS_EINVAL, "eps_stop must be >= 0");
+  if (!(isfinite(c->bt_factor) && c->bt_factor > 1.0)) return fail(CNLOS_EINVAL, "bt_factor must be > 1");
+  if (c->bt_max_trials < 0) return fail(CNLOS_EINVAL, "bt_max_trials must be >= 0");
+  if (!isfinite(c->L0) || !isfinite(c->L0_dual)) return fail(CNLOS_EINVAL, "L0, L0_dual must be finite");
+  if ((c->L0 <= 0.0 || (c->model == CNLOS_MODEL_DUAL && c->L0_dual <= 0.0)) && c->power_iters < 1)
+    return fail(CNLOS_EINVAL, "power_iters must be >= 1 when a step constant is estimated");
+  if (c->model == CNLOS_MODEL_DUAL) {
+    if (!finite_nonneg(c->a_tau) || !finite_nonneg(c->b_tau)) return fail(CNLOS_EINVAL, "a_tau, b_tau must be >= 0");
+    if (!finite_pos(c->mu1) || !finite_pos(c->mu2) || !finite_pos(c->mu3))
+      return fail(CNLOS_EINVAL, "mu1, mu2, mu3 must be > 0");
+    if (!finite_pos(c->lambda)) return fail(CNLOS_EINVAL, "lambda must be > 0");
+    if (!isfinite(c->warm_a) || !isfinite(c->warm_b)) return fail(CNLOS_EINVAL, "warm_a, warm_b must be finite");
+  }
+  return CNLOS_OK;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      p->poisoned = true;                                                              \
+      return fail(CNLOS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    }                                                                                  \
+  } while (0)
+
+PhiArgs phi_args(const cnlos_problem* p, int stage, bool tau) {
+  const cnlos_config& c = p->cfg;
+  PhiArgs pa;
+  pa.kind = c.phi;
+  pa.eta = (float)c.eta_curv;
+  if (tau) {
+    pa.a = c.a_tau;
+    pa.b = c.b_tau;
+  } else if (c.model == CNLOS_MODEL_DUAL && stage == 1) {
+    pa.a = c.warm_a >= 0.0 ? c.warm_a : c.a_u;
+    pa.b = c.warm_b >= 0.0 ? c.warm_b : c.b_u;
+  } else {
+    pa.a = c.a_u;
+    pa.b = c.b_u;
+  }
+  return pa;
+}
+
+double phi_at_zero(const PhiArgs& pa) { return pa.kind == 2 ? sqrt(pa.a) : pa.a; }
+
+cnlos_status ctl_pull(cnlos_problem* p) {
+  HIPCHK(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+cnlos_status ctl_push(cnlos_problem* p) {
+  HIPCHK(hipMemcpyAsync(p->ctl, p->ctl_host, sizeof(DevCtl), hipMemcpyHostToDevice, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+// One padded convolution of the problem (forward or adjoint).
+hipError_t conv(cnlos_problem* p, const ConvSrc& src, bool adjoint, int epi, const ConvEpi& ep,
+                const DevCtl* ctl) {
+  return launch_conv(p->logn, p->logm, p->tb, src, p->spec, adjoint, epi, ep, ctl, p->st);
+}
+
+// ||B||^2 by power iteration (B = A_D when masked, else A), from the ones vector.
+cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
+  float* X = p->AU[0];
+  float* Y = p->AU[1];
+  HIPCHK(launch_fill(X, p->V, (float)(1.0 / sqrt((double)p->V)), p->st));
+  for (int it = 0; it < p->cfg.power_iters; ++it) {
+    ConvSrc s1{};
+    s1.a = X;
+    s1.scale_div = it > 0 ? &p->ctl->pow_est : nullptr;
+    ConvEpi e1{};
+    e1.out = Y;
+    e1.w = p->wk;
+    e1.mask = masked ? p->mask : nullptr;
+    HIPCHK(conv(p, s1, false, EPI_PLAIN, e1, nullptr));
+    ConvSrc s2{};
+    s2.a = Y;
+    s2.w = p->wk;
+    s2.mask = masked ? p->mask : nullptr;
+    ConvEpi e2{};
+    e2.out = X;
+    e2.partials = p->partials;
+    HIPCHK(conv(p, s2, true, EPI_NORM, e2, nullptr));
+    HIPCHK(launch_pow_finalize(p->ctl, p->partials, p->nb_conv, p->st));
+  }
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  *est = p->ctl_host->pow_est;
+  if (!isfinite(*est) || *est <= 0.0) return fail(CNLOS_ENONFINITE, "power iteration gave no positive norm estimate");
+  return CNLOS_OK;
+}
+
+cnlos_status reset_state(cnlos_problem* p) {
+  const size_t V = p->V;
+  float* zero[] = {p->U[0], p->U[1], p->ubar, p->AU[0], p->AU[1], p->AU[2], p->gf};
+  for (float* z : zero) HIPCHK(launch_fill(z, V, 0.f, p->st));
+  HIPCHK(launch_fill(p->v, 3 * V, 0.f, p->st));
+  HIPCHK(launch_fill(p->lam, 3 * V, 0.f, p->st));
+  HIPCHK(launch_fill(p->phi, V, (float)phi_at_zero(phi_args(p, 1, false)), p->st));
+  if (p->cfg.model == CNLOS_MODEL_DUAL) {
+    float* zd[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3};
+    for (float* z : zd) HIPCHK(launch_fill(z, V, 0.f, p->st));
+    HIPCHK(launch_fill(p->w, 3 * V, 0.f, p->st));
+    HIPCHK(launch_fill(p->lam2, 3 * V, 0.f, p->st));
+    HIPCHK(launch_fill(p->phi_tau, V, (float)phi_at_zero(phi_args(p, 2, true)), p->st));
+  }
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  DevCtl& c = *p->ctl_host;
+  c.L = c.L0_obj;
+  c.t = 1.0;
+  c.beta = 0.0;
+  c.energy_prev = NAN;
+  c.halt = 0;
+  c.reason = HR_NONE;
+  c.iter = 0;
+  c.trials = 0;
+  c.bt_rejects = 0;
+  c.stage = 1;
+  c.log_count = 0;
+  p->iter_host = 0;
+  return ctl_push(p);
+}
+
+// Enqueue ADMM iteration number k (0-based) assuming iterations 0..k-1 were
+// accepted; buffer roles rotate with k.
+cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
+  const cnlos_config& c = p->cfg;
+  const int ln = p->logn, lm = p->logm;
+  const bool dual_model = c.model == CNLOS_MODEL_DUAL;
+  const int stage = (dual_model && k >= c.init_iters) ? 2 : 1;
+  float* u_cur = p->U[k & 1];
+  float* u_tr = p->U[(k + 1) & 1];
+  float* au_cur = p->AU[k % 3];
+  float* au_prev = p->AU[(k + 2) % 3];
+  float* au_tr = p->AU[(k + 1) % 3];
+  DevCtl* ctl = p->ctl;
+  const size_t V = p->V;
+
+  if (stage == 2 && k == c.init_iters) {
+    const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
+    float* zf[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3, p->w, p->lam2, p->lam};
+    size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V, 3 * V};
+    HIPCHK(launch_transition(ln, lm, ctl, u_cur, p->ubar, p->phi, pu, p->phi_tau, phi_at_zero(pt),
+                             zf, zc, 8, p->st));
+  }
+
+  if (stage == 1) {
+    const double mu = c.mu;
+    HIPCHK(launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, p->st));
+    ConvSrc sa{};
+    sa.a = au_cur;
+    sa.b = au_prev;
+    sa.c = p->tau0;
+    sa.w = p->wk;
+    sa.mask = p->mask;
+    sa.lincache = 1;
+    ConvEpi ea{};
+    ea.out = p->gf;
+    HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
+    HIPCHK(launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, p->st));
+    SolveEpi se{};
+    se.out = u_tr;
+    se.ref = p->ubar;
+    se.partials = p->partials;
+    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, p->st));
+    ConvSrc sf{};
+    sf.a = u_tr;
+    ConvEpi ef{};
+    ef.out = au_tr;
+    ef.w = p->wk;
+    ef.mask = p->mask;
+    ef.au = au_cur;
+    ef.au_prev = au_prev;
+    ef.tau0 = p->tau0;
+    ef.partials = p->partials;
+    HIPCHK(conv(p, sf, false, EPI_FWD_OBJ, ef, ctl));
+    HIPCHK(launch_check(ctl, p->partials, p->nb_conv, p->nb_conv, c.backtracking ? 1 : 0, p->st));
+    const PhiArgs pa = phi_args(p, 1, false);
+    HIPCHK(launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu, pa, nullptr,
+                       nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
+    ConvEpi dummy{};
+    (void)dummy;
+    // the data term of the energy comes from the forward pass (SL_DATA)
+    HIPCHK(launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu, p->st));
+    return CNLOS_OK;
+  }
+
+  // Algorithm 2
+  const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
+  float* tau_cur = p->T[k & 1];
+  float* tau_tr = p->T[(k + 1) & 1];
+  HIPCHK(launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, ctl, p->st));
+  HIPCHK(launch_vstep(ln, lm, p->taubar, p->lam2, p->phi_tau, p->w, mu2, ctl, p->st));
+  HIPCHK(launch_fstep(ln, lm, p->taubar, p->lam3, p->tau0, p->mask, p->f, lam, mu3, ctl, p->st));
+  ConvSrc sa{};
+  sa.a = au_cur;
+  sa.b = au_prev;
+  sa.c = p->taubar;
+  sa.w = p->wk;
+  sa.lincache = 1;
+  ConvEpi ea{};
+  ea.out = p->gf;
+  HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
+  HIPCHK(launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, p->st));
+  SolveEpi se{};
+  se.out = u_tr;
+  se.ref = p->ubar;
+  se.partials = p->partials;
+  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, p->st));
+  ConvSrc sf{};
+  sf.a = u_tr;
+  ConvEpi ef{};
+  ef.out = au_tr;
+  ef.w = p->wk;
+  ef.au = au_cur;
+  ef.au_prev = au_prev;
+  ef.partials = p->partials;
+  HIPCHK(conv(p, sf, false, EPI_FWD_DUAL, ef, ctl));
+  HIPCHK(launch_check(ctl, p->partials, p->nb_conv, p->nb_conv, c.backtracking ? 1 : 0, p->st));
+  HIPCHK(launch_rhs_tau(ln, lm, au_tr, p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3, ctl, p->st));
+  SolveEpi st2{};
+  st2.out = tau_tr;
+  st2.partials = p->partials;
+  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, p->st));
+  const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
+  HIPCHK(launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu1, pu, nullptr,
+                     nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
+  HIPCHK(launch_post(ln, lm, true, tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, mu2, pt,
+                     p->f, p->lam3, mu3, au_tr, p->tau0, p->mask, p->partials, ctl, p->st));
+  HIPCHK(launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1, p->st));
+  return CNLOS_OK;
+}
+
+float* field_ptr(cnlos_problem* p, int field, size_t* count) {
+  const size_t V = p->V;
+  const int k = p->iter_host;
+  const bool dual = p->cfg.model == CNLOS_MODEL_DUAL;
+  *count = V;
+  switch (field) {
+    case CNLOS_FIELD_U: return p->U[k & 1];
+    case CNLOS_FIELD_UBAR: return p->ubar;
+    case CNLOS_FIELD_V: *count = 3 * V; return p->v;
+    case CNLOS_FIELD_LAM: *count = 3 * V; return p->lam;
+    case CNLOS_FIELD_PHI: return p->phi;
+    case CNLOS_FIELD_AU: return p->AU[k % 3];
+    case CNLOS_FIELD_AU_PREV: return p->AU[(k + 2) % 3];
+    case CNLOS_FIELD_TAU0: return p->tau0;
+    default: break;
+  }
+  if (!dual) return nullptr;
+  switch (field) {
+    case CNLOS_FIELD_TAU: return p->T[k & 1];
+    case CNLOS_FIELD_TAUBAR: return p->taubar;
+    case CNLOS_FIELD_W: *count = 3 * V; return p->w;
+    case CNLOS_FIELD_LAM2: *count = 3 * V; return p->lam2;
+    case CNLOS_FIELD_F: return p->f;
+    case CNLOS_FIELD_LAM3: return p->lam3;
+    case CNLOS_FIELD_PHI_TAU: return p->phi_tau;
+    default: return nullptr;
+  }
+}
+
+#define CHECK_HANDLE(p)                                                      \
+  do {                                                                       \
+    if (!(p)) return fail(CNLOS_EINVAL, "problem handle is NULL");           \
+    if ((p)->poisoned) return fail(CNLOS_ESTATE, "handle poisoned by an earlier HIP failure"); \
+  } while (0)
+
+#define CHECK_SOLVER(p)                                                       \
+  do {                                                                        \
+    if ((p)->cfg.model == CNLOS_MODEL_OPERATOR)                               \
+      return fail(CNLOS_ESTATE, "operator-only problem has no ADMM state");   \
+  } while (0)
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* cnlos_version(void) { return "1.0"; }
+
+const char* cnlos_last_error(void) { return g_err.c_str(); }
+
+void cnlos_config_default(cnlos_config* c) {
+  if (!c) return;
+  memset(c, 0, sizeof(*c));
+  c->nx = c->ny = 16;
+  c->nt = 128;
+  c->model = CNLOS_MODEL_OBJECT;
+  c->wall_w_m = c->wall_h_m = 1.0;
+  c->bin_ps = 32.0;
+  c->phi = CNLOS_PHI_TSC;
+  c->falloff = CNLOS_FALLOFF_COMPENSATED;
+  c->a_u = 5e-5;
+  c->b_u = 5e-5;
+  c->a_tau = 1e-4;
+  c->b_tau = 3e-2;
+  c->warm_a = -1.0;
+  c->warm_b = -1.0;
+  c->mu = 0.1;
+  c->mu1 = 1.0;
+  c->mu2 = 800.0;
+  c->mu3 = 2.0;
+  c->lambda = 200.0;
+  c->eta_curv = 1e-3;
+  c->max_iters = 50;
+  c->init_iters = 50;
+  c->eps_stop = 0.0;
+  c->backtracking = 1;
+  c->bt_max_trials = 20;
+  c->L0 = 0.0;
+  c->L0_dual = 0.0;
+  c->bt_factor = 2.0;
+  c->power_iters = 15;
+}
+
+cnlos_status cnlos_validate(const cnlos_config* cfg, const uint8_t* mask_host) {
+  cnlos_status s = validate_cfg(cfg);
+  if (s != CNLOS_OK) return s;
+  if (mask_host) {
+    const int nn = cfg->nx * cfg->ny;
+    int kept = 0;
+    for (int i = 0; i < nn; ++i) kept += mask_host[i] != 0;
+    if (kept == 0) return fail(CNLOS_EINVAL, "mask has no measured scan point");
+  }
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_workspace_bytes(const cnlos_config* cfg, uint64_t* bytes) {
+  if (!bytes) return fail(CNLOS_EINVAL, "bytes is NULL");
+  cnlos_status s = validate_cfg(cfg);
+  if (s != CNLOS_OK) return s;
+  *bytes = (uint64_t)carve(nullptr, *cfg, nullptr);
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
+                          uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
+  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
+  cnlos_status s = cnlos_validate(cfg, mask_host);
+  if (s != CNLOS_OK) return s;
+  const size_t need = carve(nullptr, *cfg, nullptr);
+  if (!workspace_dev) return fail(CNLOS_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace_dev) % kAlign) return fail(CNLOS_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(CNLOS_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+
+  cnlos_problem* p = new (std::nothrow) cnlos_problem();
+  if (!p) return fail(CNLOS_ENOMEM, "host allocation failed");
+  p->cfg = *cfg;
+  p->logn = ilog2(cfg->nx);
+  p->logm = ilog2(cfg->nt);
+  const int n = cfg->nx, m = cfg->nt;
+  p->V = (size_t)n * n * m;
+  p->nn = n * n;
+  p->st = (hipStream_t)hip_stream;
+  p->ws = (uint8_t*)workspace_dev;
+  p->ws_bytes = workspace_bytes;
+  carve(p, *cfg, p->ws);
+  p->nb_conv = conv_blocks(p->logn, p->logm);
+  p->nb_sten = stencil_blocks(p->logn, p->logm);
+  *out = p;   // from here on errors leave a handle the caller must destroy
+
+  if (hipHostMalloc((void**)&p->ctl_host, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) {
+    p->ctl_host = nullptr;
+    p->poisoned = true;
+    return fail(CNLOS_EHIP, "pinned host allocation failed");
+  }
+  memset(p->ctl_host, 0, sizeof(DevCtl));
+
+  // ---------------- host tables (FP64) ----------------
+  const double PI = 3.14159265358979323846;
+  std::vector<float2> tw_t(m), tw_xy(n);
+  for (int j = 0; j < m; ++j) {
+    const double a = -2.0 * PI * j / (2.0 * m);
+    tw_t[j] = make_float2((float)cos(a), (float)sin(a));
+  }
+  for (int j = 0; j < n; ++j) {
+    const double a = -2.0 * PI * j / (2.0 * n);
+    tw_xy[j] = make_float2((float)cos(a), (float)sin(a));
+  }
+  // R_z as overlap lengths of [sqrt(q/m), sqrt((q+1)/m)) with [k/m, (k+1)/m), times m
+  std::vector<std::vector<std::pair<int, double>>> rows(m), cols(m);
+  for (int q = 0; q < m; ++q) {
+    const double lo = sqrt((double)q / m), hi = sqrt((double)(q + 1) / m);
+    int k0 = (int)floor(lo * m) - 1;
+    if (k0 < 0) k0 = 0;
+    int k1 = (int)ceil(hi * m) + 1;
+    if (k1 > m - 1) k1 = m - 1;
+    for (int k = k0; k <= k1; ++k) {
+      const double a = fmax(lo, (double)k / m), b = fmin(hi, (double)(k + 1) / m);
+      if (b > a) {
+        rows[q].push_back({k, m * (b - a)});
+        cols[k].push_back({q, m * (b - a)});
+      }
+    }
+  }
+  std::vector<int4> srows(m), scols(m);
+  std::vector<float> srv, scv;
+  for (int q = 0; q < m; ++q) {
+    srows[q] = make_int4(rows[q].empty() ? 0 : rows[q][0].first, (int)rows[q].size(), (int)srv.size(), 0);
+    for (size_t t = 0; t < rows[q].size(); ++t) {
+      if (rows[q][t].first != rows[q][0].first + (int)t) return fail(CNLOS_EINVAL, "resampling row not contiguous");
+      srv.push_back((float)rows[q][t].second);
+    }
+  }
+  for (int k = 0; k < m; ++k) {
+    scols[k] = make_int4(cols[k].empty() ? 0 : cols[k][0].first, (int)cols[k].size(), (int)scv.size(), 0);
+    for (size_t t = 0; t < cols[k].size(); ++t) {
+      if (cols[k][t].first != cols[k][0].first + (int)t) return fail(CNLOS_EINVAL, "resampling column not contiguous");
+      scv.push_back((float)cols[k][t].second);
+    }
+  }
+  if ((int)srv.size() > resample_nnz(m) || (int)scv.size() > resample_nnz(m))
+    return fail(CNLOS_EINVAL, "resampling table larger than its bound");
+  std::vector<float> wk(m), r3(m), sig_xy(n), sig_t(m / 2 + 1);
+  for (int k = 0; k < m; ++k) {
+    const double r = (k + 0.5) / m;
+    wk[k] = cfg->falloff == CNLOS_FALLOFF_LITERAL ? (float)(1.0 / (r * r * r)) : 1.f;
+    r3[k] = (float)(r * r * r);
+  }
+  for (int k = 0; k < n; ++k) {
+    const double s = sin(PI * k / n);
+    sig_xy[k] = (float)(4.0 * s * s);
+  }
+  for (int k = 0; k <= m / 2; ++k) {
+    const double s = sin(PI * k / m);
+    sig_t[k] = (float)(4.0 * s * s);
+  }
+  std::vector<uint8_t> mk(p->nn);
+  for (int i = 0; i < p->nn; ++i) mk[i] = mask_host[i] ? 1 : 0;
+  // cone kernel support: dq = round(m (sx dx^2 + sy dy^2)), kept when < m
+  const double R = m * kC * (cfg->bin_ps * 1e-12) / 2.0;
+  const double ax = cfg->wall_w_m / (n * R), ay = cfg->wall_h_m / (n * R);
+  const double sx = ax * ax, sy = ay * ay;
+  std::vector<int> dq((size_t)n * n);
+  long long Z = 0;
+  for (int dx = 0; dx < n; ++dx)
+    for (int dy = 0; dy < n; ++dy) {
+      const double x = (double)m * (sx * (double)(dx * dx) + sy * (double)(dy * dy));
+      const long long q = (long long)floor(x + 0.5);
+      dq[(size_t)dx * n + dy] = q < m ? (int)q : -1;
+      if (q < m) Z += (dx ? 2 : 1) * (dy ? 2 : 1);
+    }
+  std::vector<double2> etab(2 * m);
+  for (int j = 0; j < 2 * m; ++j) etab[j] = make_double2(cos(-PI * j / m), sin(-PI * j / m));
+  std::vector<double> cosn(2 * n);
+  for (int j = 0; j < 2 * n; ++j) cosn[j] = cos(PI * j / n);
+
+  // setup-only tables live in the spectrum buffer until H^ is built
+  uint8_t* scratch = reinterpret_cast<uint8_t*>(p->spec);
+  int* d_dq = reinterpret_cast<int*>(scratch);
+  double2* d_etab = reinterpret_cast<double2*>(scratch + align_up(dq.size() * sizeof(int)));
+  double* d_cosn = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(d_etab) +
+                                             align_up(etab.size() * sizeof(double2)));
+
+  auto h2d = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, p->st);
+  };
+  HIPCHK(h2d(p->tw_t, tw_t.data(), m * sizeof(float2)));
+  HIPCHK(h2d(p->tw_xy, tw_xy.data(), n * sizeof(float2)));
+  HIPCHK(h2d(p->srows, srows.data(), m * sizeof(int4)));
+  HIPCHK(h2d(p->scols, scols.data(), m * sizeof(int4)));
+  HIPCHK(h2d(p->srvals, srv.data(), srv.size() * sizeof(float)));
+  HIPCHK(h2d(p->scvals, scv.data(), scv.size() * sizeof(float)));
+  HIPCHK(h2d(p->wk, wk.data(), m * sizeof(float)));
+  HIPCHK(h2d(p->r3, r3.data(), m * sizeof(float)));
+  HIPCHK(h2d(p->sig_xy, sig_xy.data(), n * sizeof(float)));
+  HIPCHK(h2d(p->sig_t, sig_t.data(), (m / 2 + 1) * sizeof(float)));
+  HIPCHK(h2d(p->mask, mk.data(), mk.size()));
+  HIPCHK(h2d(d_dq, dq.data(), dq.size() * sizeof(int)));
+  HIPCHK(h2d(d_etab, etab.data(), etab.size() * sizeof(double2)));
+  HIPCHK(h2d(d_cosn, cosn.data(), cosn.size() * sizeof(double)));
+  HIPCHK(launch_build_hq(p->logn, p->logm, p->hq, d_dq, d_etab, d_cosn, 1.0 / (double)Z, p->st));
+
+  p->tb.tw_t = p->tw_t;
+  p->tb.tw_xy = p->tw_xy;
+  p->tb.S.rows = p->srows;
+  p->tb.S.rvals = p->srvals;
+  p->tb.S.cols = p->scols;
+  p->tb.S.cvals = p->scvals;
+  p->tb.sig_xy = p->sig_xy;
+  p->tb.sig_t = p->sig_t;
+  p->tb.hq = p->hq;
+
+  DevCtl& c = *p->ctl_host;
+  memset(&c, 0, sizeof(c));
+  c.L = c.L0_obj = c.L0_dual = 1.0;
+  c.t = 1.0;
+  c.energy_prev = NAN;
+  c.stage = 1;
+  c.bt_max_trials = cfg->bt_max_trials;
+  c.bt_factor = cfg->bt_factor;
+  c.eps_stop = cfg->eps_stop;
+  c.lambda = cfg->lambda;
+  c.meas_scale = 0.0;
+  s = ctl_push(p);   // also waits for the tables and H^
+  if (s != CNLOS_OK) return s;
+  if (cfg->model == CNLOS_MODEL_OPERATOR) return CNLOS_OK;
+
+  double L0o = cfg->L0, L0d = cfg->L0_dual;
+  if (cfg->L0 <= 0.0) {
+    double est = 0.0;
+    s = power_estimate(p, true, &est);
+    if (s != CNLOS_OK) return s;
+    L0o = 2.0 * est;
+  }
+  if (cfg->model != CNLOS_MODEL_DUAL) {
+    L0d = L0o;
+  } else if (cfg->L0_dual <= 0.0) {
+    double est = 0.0;
+    s = power_estimate(p, false, &est);
+    if (s != CNLOS_OK) return s;
+    L0d = 2.0 * est;
+  }
+  s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  p->ctl_host->L0_obj = L0o;
+  p->ctl_host->L0_dual = L0d;
+  s = ctl_push(p);
+  if (s != CNLOS_OK) return s;
+  HIPCHK(launch_fill(p->tau0, p->V, 0.f, p->st));
+  return reset_state(p);
+}
+
+cnlos_status cnlos_set_measurement(cnlos_problem* p, const float* tau0_dev) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!tau0_dev) return fail(CNLOS_EINVAL, "measurement is NULL");
+  const float* r3 = p->cfg.falloff == CNLOS_FALLOFF_COMPENSATED ? p->r3 : nullptr;
+  HIPCHK(launch_meas_prep(p->logn, p->logm, tau0_dev, p->mask, r3, p->tau0, p->partials, p->st));
+  HIPCHK(launch_meas_finish(p->logn, p->logm, p->tau0, p->ctl, p->partials, p->st));
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  if (p->ctl_host->reason == HR_NONFINITE) {
+    p->ctl_host->reason = HR_NONE;
+    ctl_push(p);
+    return fail(CNLOS_ENONFINITE, "measurement holds a non-finite value");
+  }
+  if (!(p->ctl_host->meas_scale > 0.0))
+    return fail(CNLOS_EINVAL, "measurement has no positive value on a measured scan point");
+  p->has_meas = true;
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_apply_A(cnlos_problem* p, const float* u_dev, float* tau_dev, int32_t masked) {
+  CHECK_HANDLE(p);
+  if (!u_dev || !tau_dev) return fail(CNLOS_EINVAL, "NULL volume");
+  if ((const void*)u_dev == (const void*)tau_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
+  ConvSrc s{};
+  s.a = u_dev;
+  ConvEpi e{};
+  e.out = tau_dev;
+  e.w = p->wk;
+  e.mask = masked ? p->mask : nullptr;
+  HIPCHK(conv(p, s, false, EPI_PLAIN, e, nullptr));
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev, int32_t masked) {
+  CHECK_HANDLE(p);
+  if (!u_dev || !tau_dev) return fail(CNLOS_EINVAL, "NULL volume");
+  if ((const void*)u_dev == (const void*)tau_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
+  ConvSrc s{};
+  s.a = tau_dev;
+  s.w = p->wk;
+  s.mask = masked ? p->mask : nullptr;
+  ConvEpi e{};
+  e.out = u_dev;
+  HIPCHK(conv(p, s, true, EPI_PLAIN, e, nullptr));
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_run(cnlos_problem* p, int32_t iters, cnlos_report* out) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!p->has_meas) return fail(CNLOS_ESTATE, "no measurement set");
+  const cnlos_config& c = p->cfg;
+  const int planned = c.max_iters + (c.model == CNLOS_MODEL_DUAL ? c.init_iters : 0);
+  const int start = p->iter_host;
+  const int goal = iters > 0 ? start + iters : planned;
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  const int rejects0 = p->ctl_host->bt_rejects;
+  int batch = 2;
+  bool stopped = false;
+  cnlos_status result = CNLOS_OK;
+  while (p->iter_host < goal) {
+    const int nb = batch < goal - p->iter_host ? batch : goal - p->iter_host;
+    for (int k = p->iter_host; k < p->iter_host + nb; ++k) {
+      s = enqueue_iteration(p, k);
+      if (s != CNLOS_OK) return s;
+    }
+    s = ctl_pull(p);
+    if (s != CNLOS_OK) return s;
+    DevCtl& h = *p->ctl_host;
+    p->iter_host = h.iter;
+    if (h.halt) {
+      const int reason = h.reason;
+      h.halt = 0;
+      h.reason = HR_NONE;
+      if (reason == HR_BACKTRACK || reason == HR_NONFINITE) h.trials = 0;
+      s = ctl_push(p);
+      if (s != CNLOS_OK) return s;
+      if (reason == HR_REJECT) continue;
+      if (reason == HR_STOP) {
+        stopped = true;
+        break;
+      }
+      if (reason == HR_BACKTRACK) {
+        result = fail(CNLOS_EBACKTRACK, "backtracking found no acceptable step");
+        break;
+      }
+      result = fail(CNLOS_ENONFINITE, "non-finite residual or energy");
+      break;
+    }
+    if (batch < 64) batch *= 2;
+  }
+  if (out) {
+    const DevCtl& h = *p->ctl_host;
+    out->iters_done = p->iter_host - start;
+    out->total_iters = p->iter_host;
+    out->stopped_early = stopped ? 1 : 0;
+    out->bt_rejects = h.bt_rejects - rejects0;
+    out->L_final = h.L;
+    out->energy = h.last_energy;
+    out->primal_res = h.last_primal;
+    out->dual_res = h.last_dual;
+  }
+  return result;
+}
+
+cnlos_status cnlos_reset(cnlos_problem* p) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  return reset_state(p);
+}
+
+cnlos_status cnlos_get_volume(cnlos_problem* p, float* u_dev) {
+  return cnlos_get_field(p, CNLOS_FIELD_U, u_dev);
+}
+
+cnlos_status cnlos_get_signal(cnlos_problem* p, float* tau_dev) {
+  return cnlos_get_field(p, CNLOS_FIELD_TAU, tau_dev);
+}
+
+cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!dst_dev) return fail(CNLOS_EINVAL, "destination is NULL");
+  size_t n = 0;
+  float* src = field_ptr(p, field, &n);
+  if (!src) return fail(CNLOS_EINVAL, "field not available for this model");
+  HIPCHK(hipMemcpyAsync(dst_dev, src, n * sizeof(float), hipMemcpyDeviceToDevice, p->st));
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_set_field(cnlos_problem* p, int32_t field, const float* src_dev) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!src_dev) return fail(CNLOS_EINVAL, "source is NULL");
+  if (field == CNLOS_FIELD_TAU0) return fail(CNLOS_EINVAL, "the measurement is set by cnlos_set_measurement");
+  size_t n = 0;
+  float* dst = field_ptr(p, field, &n);
+  if (!dst) return fail(CNLOS_EINVAL, "field not available for this model");
+  HIPCHK(hipMemcpyAsync(dst, src_dev, n * sizeof(float), hipMemcpyDeviceToDevice, p->st));
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_get_info(cnlos_problem* p, cnlos_info* o) {
+  CHECK_HANDLE(p);
+  if (!o) return fail(CNLOS_EINVAL, "out is NULL");
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  const DevCtl& h = *p->ctl_host;
+  o->L0_obj = h.L0_obj;
+  o->L0_dual = h.L0_dual;
+  o->L = h.L;
+  o->t = h.t;
+  o->beta = h.beta;
+  o->meas_scale = h.meas_scale;
+  o->energy_prev = h.energy_prev;
+  o->iter = h.iter;
+  o->stage = h.stage;
+  o->bt_rejects = h.bt_rejects;
+  o->has_measurement = p->has_meas ? 1 : 0;
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_set_info(cnlos_problem* p, const cnlos_info* in) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!in) return fail(CNLOS_EINVAL, "info is NULL");
+  if (in->iter < 0 || (in->stage != 1 && in->stage != 2) || !(in->L > 0) || !(in->t >= 1.0))
+    return fail(CNLOS_EINVAL, "inconsistent info");
+  if (in->stage == 2 && p->cfg.model != CNLOS_MODEL_DUAL) return fail(CNLOS_EINVAL, "stage 2 needs the dual model");
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  DevCtl& h = *p->ctl_host;
+  h.L = in->L;
+  h.t = in->t;
+  h.beta = in->beta;
+  h.energy_prev = in->energy_prev;
+  h.iter = in->iter;
+  h.stage = in->stage;
+  h.bt_rejects = in->bt_rejects;
+  h.trials = 0;
+  h.halt = 0;
+  h.reason = HR_NONE;
+  p->iter_host = in->iter;
+  return ctl_push(p);
+}
+
+cnlos_status cnlos_get_log(cnlos_problem* p, double* host, int32_t cap, int32_t* n) {
+  CHECK_HANDLE(p);
+  CHECK_SOLVER(p);
+  if (!n || (cap > 0 && !host)) return fail(CNLOS_EINVAL, "NULL output");
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
+  const int total = p->ctl_host->log_count;
+  const int avail = total < kLogRows ? total : kLogRows;
+  const int rows = cap < avail ? cap : avail;
+  *n = rows;
+  if (rows <= 0) return CNLOS_OK;
+  std::vector<double> all((size_t)kLogRows * kLogCols);
+  HIPCHK(hipMemcpyAsync(all.data(), p->logbuf, all.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  const int first = total - rows;
+  for (int r = 0; r < rows; ++r) {
+    const int src = (first + r) % kLogRows;
+    memcpy(host + (size_t)r * kLogCols, all.data() + (size_t)src * kLogCols, kLogCols * sizeof(double));
+  }
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_destroy(cnlos_problem* p) {
+  if (!p) return CNLOS_OK;
+  if (p->ctl_host) {
+    if (!p->poisoned) hipStreamSynchronize(p->st);
+    hipHostFree(p->ctl_host);
+  }
+  delete p;
+  return CNLOS_OK;
+}
+
+}  // extern "C"

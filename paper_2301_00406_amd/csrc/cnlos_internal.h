@@ -1,0 +1,164 @@
+// Internal interfaces between the host driver and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cnlos {
+
+// Reduction slots of the FP64 partials buffer.
+enum Slot : int {
+  SL_CHECK = 0,     // ||D A (u+ - ubar)||^2 (object) or ||A (u+ - ubar)||^2 (dual)
+  SL_DATA = 1,      // ||D A u+ - tau0||^2 (object energy data term)
+  SL_STEP = 2,      // ||u+ - ubar||^2
+  SL_TV_U = 3,      // sum phi_u |grad u+|
+  SL_PRIMAL = 4,    // ||v - grad u+||^2
+  SL_DUAL = 5,      // ||grad (u+ - u)||^2
+  SL_FIT = 6,       // ||A u+ - tau+||^2 (dual energy)
+  SL_FID = 7,       // ||D (tau+ - tau0)||^2 (dual energy)
+  SL_TV_TAU = 8,    // sum phi_tau |grad tau+|
+  SL_NORM = 9,      // ||x||^2 (power iteration)
+  SL_MAX = 10,      // measurement maximum (stored as double)
+  SL_BAD = 11,      // count of non-finite measurement values
+  SL_COUNT = 12
+};
+
+constexpr int kMaxBlocks = 4096;     // partial-sum capacity per slot
+constexpr int kLogRows = 4096;       // per-iteration log ring
+constexpr int kLogCols = 6;
+
+enum HaltReason : int { HR_NONE = 0, HR_REJECT = 1, HR_STOP = 2, HR_BACKTRACK = 3, HR_NONFINITE = 4 };
+
+// Scalars shared by the host driver and the kernels, resident in the workspace.
+// Every kernel of the ADMM iteration returns at once while `halt` is set, so a
+// batch of enqueued iterations stops cleanly at a rejected trial or a stop.
+struct DevCtl {
+  double L;            // current step constant
+  double t;            // FISTA t_k
+  double beta;         // extrapolation weight that produced ubar^k
+  double energy_prev;  // last energy (NaN before the first iteration)
+  double L0_obj, L0_dual;
+  double meas_scale;
+  double pow_est;
+  double last_energy, last_primal, last_dual;
+  double reserved_d;
+  int32_t halt;
+  int32_t reason;
+  int32_t iter;        // accepted iterations
+  int32_t trials;      // rejections in the current iteration
+  int32_t bt_rejects;  // rejections since create/reset
+  int32_t stage;       // 1 = Algorithm 1, 2 = Algorithm 2
+  int32_t log_count;   // rows written to the log ring
+  int32_t bt_max_trials;
+  double bt_factor;
+  double eps_stop;
+  double mu_dual;      // mu (object) or mu1 (dual) for the dual residual
+  double lambda;
+};
+
+// Sparse resampling table S (depth bin k -> squared-distance bin q) in both
+// orientations; ranges are contiguous so each row/column is (start, count, off).
+struct ResampleTables {
+  const int4* rows;    // [m]: (k_start, count, value_offset, 0)
+  const float* rvals;
+  const int4* cols;    // [m]: (q_start, count, value_offset, 0)
+  const float* cvals;
+};
+
+// Source of the t-axis forward pass of a convolution:
+//   x[k] = mask[col] * w[k] * inv_scale * (ca * a[k] + cb * b[k] - c[k]),
+// with (ca, cb) = (1, 0) or, in the linearity-cache mode, (1 + beta, -beta)
+// with beta read from the controller.  Null pointers drop their factor.
+struct ConvSrc {
+  const float* a;
+  const float* b;
+  const float* c;
+  const float* w;
+  const uint8_t* mask;
+  const double* scale_div;   // divide by *scale_div (power iteration)
+  int lincache;
+};
+
+enum Epi : int { EPI_PLAIN = 0, EPI_FWD_OBJ = 1, EPI_FWD_DUAL = 2, EPI_NORM = 3 };
+
+// Epilogue of the t-axis inverse pass of a convolution.
+struct ConvEpi {
+  float* out;              // [n][n][m]
+  const float* w;          // per-bin output weight (nullable)
+  const uint8_t* mask;     // output mask (EPI_PLAIN) / fidelity mask (EPI_FWD_OBJ)
+  const float* au;         // A u^k       (check)
+  const float* au_prev;    // A u^{k-1}   (check)
+  const float* tau0;       // data (EPI_FWD_OBJ)
+  double* partials;
+};
+
+// Epilogue of the t-axis inverse pass of a diagonal solve.
+struct SolveEpi {
+  float* out;
+  const float* ref;        // ||out - ref||^2 into SL_STEP when not null
+  double* partials;
+};
+
+struct Tables {
+  const float2* tw_t;     // exp(-2 pi i j / (2m)), j < m
+  const float2* tw_xy;    // exp(-2 pi i j / (2n)), j < n
+  ResampleTables S;
+  const float* sig_xy;    // 4 sin^2(pi k / n), k < n
+  const float* sig_t;     // 4 sin^2(pi k / m), k <= m/2
+  const float2* hq;       // H^ quarter spectrum [m+1][n+1][n+1]
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers return hipGetLastError() of their launch.
+hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
+                       bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
+                       hipStream_t st);
+hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
+                        const double* c_dev, double c_val, double mu, const SolveEpi& ep,
+                        const DevCtl* ctl, hipStream_t st);
+hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
+                           const double* cosn, double invZ, hipStream_t st);
+int conv_blocks(int logn, int logm);          // blocks of the t-axis passes (partials count)
+
+// ADMM stencils and control (k_admm.hip)
+struct PhiArgs {
+  double a, b;
+  int kind;
+  float eta;
+};
+hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
+                        float* v, double mu, const DevCtl* ctl, hipStream_t st);
+hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
+                        const float* tau0, const uint8_t* mask, float* f, double lambda,
+                        double mu3, const DevCtl* ctl, hipStream_t st);
+hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
+                        const float* lam, double mu, const DevCtl* ctl, hipStream_t st);
+hipError_t launch_rhs_tau(int logn, int logm, const float* au, const float* f, const float* lam3,
+                          const float* w, const float* lam2, float* rhs, double mu2, double mu3,
+                          const DevCtl* ctl, hipStream_t st);
+hipError_t launch_post(int logn, int logm, bool tau_mode, const float* xnew, const float* xold,
+                       const float* v, float* lam, float* xbar, float* phi, double mu,
+                       const PhiArgs& pa, const float* f, float* lam3, double mu3,
+                       const float* au, const float* tau0, const uint8_t* mask, double* partials,
+                       const DevCtl* ctl, hipStream_t st);
+int stencil_blocks(int logn, int logm);
+hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
+                        hipStream_t st);
+hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
+                           int nb_sten, int dual, double lambda, double mu_res, hipStream_t st);
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, const float* u, float* ubar,
+                             float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
+                             float* const* zero_fields, const size_t* zero_counts, int nzero,
+                             hipStream_t st);
+hipError_t launch_fill(float* x, size_t n, float val, hipStream_t st);
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
+hipError_t launch_phi_of_u(int logn, int logm, const float* u, float* phi, const PhiArgs& pa,
+                           hipStream_t st);
+hipError_t launch_meas_prep(int logn, int logm, const float* raw, const uint8_t* mask,
+                            const float* r3, float* out, double* partials, hipStream_t st);
+hipError_t launch_meas_finish(int logn, int logm, float* out, DevCtl* ctl, double* partials,
+                              hipStream_t st);
+hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, hipStream_t st);
+hipError_t launch_ctl_clear_halt(DevCtl* ctl, hipStream_t st);
+
+}  // namespace cnlos

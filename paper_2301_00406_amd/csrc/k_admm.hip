@@ -1,0 +1,556 @@
+// ADMM stencil and control kernels (Sections 3.1-3.2 and 4.1).
+//
+// Volumes are [n][n][m] float32 with t fastest; every difference operator is
+// periodic with unit spacing (the periodicity is what makes the FFT solve of
+// eq. (11) exact).  nabla is the forward difference, nabla^* its adjoint
+// (minus the backward-difference divergence).  Reductions accumulate in FP64
+// and are combined in a fixed order, so results are bitwise reproducible.
+#include <math.h>
+
+#include "cnlos_internal.h"
+#include "fft_device.h"
+
+namespace cnlos {
+
+constexpr int kStencilThreads = 256;
+
+int stencil_blocks(int logn, int logm) {
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  size_t nb = (V + kStencilThreads - 1) / kStencilThreads;
+  if (nb > (size_t)kMaxBlocks) nb = kMaxBlocks;
+  return (int)nb;
+}
+
+// periodic neighbour offsets of voxel g
+struct Nbr {
+  size_t xp, xm, yp, ym, tp, tm;
+};
+
+__device__ __forceinline__ Nbr neighbours(size_t g, int logn, int logm) {
+  const size_t M = (size_t)1 << logm, N = (size_t)1 << logn;
+  const size_t sx = N * M, sy = M;
+  const size_t k = g & (M - 1);
+  const size_t j = (g >> logm) & (N - 1);
+  const size_t i = g >> (logm + logn);
+  Nbr r;
+  r.xp = (i == N - 1) ? g - (N - 1) * sx : g + sx;
+  r.xm = (i == 0) ? g + (N - 1) * sx : g - sx;
+  r.yp = (j == N - 1) ? g - (N - 1) * sy : g + sy;
+  r.ym = (j == 0) ? g + (N - 1) * sy : g - sy;
+  r.tp = (k == M - 1) ? g - (M - 1) : g + 1;
+  r.tm = (k == 0) ? g + (M - 1) : g - 1;
+  return r;
+}
+
+__device__ __forceinline__ float phi_eval(float kappa, const PhiArgs& pa) {
+  const float a = (float)pa.a, b = (float)pa.b;
+  if (pa.kind == 1) return a + b * fabsf(kappa);
+  if (pa.kind == 2) return sqrtf(a + b * kappa * kappa);
+  return a + b * kappa * kappa;
+}
+
+// forward-difference gradient of x at voxel g (neighbours given)
+__device__ __forceinline__ void grad_at(const float* __restrict__ x, size_t g, size_t xp, size_t yp,
+                                        size_t tp, float& gx, float& gy, float& gt) {
+  const float x0 = x[g];
+  gx = x[xp] - x0;
+  gy = x[yp] - x0;
+  gt = x[tp] - x0;
+}
+
+// kappa = div^-( grad x / sqrt(|grad x|^2 + eta^2) ) at voxel g, plus grad x(g)
+__device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_t g, const Nbr& nb,
+                                              int logn, int logm, float eta2, float& gx0,
+                                              float& gy0, float& gt0) {
+  grad_at(x, g, nb.xp, nb.yp, nb.tp, gx0, gy0, gt0);
+  const float i0 = rsqrtf(gx0 * gx0 + gy0 * gy0 + gt0 * gt0 + eta2);
+  float ax, ay, at;
+  const Nbr bx = neighbours(nb.xm, logn, logm);
+  grad_at(x, nb.xm, bx.xp, bx.yp, bx.tp, ax, ay, at);
+  const float nxm = ax * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const Nbr by = neighbours(nb.ym, logn, logm);
+  grad_at(x, nb.ym, by.xp, by.yp, by.tp, ax, ay, at);
+  const float nym = ay * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const Nbr bt = neighbours(nb.tm, logn, logm);
+  grad_at(x, nb.tm, bt.xp, bt.yp, bt.tp, ax, ay, at);
+  const float ntm = at * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
+}
+
+// v = shrink(grad ubar - Lambda/mu, phi/mu), isotropic over the three components (eq. (7))
+__global__ void __launch_bounds__(kStencilThreads)
+k_vstep(const float* __restrict__ ub, const float* __restrict__ lam, const float* __restrict__ phi,
+        float* __restrict__ v, float inv_mu, int logn, int logm, const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    float gx, gy, gt;
+    grad_at(ub, g, nb.xp, nb.yp, nb.tp, gx, gy, gt);
+    const float ax = gx - lam[g] * inv_mu;
+    const float ay = gy - lam[V + g] * inv_mu;
+    const float at = gt - lam[2 * V + g] * inv_mu;
+    const float nrm = sqrtf(ax * ax + ay * ay + at * at);
+    const float thr = phi[g] * inv_mu;
+    const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
+    v[g] = ax * s;
+    v[V + g] = ay * s;
+    v[2 * V + g] = at * s;
+  }
+}
+
+// f: pointwise minimizer of lambda/2 |f - tau0|^2 on kept points + <Lambda3, f - taubar>
+//    + mu3/2 |f - taubar|^2
+__global__ void __launch_bounds__(kStencilThreads)
+k_fstep(const float* __restrict__ taubar, const float* __restrict__ lam3,
+        const float* __restrict__ tau0, const uint8_t* __restrict__ mask, float* __restrict__ f,
+        float lambda, float mu3, int logn, int logm, const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const float inv_kept = 1.f / (lambda + mu3), inv_mu3 = 1.f / mu3;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const float tb = taubar[g], l3 = lam3[g];
+    f[g] = mask[g >> logm] ? (lambda * tau0[g] + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
+  }
+}
+
+// rhs = L ubar - grad f + nabla^*(mu v + Lambda)   (eq. (10)/(11) right-hand side), in place
+__global__ void __launch_bounds__(kStencilThreads)
+k_rhs_u(const float* __restrict__ ub, float* __restrict__ gf_rhs, const float* __restrict__ v,
+        const float* __restrict__ lam, float mu, int logn, int logm, const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const float L = (float)ctl->L;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    const float px0 = mu * v[g] + lam[g], pxm = mu * v[nb.xm] + lam[nb.xm];
+    const float py0 = mu * v[V + g] + lam[V + g], pym = mu * v[V + nb.ym] + lam[V + nb.ym];
+    const float pt0 = mu * v[2 * V + g] + lam[2 * V + g],
+                ptm = mu * v[2 * V + nb.tm] + lam[2 * V + nb.tm];
+    const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
+    gf_rhs[g] = L * ub[g] - gf_rhs[g] + adj;
+  }
+}
+
+// rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem of Algorithm 2)
+__global__ void __launch_bounds__(kStencilThreads)
+k_rhs_tau(const float* __restrict__ au, const float* __restrict__ f, const float* __restrict__ lam3,
+          const float* __restrict__ w, const float* __restrict__ lam2, float* __restrict__ rhs,
+          float mu2, float mu3, int logn, int logm, const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    const float px0 = mu2 * w[g] + lam2[g], pxm = mu2 * w[nb.xm] + lam2[nb.xm];
+    const float py0 = mu2 * w[V + g] + lam2[V + g], pym = mu2 * w[V + nb.ym] + lam2[V + nb.ym];
+    const float pt0 = mu2 * w[2 * V + g] + lam2[2 * V + g],
+                ptm = mu2 * w[2 * V + nb.tm] + lam2[2 * V + nb.tm];
+    const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
+    rhs[g] = au[g] + mu3 * f[g] + lam3[g] + adj;
+  }
+}
+
+// After the accepted step: multiplier ascent (eq. (12)), FISTA extrapolation,
+// curvature weight refresh, and the FP64 energy/residual partials.
+// u mode : Lambda += mu (v - grad x+), xbar, phi_u; partials TV_U, PRIMAL, DUAL.
+// tau mode: Lambda2 += mu2 (w - grad tau+), Lambda3 += mu3 (f - tau+), taubar,
+//           phi_tau; partials TV_TAU, FIT (|A u+ - tau+|^2), FID (|D(tau+ - tau0)|^2).
+template <bool TAU>
+__global__ void __launch_bounds__(kStencilThreads)
+k_post(const float* __restrict__ xn, const float* __restrict__ xo, const float* __restrict__ v,
+       float* __restrict__ lam, float* __restrict__ xbar, float* __restrict__ phi, float mu,
+       PhiArgs pa, const float* __restrict__ f, float* __restrict__ lam3, float mu3,
+       const float* __restrict__ au, const float* __restrict__ tau0,
+       const uint8_t* __restrict__ mask, double* __restrict__ partials, int logn, int logm,
+       const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const double t = ctl->t;
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const float beta = (float)((t - 1.0) / tn);
+  const float eta2 = pa.eta * pa.eta;
+  double s_tv = 0.0, s_a = 0.0, s_b = 0.0;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    float gx, gy, gt;
+    const float kappa = curvature_at(xn, g, nb, logn, logm, eta2, gx, gy, gt);
+    const float ph = phi_eval(kappa, pa);
+    phi[g] = ph;
+    const float vx = v[g], vy = v[V + g], vt = v[2 * V + g];
+    lam[g] += mu * (vx - gx);
+    lam[V + g] += mu * (vy - gy);
+    lam[2 * V + g] += mu * (vt - gt);
+    const float x0 = xn[g];
+    const float d0 = x0 - xo[g];
+    xbar[g] = x0 + beta * d0;
+    const float gn = sqrtf(gx * gx + gy * gy + gt * gt);
+    s_tv += (double)ph * (double)gn;
+    if (!TAU) {
+      const float rx = vx - gx, ry = vy - gy, rt = vt - gt;
+      s_a += (double)rx * rx + (double)ry * ry + (double)rt * rt;
+      const float dx = (xn[nb.xp] - xo[nb.xp]) - d0;
+      const float dy = (xn[nb.yp] - xo[nb.yp]) - d0;
+      const float dt = (xn[nb.tp] - xo[nb.tp]) - d0;
+      s_b += (double)dx * dx + (double)dy * dy + (double)dt * dt;
+    } else {
+      lam3[g] += mu3 * (f[g] - x0);
+      const float r = au[g] - x0;
+      s_a += (double)r * r;
+      if (mask[g >> logm]) {
+        const float e = x0 - tau0[g];
+        s_b += (double)e * e;
+      }
+    }
+  }
+  double vals[3] = {s_tv, s_a, s_b};
+  if (!TAU) {
+    const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
+    block_sum_store<3>(vals, partials, slots, kMaxBlocks);
+  } else {
+    const int slots[3] = {SL_TV_TAU, SL_FIT, SL_FID};
+    block_sum_store<3>(vals, partials, slots, kMaxBlocks);
+  }
+}
+
+// phi = phi(kappa(x)) (warm-start hand-over and resets)
+__global__ void __launch_bounds__(kStencilThreads)
+k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int logn, int logm) {
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const float eta2 = pa.eta * pa.eta;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    float gx, gy, gt;
+    phi[g] = phi_eval(curvature_at(x, g, nb, logn, logm, eta2, gx, gy, gt), pa);
+  }
+}
+
+// Backtracking decision (Beck-Teboulle).  For the quadratic data term f the
+// sufficient-decrease test f(u+) <= f(ubar) + <u+ - ubar, grad f(ubar)> +
+// L/2 |u+ - ubar|^2 is exactly |B (u+ - ubar)|^2 <= L |u+ - ubar|^2, B = A_D
+// (object) or A (dual); the left side comes from the difference of A u+ and
+// the cached A ubar, free of the cancellation of the literal form.
+__global__ void __launch_bounds__(256)
+k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on) {
+  if (ctl->halt) return;
+  const double s_chk = block_sum_partials(partials, SL_CHECK, nb_conv, kMaxBlocks);
+  const double s_step = block_sum_partials(partials, SL_STEP, nb_step, kMaxBlocks);
+  if (threadIdx.x == 0) {
+    if (!isfinite(s_chk) || !isfinite(s_step)) {
+      ctl->halt = 1;
+      ctl->reason = HR_NONFINITE;
+    } else if (bt_on && !(s_chk <= ctl->L * s_step)) {
+      ctl->trials += 1;
+      ctl->bt_rejects += 1;
+      ctl->halt = 1;
+      if (ctl->trials > ctl->bt_max_trials) {
+        ctl->reason = HR_BACKTRACK;
+      } else {
+        ctl->reason = HR_REJECT;
+        ctl->L *= ctl->bt_factor;
+      }
+    }
+  }
+}
+
+// Energy, residuals, log row, FISTA t update, stopping rule.
+__global__ void __launch_bounds__(256)
+k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
+           int nb_conv, int nb_sten, int dual, double lambda, double mu_res) {
+  if (ctl->halt) return;
+  const double tv_u = block_sum_partials(partials, SL_TV_U, nb_sten, kMaxBlocks);
+  const double prim = block_sum_partials(partials, SL_PRIMAL, nb_sten, kMaxBlocks);
+  const double dres = block_sum_partials(partials, SL_DUAL, nb_sten, kMaxBlocks);
+  double E;
+  if (!dual) {
+    const double data = block_sum_partials(partials, SL_DATA, nb_conv, kMaxBlocks);
+    E = 0.5 * data + tv_u;
+  } else {
+    const double fit = block_sum_partials(partials, SL_FIT, nb_sten, kMaxBlocks);
+    const double fid = block_sum_partials(partials, SL_FID, nb_sten, kMaxBlocks);
+    const double tv_t = block_sum_partials(partials, SL_TV_TAU, nb_sten, kMaxBlocks);
+    E = 0.5 * fit + 0.5 * lambda * fid + tv_u + tv_t;
+  }
+  if (threadIdx.x == 0) {
+    if (!isfinite(E)) {
+      ctl->halt = 1;
+      ctl->reason = HR_NONFINITE;
+      return;
+    }
+    const double Ep = ctl->energy_prev;
+    const double rel = (isfinite(Ep) && E != 0.0) ? fabs(Ep - E) / fabs(E) : INFINITY;
+    const double primal = sqrt(prim), dualr = mu_res * sqrt(dres);
+    double* row = logbuf + (size_t)(ctl->log_count % kLogRows) * kLogCols;
+    row[0] = E;
+    row[1] = primal;
+    row[2] = dualr;
+    row[3] = ctl->L;
+    row[4] = (double)ctl->trials;
+    row[5] = rel;
+    ctl->log_count += 1;
+    const double t = ctl->t;
+    const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+    ctl->beta = (t - 1.0) / tn;
+    ctl->t = tn;
+    ctl->iter += 1;
+    ctl->trials = 0;
+    ctl->energy_prev = E;
+    ctl->last_energy = E;
+    ctl->last_primal = primal;
+    ctl->last_dual = dualr;
+    if (ctl->eps_stop > 0.0 && rel <= ctl->eps_stop) {
+      ctl->halt = 1;
+      ctl->reason = HR_STOP;
+    }
+  }
+}
+
+// Hand-over from the Algorithm-1 warm start to Algorithm 2 (idempotent: only
+// acts while stage == 1).  ubar = u, phi_u = phi(kappa(u)), phi_tau = phi(0),
+// tau, taubar, w, f and the multipliers zeroed.
+__global__ void __launch_bounds__(kStencilThreads)
+k_transition_fields(const DevCtl* ctl, const float* __restrict__ u, float* __restrict__ ubar,
+                    float* __restrict__ phi_u, PhiArgs pa, float* __restrict__ phi_tau,
+                    float phi_tau0, int logn, int logm) {
+  if (ctl->halt || ctl->stage != 1) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const float eta2 = pa.eta * pa.eta;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    float gx, gy, gt;
+    phi_u[g] = phi_eval(curvature_at(u, g, nb, logn, logm, eta2, gx, gy, gt), pa);
+    ubar[g] = u[g];
+    phi_tau[g] = phi_tau0;
+  }
+}
+
+__global__ void __launch_bounds__(kStencilThreads)
+k_zero_if_stage1(const DevCtl* ctl, float* __restrict__ x, size_t n) {
+  if (ctl->halt || ctl->stage != 1) return;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x)
+    x[g] = 0.f;
+}
+
+__global__ void k_transition_scalars(DevCtl* ctl) {
+  if (ctl->halt || ctl->stage != 1) return;
+  ctl->stage = 2;
+  ctl->t = 1.0;
+  ctl->beta = 0.0;
+  ctl->L = ctl->L0_dual;
+  ctl->trials = 0;
+  ctl->energy_prev = NAN;
+}
+
+__global__ void __launch_bounds__(kStencilThreads) k_fill(float* __restrict__ x, size_t n, float val) {
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x)
+    x[g] = val;
+}
+
+__global__ void __launch_bounds__(kStencilThreads)
+k_copy(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x)
+    dst[g] = src[g];
+}
+
+// measurement: out = mask * r3[k] * raw; partial max and non-finite count
+__global__ void __launch_bounds__(kStencilThreads)
+k_meas_prep(const float* __restrict__ raw, const uint8_t* __restrict__ mask,
+            const float* __restrict__ r3, float* __restrict__ out, double* __restrict__ partials,
+            int logn, int logm) {
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const size_t M = (size_t)1 << logm;
+  float mx = 0.f;
+  double bad = 0.0;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const float x = raw[g];
+    if (!isfinite(x)) bad += 1.0;
+    float y = mask[g >> logm] ? x : 0.f;
+    if (r3) y *= r3[g & (M - 1)];
+    out[g] = y;
+    mx = fmaxf(mx, y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+  __shared__ float redm[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) redm[wid] = mx;
+  double vals[1] = {bad};
+  const int slots[1] = {SL_BAD};
+  block_sum_store<1>(vals, partials, slots, kMaxBlocks);   // contains a barrier
+  if (threadIdx.x == 0) {
+    float m = 0.f;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) m = fmaxf(m, redm[k]);
+    partials[(size_t)SL_MAX * kMaxBlocks + blockIdx.x] = (double)m;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_meas_reduce(DevCtl* ctl, const double* __restrict__ partials, int nb) {
+  const double bad = block_sum_partials(partials, SL_BAD, nb, kMaxBlocks);
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < nb; ++i) m = fmax(m, partials[(size_t)SL_MAX * kMaxBlocks + i]);
+    ctl->meas_scale = m;
+    ctl->reason = bad > 0.0 ? HR_NONFINITE : HR_NONE;
+  }
+}
+
+__global__ void __launch_bounds__(kStencilThreads)
+k_meas_scale(float* __restrict__ out, const DevCtl* ctl, int logn, int logm) {
+  const double s = ctl->meas_scale;
+  if (!(s > 0.0) || ctl->reason != HR_NONE) return;
+  const float inv = (float)(1.0 / s);
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x)
+    out[g] *= inv;
+}
+
+__global__ void __launch_bounds__(256) k_pow_finalize(DevCtl* ctl, const double* __restrict__ partials, int nb) {
+  const double s = block_sum_partials(partials, SL_NORM, nb, kMaxBlocks);
+  if (threadIdx.x == 0) ctl->pow_est = sqrt(s);
+}
+
+__global__ void k_clear_halt(DevCtl* ctl) {
+  ctl->halt = 0;
+  ctl->reason = HR_NONE;
+}
+
+// ---------------------------------------------------------------- launchers
+static dim3 sgrid(int logn, int logm) { return dim3(stencil_blocks(logn, logm)); }
+
+hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
+                        float* v, double mu, const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_vstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, lam, phi, v,
+                     (float)(1.0 / mu), logn, logm, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
+                        const float* tau0, const uint8_t* mask, float* f, double lambda,
+                        double mu3, const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_fstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, taubar, lam3, tau0,
+                     mask, f, (float)lambda, (float)mu3, logn, logm, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
+                        const float* lam, double mu, const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_u, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, gf_rhs, v, lam,
+                     (float)mu, logn, logm, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_tau(int logn, int logm, const float* au, const float* f, const float* lam3,
+                          const float* w, const float* lam2, float* rhs, double mu2, double mu3,
+                          const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_tau, sgrid(logn, logm), dim3(kStencilThreads), 0, st, au, f, lam3, w,
+                     lam2, rhs, (float)mu2, (float)mu3, logn, logm, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_post(int logn, int logm, bool tau_mode, const float* xnew, const float* xold,
+                       const float* v, float* lam, float* xbar, float* phi, double mu,
+                       const PhiArgs& pa, const float* f, float* lam3, double mu3,
+                       const float* au, const float* tau0, const uint8_t* mask, double* partials,
+                       const DevCtl* ctl, hipStream_t st) {
+  if (tau_mode)
+    hipLaunchKernelGGL(k_post<true>, sgrid(logn, logm), dim3(kStencilThreads), 0, st, xnew, xold, v,
+                       lam, xbar, phi, (float)mu, pa, f, lam3, (float)mu3, au, tau0, mask, partials,
+                       logn, logm, ctl);
+  else
+    hipLaunchKernelGGL(k_post<false>, sgrid(logn, logm), dim3(kStencilThreads), 0, st, xnew, xold,
+                       v, lam, xbar, phi, (float)mu, pa, f, lam3, (float)mu3, au, tau0, mask,
+                       partials, logn, logm, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, st, ctl, partials, nb_conv, nb_step, bt_on);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
+                           int nb_sten, int dual, double lambda, double mu_res, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, ctl, log, partials, nb_conv, nb_sten,
+                     dual, lambda, mu_res);
+  return hipGetLastError();
+}
+
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, const float* u, float* ubar,
+                             float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
+                             float* const* zero_fields, const size_t* zero_counts, int nzero,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_transition_fields, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ctl, u,
+                     ubar, phi_u, pa_u, phi_tau, (float)phi_tau0, logn, logm);
+  for (int i = 0; i < nzero; ++i) {
+    size_t nb = (zero_counts[i] + kStencilThreads - 1) / kStencilThreads;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_zero_if_stage1, dim3((unsigned)nb), dim3(kStencilThreads), 0, st, ctl,
+                       zero_fields[i], zero_counts[i]);
+  }
+  hipLaunchKernelGGL(k_transition_scalars, dim3(1), dim3(1), 0, st, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* x, size_t n, float val, hipStream_t st) {
+  size_t nb = (n + kStencilThreads - 1) / kStencilThreads;
+  if (nb > 4096) nb = 4096;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(kStencilThreads), 0, st, x, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t st) {
+  size_t nb = (n + kStencilThreads - 1) / kStencilThreads;
+  if (nb > 4096) nb = 4096;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kStencilThreads), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_of_u(int logn, int logm, const float* u, float* phi, const PhiArgs& pa,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_phi_of, sgrid(logn, logm), dim3(kStencilThreads), 0, st, u, phi, pa, logn,
+                     logm);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas_prep(int logn, int logm, const float* raw, const uint8_t* mask,
+                            const float* r3, float* out, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_meas_prep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, raw, mask, r3,
+                     out, partials, logn, logm);
+  return hipGetLastError();
+}
+
+hipError_t launch_meas_finish(int logn, int logm, float* out, DevCtl* ctl, double* partials,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_meas_reduce, dim3(1), dim3(256), 0, st, ctl, partials,
+                     stencil_blocks(logn, logm));
+  hipLaunchKernelGGL(k_meas_scale, sgrid(logn, logm), dim3(kStencilThreads), 0, st, out, ctl, logn,
+                     logm);
+  return hipGetLastError();
+}
+
+hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_pow_finalize, dim3(1), dim3(256), 0, st, ctl, partials, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctl_clear_halt(DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_clear_halt, dim3(1), dim3(1), 0, st, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace cnlos

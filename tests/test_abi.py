@@ -1,0 +1,135 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, struct layouts agree with the header, and validation of
+configurations, masks and workspace sizes happens before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2301_00406_amd import cnlos as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cnlos.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(cnlos_[A-Za-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = C.load()
+    names = header_functions()
+    assert len(names) == 19
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r"\bT (cnlos_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_header():
+    src = f"""
+#include <stddef.h>
+#include <stdio.h>
+#include "cnlos.h"
+int main(void) {{
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
+         offsetof(cnlos_config, power_iters), sizeof(cnlos_report), sizeof(cnlos_info),
+         offsetof(cnlos_info, iter), offsetof(cnlos_config, eps_stop));
+  return 0;
+}}
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        cfile = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(cfile, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), cfile, "-o", exe], check=True)
+        vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    assert vals == [ctypes.sizeof(C.Config), C.Config.lambda_.offset, C.Config.power_iters.offset,
+                    ctypes.sizeof(C.Report), ctypes.sizeof(C.Info), C.Info.iter.offset,
+                    C.Config.eps_stop.offset]
+
+
+def test_defaults_follow_paper_parameters():
+    cfg = C.default_config()
+    assert (cfg.mu1, cfg.mu2, cfg.mu3) == (1.0, 800.0, 2.0)
+    assert cfg.a_u == 5e-5 and cfg.b_u == 5e-5 and cfg.mu == 0.1
+    assert cfg.bt_factor == 2.0 and cfg.power_iters == 15
+    assert C.load().cnlos_version().decode() == "1.0"
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("nx", 12, C.EUNSUPPORTED), ("nx", 256, C.EUNSUPPORTED), ("nx", 0, C.EINVAL),
+    ("nt", 100, C.EUNSUPPORTED), ("nt", 4096, C.EUNSUPPORTED), ("nt", -1, C.EINVAL),
+    ("bin_ps", 0.0, C.EINVAL), ("wall_w_m", -1.0, C.EINVAL), ("wall_h_m", float("nan"), C.EINVAL),
+    ("model", 3, C.EINVAL), ("phi", 7, C.EINVAL), ("falloff", 2, C.EINVAL),
+    ("mu", 0.0, C.EINVAL), ("a_u", -1e-3, C.EINVAL), ("eta_curv", 0.0, C.EINVAL),
+    ("bt_factor", 1.0, C.EINVAL), ("bt_max_trials", -1, C.EINVAL), ("max_iters", -3, C.EINVAL),
+    ("eps_stop", -1.0, C.EINVAL), ("power_iters", 0, C.EINVAL),
+])
+def test_validation_rejects_bad_configs(field, value, status):
+    cfg = C.default_config()
+    setattr(cfg, field, value)
+    assert C.validate(cfg) == status
+    assert C.last_error()
+    n = ctypes.c_uint64()
+    assert C.load().cnlos_workspace_bytes(ctypes.byref(cfg), ctypes.byref(n)) == status
+
+
+def test_validation_dual_model_parameters():
+    cfg = C.default_config(model=C.MODEL_DUAL)
+    assert C.validate(cfg) == C.OK
+    for f in ("mu1", "mu2", "mu3", "lambda_"):
+        bad = C.default_config(model=C.MODEL_DUAL)
+        setattr(bad, f, 0.0)
+        assert C.validate(bad) == C.EINVAL, f
+    assert C.validate(C.default_config(nx=16, ny=32)) == C.EUNSUPPORTED
+
+
+def test_mask_validation():
+    cfg = C.default_config()
+    assert C.validate(cfg, np.zeros((16, 16), np.uint8)) == C.EINVAL
+    m = np.zeros((16, 16), np.uint8)
+    m[3, 4] = 1
+    assert C.validate(cfg, m) == C.OK
+
+
+def test_workspace_bytes_grow_with_model_and_size():
+    sizes = {}
+    for model in (C.MODEL_OPERATOR, C.MODEL_OBJECT, C.MODEL_DUAL):
+        sizes[model] = C.workspace_bytes(C.default_config(model=model))
+    assert sizes[C.MODEL_OPERATOR] < sizes[C.MODEL_OBJECT] < sizes[C.MODEL_DUAL]
+    big = C.workspace_bytes(C.default_config(nx=64, ny=64, nt=512, model=C.MODEL_DUAL))
+    V = 64 * 64 * 512
+    # the dual model keeps about 31 volume-sized fields plus spectra
+    assert 30 * 4 * V < big < 45 * 4 * V
+    assert big % 256 == 0
+
+
+def test_create_rejects_before_touching_the_device():
+    lib = C.load()
+    cfg = C.default_config()
+    mask = np.ones((16, 16), np.uint8)
+    h = ctypes.c_void_p()
+    mp = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    need = C.workspace_bytes(cfg)
+    # undersized, misaligned and null workspaces fail validation without a GPU
+    assert lib.cnlos_create(ctypes.byref(cfg), mp, ctypes.c_void_p(1 << 20), need - 256, None,
+                            ctypes.byref(h)) == C.EINVAL
+    assert "too small" in C.last_error()
+    assert lib.cnlos_create(ctypes.byref(cfg), mp, ctypes.c_void_p((1 << 20) + 8), need, None,
+                            ctypes.byref(h)) == C.EINVAL
+    assert lib.cnlos_create(ctypes.byref(cfg), mp, None, need, None, ctypes.byref(h)) == C.EINVAL
+    zero = np.zeros((16, 16), np.uint8)
+    assert lib.cnlos_create(ctypes.byref(cfg), zero.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                            ctypes.c_void_p(1 << 20), need, None, ctypes.byref(h)) == C.EINVAL
+    assert h.value is None
+    # null handles are rejected, destroy(NULL) is fine
+    assert lib.cnlos_run(None, 1, None) == C.EINVAL
+    assert lib.cnlos_destroy(None) == C.OK

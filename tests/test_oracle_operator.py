@@ -172,3 +172,23 @@ def test_power_iteration_bounds_operator_norm():
     est200 = O.power_norm2(lambda x: O.apply_A(x, op, True), lambda y: O.apply_AT(y, op, True),
                            (nx, ny, m), 400)
     assert abs(est200 - smax2) <= 1e-3 * smax2
+
+
+def test_sampled_column_helpers_match_full_operator():
+    """The direct-summation column helpers used at sizes the FFT oracle cannot
+    hold agree with the full operator on a small grid."""
+    from tests.gpu_helpers import sampled_columns_A, sampled_columns_AT
+    n, m, wall, bin_ps = 8, 32, 0.7, 32.0
+    rng = np.random.default_rng(21)
+    u = rng.random((n, n, m))
+    y = rng.standard_normal((n, n, m))
+    cols = [(0, 0), (7, 7), (3, 5), (6, 1)]
+    for falloff in (O.FALLOFF_COMPENSATED, O.FALLOFF_LITERAL):
+        op = O.make_operator(n, n, m, wall, wall, bin_ps, falloff)
+        full = O.apply_A(u, op)
+        fullT = O.apply_AT(y, op)
+        a = sampled_columns_A(u, n, m, wall, wall, bin_ps, falloff, cols)
+        b = sampled_columns_AT(y, n, m, wall, wall, bin_ps, falloff, cols)
+        for c in cols:
+            np.testing.assert_allclose(a[c], full[c], rtol=1e-11, atol=1e-12 * np.abs(full).max())
+            np.testing.assert_allclose(b[c], fullT[c], rtol=1e-11, atol=1e-12 * np.abs(fullT).max())
