@@ -235,6 +235,36 @@ cnlos_status cnlos_set_info(cnlos_problem* p, const cnlos_info* in);
  * Synchronizes the stream. */
 cnlos_status cnlos_get_log(cnlos_problem* p, double* host, int32_t cap, int32_t* n);
 
+/* Kernel kinds of the per-kernel timer (bit k of a mask selects kind k). */
+typedef enum {
+  CNLOS_KK_T_FWD_CONV = 0,   /* convolution: resample + R2C along t           */
+  CNLOS_KK_PLANE_CONV = 1,   /* convolution: padded (x, y) transform with H^  */
+  CNLOS_KK_T_INV_CONV = 2,   /* convolution: C2R along t + R_t^{-1} + epilogue */
+  CNLOS_KK_T_FWD_SOLVE = 3,  /* diagonal solve: R2C along t                   */
+  CNLOS_KK_PLANE_SOLVE = 4,  /* diagonal solve: (x, y) transform and divide    */
+  CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t                   */
+  CNLOS_KK_VSTEP = 6,        /* shrinkage steps (v, w)                         */
+  CNLOS_KK_FSTEP = 7,        /* dual model f step                              */
+  CNLOS_KK_RHS_U = 8,        /* right-hand side of the u solve                 */
+  CNLOS_KK_RHS_TAU = 9,      /* right-hand side of the tau solve               */
+  CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature (u)       */
+  CNLOS_KK_POST_TAU = 11,    /* multiplier, extrapolation, curvature (tau)     */
+  CNLOS_KK_CONTROL = 12,     /* backtracking decision and iteration finalize   */
+  CNLOS_KK_OTHER = 13,       /* warm-start hand-over                           */
+  CNLOS_KK_COUNT = 14
+} cnlos_kernel_kind;
+
+/* Per-kernel timing for tracing and roofline measurement (not part of the
+ * paper's method).  Every later launch of a selected kind is bracketed by two
+ * HIP events recorded on the problem's stream; 0 disables.  Costs two event
+ * records per timed launch. */
+cnlos_status cnlos_profile_enable(cnlos_problem* p, uint32_t kind_mask);
+
+/* Accumulated milliseconds and launch counts per kind (arrays of
+ * CNLOS_KK_COUNT, either may be NULL); reset != 0 zeroes the accumulators.
+ * Synchronizes the stream. */
+cnlos_status cnlos_profile_read(cnlos_problem* p, double* ms, int64_t* launches, int32_t reset);
+
 /* Release the handle (the workspace stays the caller's).  NULL is accepted. */
 cnlos_status cnlos_destroy(cnlos_problem* p);
 

@@ -20,6 +20,9 @@ FALLOFF_COMPENSATED, FALLOFF_LITERAL = 0, 1
 (FIELD_U, FIELD_UBAR, FIELD_V, FIELD_LAM, FIELD_PHI, FIELD_AU, FIELD_AU_PREV, FIELD_TAU0,
  FIELD_TAU, FIELD_TAUBAR, FIELD_W, FIELD_LAM2, FIELD_F, FIELD_LAM3, FIELD_PHI_TAU) = range(15)
 VECTOR_FIELDS = {FIELD_V, FIELD_LAM, FIELD_W, FIELD_LAM2}
+KERNEL_KINDS = ["t_fwd_conv", "plane_conv", "t_inv_conv", "t_fwd_solve", "plane_solve",
+                "t_inv_solve", "vstep", "fstep", "rhs_u", "rhs_tau", "post_u", "post_tau",
+                "control", "other"]
 
 _STATUS_NAMES = {OK: "CNLOS_OK", EINVAL: "CNLOS_EINVAL", EUNSUPPORTED: "CNLOS_EUNSUPPORTED",
                  ENOMEM: "CNLOS_ENOMEM", EHIP: "CNLOS_EHIP", ESTATE: "CNLOS_ESTATE",
@@ -94,6 +97,8 @@ def load() -> ctypes.CDLL:
         "cnlos_get_info": ([P, POINTER(Info)], c_int32),
         "cnlos_set_info": ([P, POINTER(Info)], c_int32),
         "cnlos_get_log": ([P, POINTER(c_double), c_int32, POINTER(c_int32)], c_int32),
+        "cnlos_profile_enable": ([P, ctypes.c_uint32], c_int32),
+        "cnlos_profile_read": ([P, POINTER(c_double), POINTER(ctypes.c_int64), c_int32], c_int32),
         "cnlos_destroy": ([P], c_int32),
     }
     for name, (args, res) in sig.items():
@@ -266,6 +271,20 @@ class Problem:
             if f in d:
                 setattr(inf, f, d[f])
         check(self._lib.cnlos_set_info(self._h, byref(inf)))
+
+    def profile_enable(self, kinds):
+        """Time every later launch of the named kernel kinds with HIP events."""
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KERNEL_KINDS.index(k)
+        check(self._lib.cnlos_profile_enable(self._h, mask))
+
+    def profile_read(self, reset=True):
+        n = len(KERNEL_KINDS)
+        ms = (c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        check(self._lib.cnlos_profile_read(self._h, ms, cnt, int(bool(reset))))
+        return {k: (ms[i], int(cnt[i])) for i, k in enumerate(KERNEL_KINDS) if cnt[i]}
 
     def log(self, cap=4096):
         buf = np.zeros((cap, 6), dtype=np.float64)

@@ -68,6 +68,8 @@ struct cnlos_problem {
   float2* hq = nullptr;
   float2* tw_t = nullptr;
   float2* tw_xy = nullptr;
+  float2* twc_t = nullptr;
+  float2* twc_xy = nullptr;
   int4* srows = nullptr;
   float* srvals = nullptr;
   int4* scols = nullptr;
@@ -93,9 +95,60 @@ struct cnlos_problem {
   float* lam3 = nullptr;
   float* phi_tau = nullptr;
   Tables tb;
-  int nb_conv = 0, nb_sten = 0;
-  int nnz_r = 0;
+  int nb_conv = 0, nb_solve = 0, nb_sten = 0;
+  Prof prof;
 };
+
+// ---------------------------------------------------------------- event timer
+namespace cnlos {
+
+hipError_t Prof::begin(int kind, hipStream_t st) {
+  Pending pd;
+  pd.kind = kind;
+  hipError_t e = hipSuccess;
+  for (hipEvent_t* ev : {&pd.a, &pd.b}) {
+    if (!pool.empty()) {
+      *ev = pool.back();
+      pool.pop_back();
+    } else {
+      e = hipEventCreate(ev);
+      if (e != hipSuccess) return e;
+    }
+  }
+  pending.push_back(pd);
+  return hipEventRecord(pd.a, st);
+}
+
+hipError_t Prof::end(int kind, hipStream_t st) {
+  for (auto it = pending.rbegin(); it != pending.rend(); ++it)
+    if (it->kind == kind) return hipEventRecord(it->b, st);
+  return hipErrorInvalidValue;
+}
+
+void Prof::harvest() {
+  for (const Pending& pd : pending) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pd.a, pd.b) == hipSuccess) {
+      ms[pd.kind] += t;
+      launches[pd.kind] += 1;
+    }
+    pool.push_back(pd.a);
+    pool.push_back(pd.b);
+  }
+  pending.clear();
+}
+
+void Prof::release() {
+  for (const Pending& pd : pending) {
+    pool.push_back(pd.a);
+    pool.push_back(pd.b);
+  }
+  pending.clear();
+  for (hipEvent_t e : pool) hipEventDestroy(e);
+  pool.clear();
+}
+
+}  // namespace cnlos
 
 namespace {
 
@@ -118,6 +171,8 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
   float2* hq = cv.take<float2>(nhq);
   float2* tw_t = cv.take<float2>(m);
   float2* tw_xy = cv.take<float2>(n);
+  float2* twc_t = cv.take<float2>(m);
+  float2* twc_xy = cv.take<float2>(2 * n);
   int4* srows = cv.take<int4>(m);
   float* srvals = cv.take<float>(resample_nnz(m));
   int4* scols = cv.take<int4>(m);
@@ -135,6 +190,8 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
     p->hq = hq;
     p->tw_t = tw_t;
     p->tw_xy = tw_xy;
+    p->twc_t = twc_t;
+    p->twc_xy = twc_xy;
     p->srows = srows;
     p->srvals = srvals;
     p->scols = scols;
@@ -236,6 +293,15 @@ cnlos_status validate_cfg(const cnlos_config* c) {
     }                                                                                  \
   } while (0)
 
+// launch `call` with event timing when its kind is selected
+#define TIMED(kind, call)                                      \
+  do {                                                         \
+    const bool t_ = p->prof.on(kind);                          \
+    if (t_) HIPCHK(p->prof.begin(kind, p->st));                \
+    HIPCHK(call);                                              \
+    if (t_) HIPCHK(p->prof.end(kind, p->st));                  \
+  } while (0)
+
 PhiArgs phi_args(const cnlos_problem* p, int stage, bool tau) {
   const cnlos_config& c = p->cfg;
   PhiArgs pa;
@@ -259,6 +325,7 @@ double phi_at_zero(const PhiArgs& pa) { return pa.kind == 2 ? sqrt(pa.a) : pa.a;
 cnlos_status ctl_pull(cnlos_problem* p) {
   HIPCHK(hipMemcpyAsync(p->ctl_host, p->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, p->st));
   HIPCHK(hipStreamSynchronize(p->st));
+  p->prof.harvest();
   return CNLOS_OK;
 }
 
@@ -271,7 +338,7 @@ cnlos_status ctl_push(cnlos_problem* p) {
 // One padded convolution of the problem (forward or adjoint).
 hipError_t conv(cnlos_problem* p, const ConvSrc& src, bool adjoint, int epi, const ConvEpi& ep,
                 const DevCtl* ctl) {
-  return launch_conv(p->logn, p->logm, p->tb, src, p->spec, adjoint, epi, ep, ctl, p->st);
+  return launch_conv(p->logn, p->logm, p->tb, src, p->spec, adjoint, epi, ep, ctl, p->st, &p->prof);
 }
 
 // ||B||^2 by power iteration (B = A_D when masked, else A), from the ones vector.
@@ -356,13 +423,13 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
     const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
     float* zf[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3, p->w, p->lam2, p->lam};
     size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V, 3 * V};
-    HIPCHK(launch_transition(ln, lm, ctl, u_cur, p->ubar, p->phi, pu, p->phi_tau, phi_at_zero(pt),
+    TIMED(KK_OTHER, launch_transition(ln, lm, ctl, u_cur, p->ubar, p->phi, pu, p->phi_tau, phi_at_zero(pt),
                              zf, zc, 8, p->st));
   }
 
   if (stage == 1) {
     const double mu = c.mu;
-    HIPCHK(launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, p->st));
+    TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, p->st));
     ConvSrc sa{};
     sa.a = au_cur;
     sa.b = au_prev;
@@ -373,12 +440,12 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
     ConvEpi ea{};
     ea.out = p->gf;
     HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
-    HIPCHK(launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, p->st));
+    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, p->st));
     SolveEpi se{};
     se.out = u_tr;
     se.ref = p->ubar;
     se.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, p->st));
+    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, p->st, &p->prof));
     ConvSrc sf{};
     sf.a = u_tr;
     ConvEpi ef{};
@@ -390,14 +457,12 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
     ef.tau0 = p->tau0;
     ef.partials = p->partials;
     HIPCHK(conv(p, sf, false, EPI_FWD_OBJ, ef, ctl));
-    HIPCHK(launch_check(ctl, p->partials, p->nb_conv, p->nb_conv, c.backtracking ? 1 : 0, p->st));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0, p->st));
     const PhiArgs pa = phi_args(p, 1, false);
-    HIPCHK(launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu, pa, nullptr,
+    TIMED(KK_POST_U, launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu, pa, nullptr,
                        nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
-    ConvEpi dummy{};
-    (void)dummy;
     // the data term of the energy comes from the forward pass (SL_DATA)
-    HIPCHK(launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu, p->st));
+    TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu, p->st));
     return CNLOS_OK;
   }
 
@@ -405,9 +470,9 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
   const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
   float* tau_cur = p->T[k & 1];
   float* tau_tr = p->T[(k + 1) & 1];
-  HIPCHK(launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, ctl, p->st));
-  HIPCHK(launch_vstep(ln, lm, p->taubar, p->lam2, p->phi_tau, p->w, mu2, ctl, p->st));
-  HIPCHK(launch_fstep(ln, lm, p->taubar, p->lam3, p->tau0, p->mask, p->f, lam, mu3, ctl, p->st));
+  TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, ctl, p->st));
+  TIMED(KK_VSTEP, launch_vstep(ln, lm, p->taubar, p->lam2, p->phi_tau, p->w, mu2, ctl, p->st));
+  TIMED(KK_FSTEP, launch_fstep(ln, lm, p->taubar, p->lam3, p->tau0, p->mask, p->f, lam, mu3, ctl, p->st));
   ConvSrc sa{};
   sa.a = au_cur;
   sa.b = au_prev;
@@ -417,12 +482,12 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
   ConvEpi ea{};
   ea.out = p->gf;
   HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
-  HIPCHK(launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, p->st));
+  TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, p->st));
   SolveEpi se{};
   se.out = u_tr;
   se.ref = p->ubar;
   se.partials = p->partials;
-  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, p->st));
+  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, p->st, &p->prof));
   ConvSrc sf{};
   sf.a = u_tr;
   ConvEpi ef{};
@@ -432,18 +497,19 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
   ef.au_prev = au_prev;
   ef.partials = p->partials;
   HIPCHK(conv(p, sf, false, EPI_FWD_DUAL, ef, ctl));
-  HIPCHK(launch_check(ctl, p->partials, p->nb_conv, p->nb_conv, c.backtracking ? 1 : 0, p->st));
-  HIPCHK(launch_rhs_tau(ln, lm, au_tr, p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3, ctl, p->st));
+  TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0, p->st));
+  TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, au_tr, p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3, ctl, p->st));
   SolveEpi st2{};
   st2.out = tau_tr;
   st2.partials = p->partials;
-  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, p->st));
+  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, p->st,
+                      &p->prof));
   const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
-  HIPCHK(launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu1, pu, nullptr,
+  TIMED(KK_POST_U, launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu1, pu, nullptr,
                      nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
-  HIPCHK(launch_post(ln, lm, true, tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, mu2, pt,
+  TIMED(KK_POST_TAU, launch_post(ln, lm, true, tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, mu2, pt,
                      p->f, p->lam3, mu3, au_tr, p->tau0, p->mask, p->partials, ctl, p->st));
-  HIPCHK(launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1, p->st));
+  TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1, p->st));
   return CNLOS_OK;
 }
 
@@ -578,6 +644,7 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
   p->ws_bytes = workspace_bytes;
   carve(p, *cfg, p->ws);
   p->nb_conv = conv_blocks(p->logn, p->logm);
+  p->nb_solve = solve_blocks(p->logn, p->logm);
   p->nb_sten = stencil_blocks(p->logn, p->logm);
   *out = p;   // from here on errors leave a handle the caller must destroy
 
@@ -599,6 +666,17 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
     const double a = -2.0 * PI * j / (2.0 * n);
     tw_xy[j] = make_float2((float)cos(a), (float)sin(a));
   }
+  // per-span butterfly twiddles: entry d + k holds exp(-pi i k / d), d = 1, 2, 4, ...
+  auto per_span = [&](int size) {
+    std::vector<float2> t(size, make_float2(1.f, 0.f));
+    for (int d = 1; d < size; d <<= 1)
+      for (int k = 0; k < d; ++k) {
+        const double a = -PI * k / d;
+        t[d + k] = make_float2((float)cos(a), (float)sin(a));
+      }
+    return t;
+  };
+  const std::vector<float2> twc_t = per_span(m), twc_xy = per_span(2 * n);
   // R_z as overlap lengths of [sqrt(q/m), sqrt((q+1)/m)) with [k/m, (k+1)/m), times m
   std::vector<std::vector<std::pair<int, double>>> rows(m), cols(m);
   for (int q = 0; q < m; ++q) {
@@ -679,6 +757,8 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
   };
   HIPCHK(h2d(p->tw_t, tw_t.data(), m * sizeof(float2)));
   HIPCHK(h2d(p->tw_xy, tw_xy.data(), n * sizeof(float2)));
+  HIPCHK(h2d(p->twc_t, twc_t.data(), m * sizeof(float2)));
+  HIPCHK(h2d(p->twc_xy, twc_xy.data(), 2 * n * sizeof(float2)));
   HIPCHK(h2d(p->srows, srows.data(), m * sizeof(int4)));
   HIPCHK(h2d(p->scols, scols.data(), m * sizeof(int4)));
   HIPCHK(h2d(p->srvals, srv.data(), srv.size() * sizeof(float)));
@@ -695,6 +775,8 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
 
   p->tb.tw_t = p->tw_t;
   p->tb.tw_xy = p->tw_xy;
+  p->tb.twc_t = p->twc_t;
+  p->tb.twc_xy = p->twc_xy;
   p->tb.S.rows = p->srows;
   p->tb.S.rvals = p->srvals;
   p->tb.S.cols = p->scols;
@@ -953,12 +1035,34 @@ cnlos_status cnlos_get_log(cnlos_problem* p, double* host, int32_t cap, int32_t*
   return CNLOS_OK;
 }
 
+cnlos_status cnlos_profile_enable(cnlos_problem* p, uint32_t kind_mask) {
+  CHECK_HANDLE(p);
+  p->prof.mask = kind_mask & ((1u << KK_COUNT) - 1u);
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_profile_read(cnlos_problem* p, double* ms, int64_t* launches, int32_t reset) {
+  CHECK_HANDLE(p);
+  HIPCHK(hipStreamSynchronize(p->st));
+  p->prof.harvest();
+  for (int k = 0; k < KK_COUNT; ++k) {
+    if (ms) ms[k] = p->prof.ms[k];
+    if (launches) launches[k] = p->prof.launches[k];
+    if (reset) {
+      p->prof.ms[k] = 0.0;
+      p->prof.launches[k] = 0;
+    }
+  }
+  return CNLOS_OK;
+}
+
 cnlos_status cnlos_destroy(cnlos_problem* p) {
   if (!p) return CNLOS_OK;
   if (p->ctl_host) {
     if (!p->poisoned) hipStreamSynchronize(p->st);
     hipHostFree(p->ctl_host);
   }
+  p->prof.release();
   delete p;
   return CNLOS_OK;
 }

@@ -4,7 +4,47 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace cnlos {
+
+// Kernel kinds for event timing (mirrors cnlos_kernel_kind of the ABI).
+enum KernelKind : int {
+  KK_T_FWD_CONV = 0,
+  KK_PLANE_CONV = 1,
+  KK_T_INV_CONV = 2,
+  KK_T_FWD_SOLVE = 3,
+  KK_PLANE_SOLVE = 4,
+  KK_T_INV_SOLVE = 5,
+  KK_VSTEP = 6,
+  KK_FSTEP = 7,
+  KK_RHS_U = 8,
+  KK_RHS_TAU = 9,
+  KK_POST_U = 10,
+  KK_POST_TAU = 11,
+  KK_CONTROL = 12,
+  KK_OTHER = 13,
+  KK_COUNT = 14
+};
+
+// HIP-event timer around launches of selected kernel kinds, on the launch
+// stream.  Pairs are harvested after the stream has been synchronized.
+struct Prof {
+  uint32_t mask = 0;
+  double ms[KK_COUNT] = {};
+  long long launches[KK_COUNT] = {};
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  bool on(int kind) const { return (mask >> kind) & 1u; }
+  hipError_t begin(int kind, hipStream_t st);
+  hipError_t end(int kind, hipStream_t st);
+  void harvest();     // stream must be idle
+  void release();
+};
 
 // Reduction slots of the FP64 partials buffer.
 enum Slot : int {
@@ -102,6 +142,8 @@ struct SolveEpi {
 struct Tables {
   const float2* tw_t;     // exp(-2 pi i j / (2m)), j < m
   const float2* tw_xy;    // exp(-2 pi i j / (2n)), j < n
+  const float2* twc_t;    // per-span butterfly twiddles: [d + k] = exp(-pi i k / d), size m
+  const float2* twc_xy;   // the same for the (x, y) transforms, size 2n
   ResampleTables S;
   const float* sig_xy;    // 4 sin^2(pi k / n), k < n
   const float* sig_t;     // 4 sin^2(pi k / m), k <= m/2
@@ -112,13 +154,14 @@ struct Tables {
 // All launchers return hipGetLastError() of their launch.
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       hipStream_t st);
+                       hipStream_t st, Prof* prof);
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
                         const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, hipStream_t st);
+                        const DevCtl* ctl, hipStream_t st, Prof* prof);
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
                            const double* cosn, double invZ, hipStream_t st);
-int conv_blocks(int logn, int logm);          // blocks of the t-axis passes (partials count)
+int conv_blocks(int logn, int logm);          // blocks of the convolution t passes
+int solve_blocks(int logn, int logm);         // blocks of the diagonal-solve t passes
 
 // ADMM stencils and control (k_admm.hip)
 struct PhiArgs {

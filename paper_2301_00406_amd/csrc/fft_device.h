@@ -112,6 +112,125 @@ struct FftRun<LOGL, STOP, STOP, MAXR, INV> {
 };
 
 // ---------------------------------------------------------------------------
+// Lane-split register FFT.  A group of LANES consecutive lanes holds one
+// sequence; lane s keeps the elements at positions p = LANES * r + s,
+// r < E, in registers.  Stages whose span is a multiple of LANES are done in
+// registers ("in-lane"); spans LANES/2 .. 1 pair lanes s and s ^ span
+// ("cross-lane") through DPP / swizzle lane exchanges.  Stage twiddles come
+// from the per-span table twc[d + k] = W_{2d}^k (d = 1, 2, 4, ...), which
+// neighbouring lanes read at neighbouring addresses (no LDS bank conflicts).
+// ---------------------------------------------------------------------------
+// Value of lane (lane ^ D).  D = 1, 2: DPP quad permutation; D < 32:
+// ds_swizzle in bit-mask mode (lane' = lane ^ D within 32-lane halves);
+// D = 32: ds_bpermute.
+template <int D>
+__device__ __forceinline__ float lane_xor(float v) {
+  const int i = __float_as_int(v);
+  if constexpr (D == 1) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));   // [1,0,3,2]
+  } else if constexpr (D == 2) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));   // [2,3,0,1]
+  } else if constexpr (D < 32) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(i, 0x1F | (D << 10)));
+  } else {
+    return __shfl_xor(v, D, 64);
+  }
+}
+
+template <int D>
+__device__ __forceinline__ float2 lane_xor2(float2 v) {
+  return make_float2(lane_xor<D>(v.x), lane_xor<D>(v.y));
+}
+
+// One cross-lane DIF stage of span D.  Lower lane: a + b; upper lane:
+// (a - b) w, written branch-free as (o + sgn x) w' with sgn = -1, w' = w on
+// the upper lane and sgn = 1, w' = 1 on the lower one.
+template <int D, int E>
+__device__ __forceinline__ void dif_xstage(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+  const bool upper = (s & D) != 0;
+  const float2 tw_ = twc[D + (s & (D - 1))];
+  const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
+  const float sg = upper ? -1.f : 1.f;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const float2 o = lane_xor2<D>(x[r]);
+    x[r] = cmul(make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y), w);
+  }
+}
+
+// One cross-lane DIT stage of span D.  Lower lane: a + b conj(w); upper
+// lane: a - b conj(w); branch-free: y = (upper ? mine : other) conj(w),
+// result = (upper ? other : mine) + sgn y.
+template <int D, int E>
+__device__ __forceinline__ void dit_xstage(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+  const bool upper = (s & D) != 0;
+  const float2 w = twc[D + (s & (D - 1))];
+  const float sg = upper ? -1.f : 1.f;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const float2 o = lane_xor2<D>(x[r]);
+    const float2 b = upper ? x[r] : o;
+    const float2 a = upper ? o : x[r];
+    const float2 y = cmulc(b, w);
+    x[r] = make_float2(a.x + sg * y.x, a.y + sg * y.y);
+  }
+}
+
+// DIF stages with spans LANES*DR0, ..., LANES (r distances DR0 .. 1).
+template <int LANES, int E, int DR0>
+__device__ __forceinline__ void dif_inlane(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+#pragma unroll
+  for (int dr = DR0; dr >= 1; dr >>= 1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (r & dr) continue;
+      const float2 a = x[r], b = x[r + dr];
+      const int pos = LANES * (r & (dr - 1)) + s;
+      x[r] = cadd(a, b);
+      x[r + dr] = cmul(csub(a, b), twc[LANES * dr + pos]);
+    }
+  }
+}
+
+// DIF stages with spans LANES/2 .. 1 across the lanes of a group.
+template <int LANES, int E>
+__device__ __forceinline__ void dif_xlane(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+  if constexpr (LANES >= 64) dif_xstage<32, E>(x, s, twc);
+  if constexpr (LANES >= 32) dif_xstage<16, E>(x, s, twc);
+  if constexpr (LANES >= 16) dif_xstage<8, E>(x, s, twc);
+  if constexpr (LANES >= 8) dif_xstage<4, E>(x, s, twc);
+  if constexpr (LANES >= 4) dif_xstage<2, E>(x, s, twc);
+  if constexpr (LANES >= 2) dif_xstage<1, E>(x, s, twc);
+}
+
+// DIT stages with spans 1 .. LANES/2 across the lanes (conjugate twiddles).
+template <int LANES, int E>
+__device__ __forceinline__ void dit_xlane(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+  if constexpr (LANES >= 2) dit_xstage<1, E>(x, s, twc);
+  if constexpr (LANES >= 4) dit_xstage<2, E>(x, s, twc);
+  if constexpr (LANES >= 8) dit_xstage<4, E>(x, s, twc);
+  if constexpr (LANES >= 16) dit_xstage<8, E>(x, s, twc);
+  if constexpr (LANES >= 32) dit_xstage<16, E>(x, s, twc);
+  if constexpr (LANES >= 64) dit_xstage<32, E>(x, s, twc);
+}
+
+// DIT stages with spans LANES, ..., LANES*DRMAX (r distances 1 .. DRMAX).
+template <int LANES, int E, int DRMAX>
+__device__ __forceinline__ void dit_inlane(float2 (&x)[E], int s, const float2* __restrict__ twc) {
+#pragma unroll
+  for (int dr = 1; dr <= DRMAX; dr <<= 1) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      if (r & dr) continue;
+      const int pos = LANES * (r & (dr - 1)) + s;
+      const float2 a = x[r], b = cmulc(x[r + dr], twc[LANES * dr + pos]);
+      x[r] = cadd(a, b);
+      x[r + dr] = csub(a, b);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Deterministic FP64 reductions: wave shuffle, then LDS in lane order, then a
 // per-block partial written to partials[slot * max_blocks + blockIdx.x].
 // ---------------------------------------------------------------------------

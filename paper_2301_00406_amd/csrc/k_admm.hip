@@ -13,11 +13,13 @@
 namespace cnlos {
 
 constexpr int kStencilThreads = 256;
+constexpr int kStencilMaxBlocks = 1024;   // 16 waves per CU; keeps the partial arrays short
+constexpr int kCtlThreads = 1024;
 
 int stencil_blocks(int logn, int logm) {
   const size_t V = (size_t)1 << (2 * logn + logm);
   size_t nb = (V + kStencilThreads - 1) / kStencilThreads;
-  if (nb > (size_t)kMaxBlocks) nb = kMaxBlocks;
+  if (nb > (size_t)kStencilMaxBlocks) nb = kStencilMaxBlocks;
   return (int)nb;
 }
 
@@ -235,7 +237,7 @@ k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int l
 // L/2 |u+ - ubar|^2 is exactly |B (u+ - ubar)|^2 <= L |u+ - ubar|^2, B = A_D
 // (object) or A (dual); the left side comes from the difference of A u+ and
 // the cached A ubar, free of the cancellation of the literal form.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kCtlThreads)
 k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on) {
   if (ctl->halt) return;
   const double s_chk = block_sum_partials(partials, SL_CHECK, nb_conv, kMaxBlocks);
@@ -259,7 +261,7 @@ k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_st
 }
 
 // Energy, residuals, log row, FISTA t update, stopping rule.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kCtlThreads)
 k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
            int nb_conv, int nb_sten, int dual, double lambda, double mu_res) {
   if (ctl->halt) return;
@@ -397,9 +399,17 @@ k_meas_prep(const float* __restrict__ raw, const uint8_t* __restrict__ mask,
 __global__ void __launch_bounds__(256)
 k_meas_reduce(DevCtl* ctl, const double* __restrict__ partials, int nb) {
   const double bad = block_sum_partials(partials, SL_BAD, nb, kMaxBlocks);
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    m = fmax(m, partials[(size_t)SL_MAX * kMaxBlocks + i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  __shared__ double redm[4];
+  if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int i = 0; i < nb; ++i) m = fmax(m, partials[(size_t)SL_MAX * kMaxBlocks + i]);
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, redm[k]);
+    m = fmax(m, redm[0]);
     ctl->meas_scale = m;
     ctl->reason = bad > 0.0 ? HR_NONFINITE : HR_NONE;
   }
@@ -477,14 +487,15 @@ hipError_t launch_post(int logn, int logm, bool tau_mode, const float* xnew, con
 
 hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(256), 0, st, ctl, partials, nb_conv, nb_step, bt_on);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(kCtlThreads), 0, st, ctl, partials, nb_conv, nb_step,
+                     bt_on);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
                            int nb_sten, int dual, double lambda, double mu_res, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, ctl, log, partials, nb_conv, nb_sten,
-                     dual, lambda, mu_res);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kCtlThreads), 0, st, ctl, log, partials, nb_conv,
+                     nb_sten, dual, lambda, mu_res);
   return hipGetLastError();
 }
 

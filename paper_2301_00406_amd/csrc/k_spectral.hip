@@ -21,13 +21,6 @@ namespace cnlos {
 // ---------------------------------------------------------------------------
 // launch shapes
 // ---------------------------------------------------------------------------
-template <int LOGM>
-struct TCfg {
-  static constexpr int J = LOGM <= 8 ? 16 : (LOGM <= 10 ? 8 : 4);   // columns per block
-  static constexpr int ES = J + 1;                                  // padded LDS stride
-  static constexpr int NT = 256;
-};
-
 template <int LOGN>
 struct PlaneCfg {
   static constexpr int NN = 1 << (2 * LOGN);
@@ -36,20 +29,64 @@ struct PlaneCfg {
 };
 
 // ---------------------------------------------------------------------------
-// t pass, forward, convolution: x -> S x -> zero-pad to 2m -> R2C -> planes
+// t passes.  A block handles J = 8 scan columns; each column's FFT lives in
+// the registers of a group of G lanes (lane s keeps positions G*r + s).
+// Spectrum planes are exchanged with global memory through an LDS staging
+// tile [kt][J], so every plane access is a 64-byte segment.
 // ---------------------------------------------------------------------------
+template <int LOGF>
+struct TGeo {                                 // transform of length F = 2^LOGF
+  static constexpr int F = 1 << LOGF;
+  static constexpr int G = (F / 2) < 64 ? (F / 2) : 64;   // lanes per column
+  static constexpr int E = F / G;                         // elements per lane (>= 2)
+  static constexpr int J = LOGF >= 11 ? 4 : 8;            // columns per block
+  static constexpr int NT = J * G;
+};
+
+// LDS index of staging element (kt, column b): rows of J + 1 plus one extra
+// slot every 8 rows, so that rows kt and kt + 8 (bit-reversed neighbours) and
+// consecutive rows fall into different banks.
+template <int J>
+__device__ __forceinline__ int stg(int k, int b) { return k * (J + 1) + (k >> 3) + b; }
+template <int J>
+constexpr int stg_size(int rows) { return rows * (J + 1) + rows / 8 + J; }
+// LDS index of a column's transform element p, padded every 8 elements so
+// that bit-reversed access patterns spread over the banks.
+__device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
+
+// t pass, forward, convolution: x -> R_z x -> zero-pad to 2m -> R2C -> planes.
+// The real length-2m transform is a complex length-m transform of the packed
+// pairs (x[2p], x[2p+1]); its upper half is zero, so the first DIF stage is a
+// twist.
 template <int LOGM>
-__global__ void __launch_bounds__(256)
-k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw, float2* __restrict__ spec,
-            int nn, const DevCtl* ctl) {
-  constexpr int M = 1 << LOGM, H = M / 2;
-  constexpr int J = TCfg<LOGM>::J, ES = TCfg<LOGM>::ES;
-  __shared__ float2 z[M * ES];
+__global__ void __launch_bounds__(TGeo<LOGM>::NT)
+k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
+            const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl) {
+  using T = TGeo<LOGM>;
+  constexpr int M = 1 << LOGM, G = T::G, E = T::E, J = T::J, NT = T::NT;
+  constexpr int ZS = M + M / 8 + 4;               // per-column LDS stride (float2)
+  constexpr int LDS2 = (J * ZS > stg_size<J>(M + 1)) ? J * ZS : stg_size<J>(M + 1);
+  // the resampling table (<= 3m + 64 values) is staged in LDS up to m = 1024
+  constexpr bool STAGE = M <= 1024;
+  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
+  __shared__ float2 lds[LDS2];
   __shared__ float2 tws[M];
+  __shared__ float2 twc[M];
+  __shared__ int4 srow_l[STAGE ? M : 1];
+  __shared__ float sval_l[NNZ];
   if (ctl != nullptr && ctl->halt) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int col0 = blockIdx.x * J;
-  for (int i = tid; i < M; i += nthr) tws[i] = tw[i];
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = blockIdx.x * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) {
+    tws[i] = tw[i];
+    twc[i] = twcg[i];
+  }
+  if constexpr (STAGE) {
+    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
+    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
+  }
+  const int4* srow = STAGE ? srow_l : S.rows;
+  const float* sval = STAGE ? sval_l : S.rvals;
 
   float ca = 1.f, cb = 0.f;
   if (src.lincache) {
@@ -58,103 +95,127 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw, float2
     cb = (float)(-beta);
   }
   const float sc = src.scale_div ? (float)(1.0 / *src.scale_div) : 1.f;
-
-  // real input of each column, staged in the (still unused) upper half
-  float* xf = reinterpret_cast<float*>(z + H * ES);
-  for (int it = tid; it < J * M; it += nthr) {
-    const int k = it & (M - 1), b = it >> LOGM;
-    const int col = col0 + b;
+  const float mk = src.mask ? (float)src.mask[col] : 1.f;
+  float* xf = reinterpret_cast<float*>(lds + b * ZS);     // this column's real input
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = G * r + s;
     const size_t g = (size_t)col * M + k;
     float x = ca * src.a[g];
     if (src.b) x += cb * src.b[g];
     if (src.c) x -= src.c[g];
     if (src.w) x *= src.w[k];
-    if (src.mask) x *= (float)src.mask[col];
-    xf[k * ES + b] = x * sc;
+    xf[k] = x * sc * mk;
   }
   __syncthreads();
-  // R_z: squared-distance bins q = 2p, 2p+1 packed as one complex value
-  for (int it = tid; it < J * H; it += nthr) {
-    const int b = it % J, p = it / J;
-    float r[2];
+  // R_z rows 2p, 2p+1 packed as one complex value, lower half of the transform
+  float2 x[E];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int4 ri = S.rows[2 * p + s];
+  for (int r = 0; r < E / 2; ++r) {
+    const int p = G * r + s;
+    float v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int4 ri = srow[2 * p + h];
       float acc = 0.f;
-      for (int t = 0; t < ri.y; ++t) acc += S.rvals[ri.z + t] * xf[(ri.x + t) * ES + b];
-      r[s] = acc;
+      for (int t = 0; t < ri.y; ++t) acc += sval[ri.z + t] * xf[ri.x + t];
+      v[h] = acc;
     }
-    z[p * ES + b] = make_float2(r[0], r[1]);
+    x[r] = make_float2(v[0], v[1]);
   }
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) x[r + E / 2] = cmul(x[r], tws[2 * (G * r + s)]);
+  dif_inlane<G, E, E / 4>(x, s, twc);
+  dif_xlane<G, E>(x, s, twc);
+  __syncthreads();                                 // every column's input consumed
+  float2* z = lds + b * ZS;
+#pragma unroll
+  for (int r = 0; r < E; ++r) z[zix(G * r + s)] = x[r];
   __syncthreads();
-  // first DIF stage against the zero upper half
-  for (int it = tid; it < J * H; it += nthr) {
-    const int b = it % J, p = it / J;
-    z[(p + H) * ES + b] = cmul(z[p * ES + b], tws[2 * p]);
-  }
-  __syncthreads();
-  FftRun<LOGM, 1, LOGM, 3, false>::go(z, J, 1, ES, tws, LOGM + 1, tid, nthr);
-  // untangle the packed real transform: X[k], k = 0..m
-  for (int it = tid; it < J * (M + 1); it += nthr) {
-    const int b = it % J, k = it / J;
-    const float2 zk = z[brev(k & (M - 1), LOGM) * ES + b];
-    const float2 zm = z[brev((M - k) & (M - 1), LOGM) * ES + b];
+  // untangle the packed real transform: X[k] = 1/2 (Z_k + conj Z_{m-k}) - i/2 W^k (Z_k - conj Z_{m-k})
+  float2 X[E];
+  float2 XM = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r <= E; ++r) {
+    const int k = r < E ? G * r + s : M;
+    if (r == E && s != 0) break;
+    const float2 zk = z[zix(brev(k & (M - 1), LOGM))];
+    const float2 zm = z[zix(brev((M - k) & (M - 1), LOGM))];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     const float2 o = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
     const float2 wk = k < M ? tws[k] : make_float2(-1.f, 0.f);
     const float2 wo = cmul(wk, o);
-    spec[(size_t)k * nn + col0 + b] = make_float2(e.x + wo.y, e.y - wo.x);
+    const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
+    if (r < E) X[r] = v; else XM = v;
+  }
+  __syncthreads();                                 // staging overwrites the columns
+#pragma unroll
+  for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
+  if (s == 0) lds[stg<J>(M, b)] = XM;
+  __syncthreads();
+  for (int it = tid; it < (M + 1) * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
   }
 }
 
-// ---------------------------------------------------------------------------
 // t pass, inverse, convolution: planes -> C2R (length 2m) -> crop -> S^T -> epilogue
-// ---------------------------------------------------------------------------
 template <int LOGM, int EPI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
-            const float2* __restrict__ tw, ConvEpi ep, float scale, const DevCtl* ctl) {
-  constexpr int M = 1 << LOGM, H = M / 2;
-  constexpr int J = TCfg<LOGM>::J, ES = TCfg<LOGM>::ES;
-  __shared__ float2 z[M * ES];
+            const float2* __restrict__ tw, const float2* __restrict__ twcg, ConvEpi ep, float scale,
+            const DevCtl* ctl) {
+  using T = TGeo<LOGM>;
+  constexpr int M = 1 << LOGM, H = M / 2, G = T::G, E = T::E, J = T::J, NT = T::NT;
+  constexpr bool STAGE = M <= 1024;
+  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
+  __shared__ float2 lds[stg_size<J>(M + 1)];
   __shared__ float2 tws[M];
+  __shared__ float2 twc[M];
+  __shared__ int4 scol_l[STAGE ? M : 1];
+  __shared__ float sval_l[NNZ];
   if (ctl != nullptr && ctl->halt) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int col0 = blockIdx.x * J;
-  for (int i = tid; i < M; i += nthr) tws[i] = tw[i];
-  __syncthreads();
-
-  // Hermitian pair (k, m-k) -> packed even/odd spectrum Z, bit-reversed
-  for (int it = tid; it < J * (H + 1); it += nthr) {
-    const int b = it % J, k = it / J;
-    const int col = col0 + b;
-    const float2 Xk = spec[(size_t)k * nn + col];
-    const float2 Xm = spec[(size_t)(M - k) * nn + col];
-    const float2 wk = tws[k];
-    {
-      const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
-      const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
-      const float2 wo = cmulc(o, wk);
-      z[brev(k, LOGM) * ES + b] = make_float2(e.x - wo.y, e.y + wo.x);
-    }
-    if (k != 0 && k != H) {
-      const float2 e = make_float2(0.5f * (Xm.x + Xk.x), 0.5f * (Xm.y - Xk.y));
-      const float2 o = make_float2(0.5f * (Xm.x - Xk.x), 0.5f * (Xm.y + Xk.y));
-      float2 wo = cmul(o, wk);
-      wo = make_float2(-wo.x, -wo.y);
-      z[brev(M - k, LOGM) * ES + b] = make_float2(e.x - wo.y, e.y + wo.x);
-    }
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = blockIdx.x * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) {
+    tws[i] = tw[i];
+    twc[i] = twcg[i];
+  }
+  if constexpr (STAGE) {
+    for (int i = tid; i < M; i += NT) scol_l[i] = S.cols[i];
+    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.cvals[i];
+  }
+  const int4* scol = STAGE ? scol_l : S.cols;
+  const float* sval = STAGE ? sval_l : S.cvals;
+  for (int it = tid; it < (M + 1) * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
   }
   __syncthreads();
-  FftRun<LOGM, 0, LOGM - 1, 3, true>::go(z, J, 1, ES, tws, LOGM + 1, tid, nthr);
-  // last DIT stage, lower half only (the crop to the first m real samples)
-  for (int it = tid; it < J * H; it += nthr) {
-    const int b = it % J, p = it / J;
-    z[p * ES + b] = cadd(z[p * ES + b], cmulc(z[(p + H) * ES + b], tws[2 * p]));
+  // packed even/odd spectrum at this lane's bit-reversed positions:
+  // Z[k] = 1/2 (X_k + conj X_{m-k}) + i/2 conj(W^k) (X_k - conj X_{m-k})
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = brev(G * r + s, LOGM);
+    const float2 Xk = lds[stg<J>(k, b)];
+    const float2 Xm = lds[stg<J>(M - k, b)];
+    const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
+    const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
+    const float2 wo = cmulc(o, tws[k]);
+    x[r] = make_float2(e.x - wo.y, e.y + wo.x);
   }
+  dit_xlane<G, E>(x, s, twc);
+  dit_inlane<G, E, E / 4>(x, s, twc);
+  // last stage (span m/2), lower half only: the crop to the first m samples
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) x[r] = cadd(x[r], cmulc(x[r + E / 2], tws[2 * (G * r + s)]));
+  __syncthreads();                                 // staging consumed
+  float2* g2 = lds + b * (H + 2);                  // this column's real samples, packed
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) g2[G * r + s] = cscale(x[r], scale);
   __syncthreads();
-
-  const float* zf = reinterpret_cast<const float*>(z);
+  const float* g = reinterpret_cast<const float*>(g2);
   double acc0 = 0.0, acc1 = 0.0;
   float ca = 1.f, cb = 0.f;
   if (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) {
@@ -162,31 +223,27 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
     ca = (float)(1.0 + beta);
     cb = (float)(-beta);
   }
-  for (int it = tid; it < J * M; it += nthr) {
-    const int k = it & (M - 1), b = it >> LOGM;
-    const int col = col0 + b;
-    const int4 ci = S.cols[k];
+  const float mk = ep.mask ? (float)ep.mask[col] : 1.f;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = G * r + s;
+    const int4 ci = scol[k];
     float tk = 0.f;
-    for (int t = 0; t < ci.y; ++t) {
-      const int q = ci.x + t;
-      tk += S.cvals[ci.z + t] * zf[((q >> 1) * ES + b) * 2 + (q & 1)];
-    }
-    tk *= scale;
+    for (int t = 0; t < ci.y; ++t) tk += sval[ci.z + t] * g[ci.x + t];
     if (ep.w) tk *= ep.w[k];
-    const size_t g = (size_t)col * M + k;
+    const size_t gi = (size_t)col * M + k;
     if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
-      if (ep.mask) tk *= (float)ep.mask[col];
-      ep.out[g] = tk;
+      tk *= mk;
+      ep.out[gi] = tk;
       if (EPI == EPI_NORM) acc0 += (double)tk * (double)tk;
     } else {
-      ep.out[g] = tk;
-      const float aub = ca * ep.au[g] + cb * ep.au_prev[g];
-      const float d = tk - aub;
+      ep.out[gi] = tk;
+      const float d = tk - (ca * ep.au[gi] + cb * ep.au_prev[gi]);
       if (EPI == EPI_FWD_OBJ) {
-        if (ep.mask[col]) {
+        if (mk != 0.f) {
           acc0 += (double)d * (double)d;
-          const float r = tk - ep.tau0[g];
-          acc1 += (double)r * (double)r;
+          const float rr = tk - ep.tau0[gi];
+          acc1 += (double)rr * (double)rr;
         }
       } else {
         acc0 += (double)d * (double)d;
@@ -282,121 +339,255 @@ k_plane_conv(float2* __restrict__ spec, const float2* __restrict__ hq,
 }
 
 // ---------------------------------------------------------------------------
-// FFT-diagonal solve, eq. (11):  (c I + mu nabla^* nabla) x = rhs, periodic.
-// t pass forward (R2C, length m), plane (2-D FFT, divide, inverse), t pass inverse.
+// Register-resident plane kernel of the convolution (n <= 64).  Rows: 8 lanes
+// per row transform the zero-padded row (length 2n) with the upper half of
+// the first stage folded into a twist; the 2n spectrum positions go to LDS.
+// Columns: 8 lanes per spectrum column transform the zero-padded column,
+// multiply by H^ (or its conjugate) at the position's frequency, transform
+// back and keep the first n rows.  Rows again: inverse, keep the first n.
+// LDS is touched three times per element; every butterfly runs in registers.
 // ---------------------------------------------------------------------------
-template <int LOGM>
-__global__ void __launch_bounds__(256)
-k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
-             float2* __restrict__ spec, int nn, const DevCtl* ctl) {
-  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
-  constexpr int J = TCfg<LOGM>::J, ES = TCfg<LOGM>::ES;
-  __shared__ float2 z[H * ES];
-  __shared__ float2 tws[M];
+template <int LOGN>
+struct PlaneRegCfg {
+  static constexpr int N = 1 << LOGN, L = 2 * N, NT = 8 * N;
+  static constexpr int RE = L / 8, YS = L + 8;
+};
+
+template <int LOGN, bool ADJ>
+__global__ void __launch_bounds__(PlaneRegCfg<LOGN>::NT)
+k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
+                 const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl) {
+  using PC = PlaneRegCfg<LOGN>;
+  constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, NT = PC::NT;
+  constexpr int RE = PC::RE, YS = PC::YS, N1 = N + 1;
+  __shared__ float2 Y[N * YS];
+  __shared__ float2 tws[N];
+  __shared__ float2 twc[L];
   if (ctl != nullptr && ctl->halt) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int col0 = blockIdx.x * J;
-  for (int i = tid; i < M; i += nthr) tws[i] = tw[i];
-  const float2* src2 = reinterpret_cast<const float2*>(src);
-  for (int it = tid; it < J * H; it += nthr) {
-    const int p = it & (H - 1), b = it >> LOGH;
-    z[p * ES + b] = src2[(size_t)(col0 + b) * H + p];
+  const int tid = threadIdx.x;
+  float2* P = spec + (size_t)blockIdx.x * N * N;
+  const float2* Hp = hq + (size_t)blockIdx.x * N1 * N1;
+  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+  for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
+  __syncthreads();
+  {
+    const int row = tid >> 3, s = tid & 7;
+    float2 x[RE];
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) x[r] = P[row * N + 8 * r + s];
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) x[r + RE / 2] = cmul(x[r], tws[8 * r + s]);
+    dif_inlane<8, RE, RE / 4>(x, s, twc);
+    dif_xlane<8, RE>(x, s, twc);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) Y[row * YS + 8 * r + s] = x[r];
   }
   __syncthreads();
-  FftRun<LOGH, 0, LOGH, 3, false>::go(z, J, 1, ES, tws, LOGM + 1, tid, nthr);
-  for (int it = tid; it < J * (H + 1); it += nthr) {
-    const int b = it % J, k = it / J;
-    const float2 zk = z[brev(k & (H - 1), LOGH) * ES + b];
-    const float2 zm = z[brev((H - k) & (H - 1), LOGH) * ES + b];
-    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    const float2 o = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-    const float2 wk = k < H ? tws[2 * k] : make_float2(-1.f, 0.f);
-    const float2 wo = cmul(wk, o);
-    spec[(size_t)k * nn + col0 + b] = make_float2(e.x + wo.y, e.y - wo.x);
+  {
+    // 2n spectrum columns, 8 lanes each, two columns per lane group
+    const int s = tid & 7;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+      const int col = (tid >> 3) + half * N;
+      float2 c[RE];
+#pragma unroll
+      for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
+#pragma unroll
+      for (int r = 0; r < RE / 2; ++r) c[r + RE / 2] = cmul(c[r], tws[8 * r + s]);
+      dif_inlane<8, RE, RE / 4>(c, s, twc);
+      dif_xlane<8, RE>(c, s, twc);
+      int ky = brev(col, LOGL);
+      ky = ky <= N ? ky : L - ky;
+#pragma unroll
+      for (int r = 0; r < RE; ++r) {
+        int kx = brev(8 * r + s, LOGL);
+        kx = kx <= N ? kx : L - kx;
+        const float2 h = Hp[kx * N1 + ky];
+        c[r] = ADJ ? cmulc(c[r], h) : cmul(c[r], h);
+      }
+      dit_xlane<8, RE>(c, s, twc);
+      dit_inlane<8, RE, RE / 4>(c, s, twc);
+#pragma unroll
+      for (int r = 0; r < RE / 2; ++r) c[r] = cadd(c[r], cmulc(c[r + RE / 2], tws[8 * r + s]));
+#pragma unroll
+      for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = c[r];
+    }
+  }
+  __syncthreads();
+  {
+    const int row = tid >> 3, s = tid & 7;
+    float2 x[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) x[r] = Y[row * YS + 8 * r + s];
+    dit_xlane<8, RE>(x, s, twc);
+    dit_inlane<8, RE, RE / 4>(x, s, twc);
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) x[r] = cadd(x[r], cmulc(x[r + RE / 2], tws[8 * r + s]));
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) P[row * N + 8 * r + s] = x[r];
   }
 }
 
+// Register-resident plane kernel of the diagonal solve (n <= 128): rows and
+// columns of length n by 8 lanes each, divide at the column step.
 template <int LOGN>
-__global__ void __launch_bounds__(PlaneCfg<LOGN>::NT)
-k_plane_solve(float2* __restrict__ spec, const float2* __restrict__ tw,
-              const float* __restrict__ sig_xy, const float* __restrict__ sig_t,
-              const double* c_dev, float c_val, float mu, const DevCtl* ctl) {
-  constexpr int N = 1 << LOGN, NP = N + 1, NN = N * N;
-  constexpr int NT = PlaneCfg<LOGN>::NT;
-  __shared__ float2 A[N * NP];
-  __shared__ float2 tws[N];
+struct PlaneSolveCfg {
+  static constexpr int N = 1 << LOGN, NT = 8 * N, E = N / 8, YS = N + 8;
+};
+
+template <int LOGN>
+__global__ void __launch_bounds__(PlaneSolveCfg<LOGN>::NT)
+k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
+                  const float* __restrict__ sig_xy, const float* __restrict__ sig_t,
+                  const double* c_dev, float c_val, float mu, const DevCtl* ctl) {
+  using PC = PlaneSolveCfg<LOGN>;
+  constexpr int N = PC::N, NT = PC::NT, E = PC::E, YS = PC::YS;
+  __shared__ float2 Y[N * YS];
+  __shared__ float2 twc[N];
   __shared__ float sg[N];
   if (ctl != nullptr && ctl->halt) return;
   const int tid = threadIdx.x;
   const int plane = blockIdx.x;
-  float2* P = spec + (size_t)plane * NN;
+  float2* P = spec + (size_t)plane * N * N;
   for (int i = tid; i < N; i += NT) {
-    tws[i] = tw[i];
+    twc[i] = twcg[i];
     sg[i] = sig_xy[i];
   }
-  for (int e = tid; e < NN; e += NT) A[(e >> LOGN) * NP + (e & (N - 1))] = P[e];
   __syncthreads();
-  FftRun<LOGN, 0, LOGN, 3, false>::go(A, N, NP, 1, tws, LOGN + 1, tid, NT);
-  FftRun<LOGN, 0, LOGN, 3, false>::go(A, N, 1, NP, tws, LOGN + 1, tid, NT);
+  const int g = tid >> 3, s = tid & 7;
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = P[g * N + 8 * r + s];
+  dif_inlane<8, E, E / 2>(x, s, twc);
+  dif_xlane<8, E>(x, s, twc);
+#pragma unroll
+  for (int r = 0; r < E; ++r) Y[g * YS + 8 * r + s] = x[r];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = Y[(8 * r + s) * YS + g];
+  dif_inlane<8, E, E / 2>(x, s, twc);
+  dif_xlane<8, E>(x, s, twc);
   const float c = c_dev ? (float)(*c_dev) : c_val;
-  const float base = c + mu * sig_t[plane];
-  for (int e = tid; e < NN; e += NT) {
-    const int pi = e >> LOGN, pj = e & (N - 1);
-    const float den = base + mu * (sg[brev(pi, LOGN)] + sg[brev(pj, LOGN)]);
-    A[pi * NP + pj] = cscale(A[pi * NP + pj], 1.f / den);
-  }
+  const float base = c + mu * (sig_t[plane] + sg[brev(g, LOGN)]);
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = cscale(x[r], 1.f / (base + mu * sg[brev(8 * r + s, LOGN)]));
+  dit_xlane<8, E>(x, s, twc);
+  dit_inlane<8, E, E / 2>(x, s, twc);
+#pragma unroll
+  for (int r = 0; r < E; ++r) Y[(8 * r + s) * YS + g] = x[r];
   __syncthreads();
-  FftRun<LOGN, 0, LOGN, 3, true>::go(A, N, 1, NP, tws, LOGN + 1, tid, NT);
-  FftRun<LOGN, 0, LOGN, 3, true>::go(A, N, NP, 1, tws, LOGN + 1, tid, NT);
-  for (int e = tid; e < NN; e += NT) P[e] = A[(e >> LOGN) * NP + (e & (N - 1))];
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = Y[g * YS + 8 * r + s];
+  dit_xlane<8, E>(x, s, twc);
+  dit_inlane<8, E, E / 2>(x, s, twc);
+#pragma unroll
+  for (int r = 0; r < E; ++r) P[g * N + 8 * r + s] = x[r];
 }
 
+// ---------------------------------------------------------------------------
+// FFT-diagonal solve, eq. (11):  (c I + mu nabla^* nabla) x = rhs, periodic.
+// t pass forward (R2C, length m), plane (2-D FFT, divide, inverse), t pass inverse.
+// ---------------------------------------------------------------------------
+// t pass, forward, diagonal solve: real length m -> complex length m/2 of the
+// packed pairs -> untangle -> planes kt = 0 .. m/2.
 template <int LOGM>
-__global__ void __launch_bounds__(256)
-k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__ tw,
-             SolveEpi ep, float scale, const DevCtl* ctl) {
-  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1, Q = H / 2;
-  constexpr int J = TCfg<LOGM>::J, ES = TCfg<LOGM>::ES;
-  __shared__ float2 z[H * ES];
+__global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
+k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
+             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl) {
+  using T = TGeo<LOGM - 1>;
+  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
+  constexpr int G = T::G, E = T::E, J = T::J, NT = T::NT, ZS = H + H / 8 + 4;
+  constexpr int LDS2 = (J * ZS > stg_size<J>(H + 1)) ? J * ZS : stg_size<J>(H + 1);
+  __shared__ float2 lds[LDS2];
   __shared__ float2 tws[M];
+  __shared__ float2 twc[H];
   if (ctl != nullptr && ctl->halt) return;
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int col0 = blockIdx.x * J;
-  for (int i = tid; i < M; i += nthr) tws[i] = tw[i];
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = blockIdx.x * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) tws[i] = tw[i];
+  for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
+  const float2* src2 = reinterpret_cast<const float2*>(src) + (size_t)col * H;
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = src2[G * r + s];
   __syncthreads();
-  for (int it = tid; it < J * (Q + 1); it += nthr) {
-    const int b = it % J, k = it / J;
-    const int col = col0 + b;
-    const float2 Xk = spec[(size_t)k * nn + col];
-    const float2 Xm = spec[(size_t)(H - k) * nn + col];
-    const float2 wk = tws[2 * k];   // W_m^k
-    {
-      const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
-      const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
-      const float2 wo = cmulc(o, wk);
-      z[brev(k & (H - 1), LOGH) * ES + b] = make_float2(e.x - wo.y, e.y + wo.x);
-    }
-    if (k != 0 && k != Q) {
-      const float2 e = make_float2(0.5f * (Xm.x + Xk.x), 0.5f * (Xm.y - Xk.y));
-      const float2 o = make_float2(0.5f * (Xm.x - Xk.x), 0.5f * (Xm.y + Xk.y));
-      float2 wo = cmul(o, wk);
-      wo = make_float2(-wo.x, -wo.y);
-      z[brev(H - k, LOGH) * ES + b] = make_float2(e.x - wo.y, e.y + wo.x);
-    }
+  dif_inlane<G, E, E / 2>(x, s, twc);
+  dif_xlane<G, E>(x, s, twc);
+  float2* z = lds + b * ZS;
+#pragma unroll
+  for (int r = 0; r < E; ++r) z[zix(G * r + s)] = x[r];
+  __syncthreads();
+  float2 X[E];
+  float2 XH = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r <= E; ++r) {
+    const int k = r < E ? G * r + s : H;
+    if (r == E && s != 0) break;
+    const float2 zk = z[zix(brev(k & (H - 1), LOGH))];
+    const float2 zm = z[zix(brev((H - k) & (H - 1), LOGH))];
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 o = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+    const float2 wk = k < H ? tws[2 * k] : make_float2(-1.f, 0.f);
+    const float2 wo = cmul(wk, o);
+    const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
+    if (r < E) X[r] = v; else XH = v;
   }
   __syncthreads();
-  FftRun<LOGH, 0, LOGH, 3, true>::go(z, J, 1, ES, tws, LOGM + 1, tid, nthr);
+#pragma unroll
+  for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
+  if (s == 0) lds[stg<J>(H, b)] = XH;
+  __syncthreads();
+  for (int it = tid; it < (H + 1) * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
+  }
+}
+
+// t pass, inverse, diagonal solve: planes kt = 0 .. m/2 -> C2R (length m).
+template <int LOGM>
+__global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
+k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__ tw,
+             const float2* __restrict__ twcg, SolveEpi ep, float scale, const DevCtl* ctl) {
+  using T = TGeo<LOGM - 1>;
+  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
+  constexpr int G = T::G, E = T::E, J = T::J, NT = T::NT;
+  __shared__ float2 lds[stg_size<J>(H + 1)];
+  __shared__ float2 tws[M];
+  __shared__ float2 twc[H];
+  if (ctl != nullptr && ctl->halt) return;
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = blockIdx.x * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) tws[i] = tw[i];
+  for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
+  for (int it = tid; it < (H + 1) * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
+  }
+  __syncthreads();
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = brev(G * r + s, LOGH);
+    const float2 Xk = lds[stg<J>(k, b)];
+    const float2 Xm = lds[stg<J>(H - k, b)];
+    const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
+    const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
+    const float2 wo = cmulc(o, tws[2 * k]);
+    x[r] = make_float2(e.x - wo.y, e.y + wo.x);
+  }
+  dit_xlane<G, E>(x, s, twc);
+  dit_inlane<G, E, E / 2>(x, s, twc);
   double acc = 0.0;
-  float2* out2 = reinterpret_cast<float2*>(ep.out);
-  const float2* ref2 = reinterpret_cast<const float2*>(ep.ref);
-  for (int it = tid; it < J * H; it += nthr) {
-    const int p = it & (H - 1), b = it >> LOGH;
-    const size_t g = (size_t)(col0 + b) * H + p;
-    const float2 y = cscale(z[p * ES + b], scale);
-    out2[g] = y;
-    if (ep.ref) {
-      const float2 r = ref2[g];
-      const float d0 = y.x - r.x, d1 = y.y - r.y;
+  float2* out2 = reinterpret_cast<float2*>(ep.out) + (size_t)col * H;
+  const float2* ref2 = ep.ref ? reinterpret_cast<const float2*>(ep.ref) + (size_t)col * H : nullptr;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int p = G * r + s;
+    const float2 y = cscale(x[r], scale);
+    out2[p] = y;
+    if (ref2) {
+      const float2 rv = ref2[p];
+      const float d0 = y.x - rv.x, d1 = y.y - rv.y;
       acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
     }
   }
@@ -460,45 +651,69 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int LOGM>
-static int cols_per_block() { return TCfg<LOGM>::J; }
+// blocks of the t passes (their partial sums are indexed by block)
+int conv_blocks(int logn, int logm) { return (1 << (2 * logn)) / (logm >= 11 ? 4 : 8); }
+int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / (logm - 1 >= 11 ? 4 : 8); }
 
-static int cols_per_block_rt(int logm) {
-  return logm <= 8 ? 16 : (logm <= 10 ? 8 : 4);
-}
-
-int conv_blocks(int logn, int logm) { return (1 << (2 * logn)) / cols_per_block_rt(logm); }
+#define CNLOS_TIMED(prof, kind, st, launch)                 \
+  do {                                                     \
+    const bool t_ = (prof) != nullptr && (prof)->on(kind); \
+    if (t_) (void)(prof)->begin(kind, st);                 \
+    launch;                                                \
+    if (t_) (void)(prof)->end(kind, st);                   \
+  } while (0)
 
 template <int LOGN, int LOGM>
 static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, bool adjoint,
-                            int epi, const ConvEpi& ep, const DevCtl* ctl, hipStream_t st) {
+                            int epi, const ConvEpi& ep, const DevCtl* ctl, hipStream_t st,
+                            Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
-  const int nb = NN / TCfg<LOGM>::J;
-  hipLaunchKernelGGL(k_tfwd_conv<LOGM>, dim3(nb), dim3(256), 0, st, src, tb.S, tb.tw_t, spec, NN,
-                     ctl);
-  if (adjoint)
-    hipLaunchKernelGGL((k_plane_conv<LOGN, true>), dim3(M + 1), dim3(PlaneCfg<LOGN>::NT), 0, st,
-                       spec, tb.hq, tb.tw_xy, ctl);
-  else
-    hipLaunchKernelGGL((k_plane_conv<LOGN, false>), dim3(M + 1), dim3(PlaneCfg<LOGN>::NT), 0, st,
-                       spec, tb.hq, tb.tw_xy, ctl);
+  using TG = TGeo<LOGM>;
+  const int nb = NN / TG::J;
+  CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
+              hipLaunchKernelGGL(k_tfwd_conv<LOGM>, dim3(nb), dim3(TG::NT), 0, st, src, tb.S,
+                                 tb.tw_t, tb.twc_t, spec, NN, ctl));
+  if constexpr (LOGN <= 6) {
+    constexpr int LN = LOGN;
+    if (adjoint)
+      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M + 1),
+                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
+    else
+      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M + 1),
+                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
+  } else {
+    if (adjoint)
+      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
+                  hipLaunchKernelGGL((k_plane_conv<LOGN, true>), dim3(M + 1),
+                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl));
+    else
+      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
+                  hipLaunchKernelGGL((k_plane_conv<LOGN, false>), dim3(M + 1),
+                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl));
+  }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
   switch (epi) {
     case EPI_PLAIN:
-      hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_PLAIN>), dim3(nb), dim3(256), 0, st, spec, NN,
-                         tb.S, tb.tw_t, ep, scale, ctl);
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_PLAIN>), dim3(nb), dim3(TG::NT), 0, st,
+                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     case EPI_FWD_OBJ:
-      hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_OBJ>), dim3(nb), dim3(256), 0, st, spec, NN,
-                         tb.S, tb.tw_t, ep, scale, ctl);
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_OBJ>), dim3(nb), dim3(TG::NT), 0, st,
+                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     case EPI_FWD_DUAL:
-      hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_DUAL>), dim3(nb), dim3(256), 0, st, spec, NN,
-                         tb.S, tb.tw_t, ep, scale, ctl);
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_DUAL>), dim3(nb), dim3(TG::NT), 0,
+                                     st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     default:
-      hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_NORM>), dim3(nb), dim3(256), 0, st, spec, NN,
-                         tb.S, tb.tw_t, ep, scale, ctl);
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_NORM>), dim3(nb), dim3(TG::NT), 0, st,
+                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
   }
   return hipGetLastError();
@@ -507,15 +722,21 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
 template <int LOGN, int LOGM>
 static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, const double* c_dev,
                              double c_val, double mu, const SolveEpi& ep, const DevCtl* ctl,
-                             hipStream_t st) {
+                             hipStream_t st, Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
-  const int nb = NN / TCfg<LOGM>::J;
-  hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb), dim3(256), 0, st, rhs, tb.tw_t, spec, NN, ctl);
-  hipLaunchKernelGGL(k_plane_solve<LOGN>, dim3(M / 2 + 1), dim3(PlaneCfg<LOGN>::NT), 0, st, spec,
-                     tb.tw_xy, tb.sig_xy, tb.sig_t, c_dev, (float)c_val, (float)mu, ctl);
+  using TG = TGeo<LOGM - 1>;
+  const int nb = NN / TG::J;
+  CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+              hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb), dim3(TG::NT), 0, st, rhs, tb.tw_t,
+                                 tb.twc_t, spec, NN, ctl));
+  CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
+              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2 + 1),
+                                 dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
+                                 tb.sig_t, c_dev, (float)c_val, (float)mu, ctl));
   const float scale = (float)(2.0 / ((double)NN * (double)M));
-  hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb), dim3(256), 0, st, spec, NN, tb.tw_t, ep, scale,
-                     ctl);
+  CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
+              hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb), dim3(TG::NT), 0, st, spec, NN,
+                                 tb.tw_t, tb.twc_t, ep, scale, ctl));
   return hipGetLastError();
 }
 
@@ -544,14 +765,14 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, c
 
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       hipStream_t st) {
-  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, st)
+                       hipStream_t st, Prof* prof) {
+  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, st, prof)
 }
 
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
                         const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, hipStream_t st) {
-  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, spec, c_dev, c_val, mu, ep, ctl, st)
+                        const DevCtl* ctl, hipStream_t st, Prof* prof) {
+  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, spec, c_dev, c_val, mu, ep, ctl, st, prof)
 }
 
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
