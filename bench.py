@@ -75,18 +75,14 @@ def algorithmic_bytes(kind, n, m, dual):
         return 2 * spec_s
     if kind == "t_inv_solve":      # the u solve also reads ubar
         return spec_s + f + (f / 2 if dual else f)
-    if kind == "vstep":
-        return 8 * f
-    if kind == "fstep":
-        return 4 * f + n * n
+    if kind == "vstep":            # dual: v, w and f steps in one kernel
+        return 20 * f + n * n if dual else 8 * f
     if kind == "rhs_u":
         return 9 * f
     if kind == "rhs_tau":
         return 10 * f
-    if kind == "post_u":
-        return 13 * f
-    if kind == "post_tau":
-        return 18 * f + n * n
+    if kind == "post_u":           # dual: u side and tau side in one kernel
+        return 31 * f + n * n if dual else 13 * f
     return 0.0
 
 

@@ -243,12 +243,14 @@ typedef enum {
   CNLOS_KK_T_FWD_SOLVE = 3,  /* diagonal solve: R2C along t                   */
   CNLOS_KK_PLANE_SOLVE = 4,  /* diagonal solve: (x, y) transform and divide    */
   CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t                   */
-  CNLOS_KK_VSTEP = 6,        /* shrinkage steps (v, w)                         */
-  CNLOS_KK_FSTEP = 7,        /* dual model f step                              */
+  CNLOS_KK_VSTEP = 6,        /* steps before the u solve: v (object model);
+                                v, w and f in one kernel (dual model)          */
+  CNLOS_KK_FSTEP = 7,        /* reserved (the f step runs inside VSTEP)        */
   CNLOS_KK_RHS_U = 8,        /* right-hand side of the u solve                 */
   CNLOS_KK_RHS_TAU = 9,      /* right-hand side of the tau solve               */
-  CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature (u)       */
-  CNLOS_KK_POST_TAU = 11,    /* multiplier, extrapolation, curvature (tau)     */
+  CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature: u (object
+                                model); u and tau in one kernel (dual model)   */
+  CNLOS_KK_POST_TAU = 11,    /* reserved (the tau side runs inside POST_U)     */
   CNLOS_KK_CONTROL = 12,     /* backtracking decision and iteration finalize   */
   CNLOS_KK_OTHER = 13,       /* warm-start hand-over                           */
   CNLOS_KK_COUNT = 14

@@ -111,7 +111,9 @@ hipError_t Prof::begin(int kind, hipStream_t st) {
       *ev = pool.back();
       pool.pop_back();
     } else {
-      e = hipEventCreate(ev);
+      // timing-only events: no system-scope fence (no cache write-back between
+      // the bracketed kernel and its neighbours)
+      e = hipEventCreateWithFlags(ev, hipEventDisableSystemFence);
       if (e != hipSuccess) return e;
     }
   }
@@ -470,9 +472,9 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
   const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
   float* tau_cur = p->T[k & 1];
   float* tau_tr = p->T[(k + 1) & 1];
-  TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, ctl, p->st));
-  TIMED(KK_VSTEP, launch_vstep(ln, lm, p->taubar, p->lam2, p->phi_tau, p->w, mu2, ctl, p->st));
-  TIMED(KK_FSTEP, launch_fstep(ln, lm, p->taubar, p->lam3, p->tau0, p->mask, p->f, lam, mu3, ctl, p->st));
+  TIMED(KK_VSTEP, launch_pre_dual(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, p->taubar, p->lam2,
+                                  p->phi_tau, p->w, mu2, p->lam3, p->tau0, p->mask, p->f, lam, mu3,
+                                  ctl, p->st));
   ConvSrc sa{};
   sa.a = au_cur;
   sa.b = au_prev;
@@ -504,11 +506,11 @@ cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
   st2.partials = p->partials;
   HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, p->st,
                       &p->prof));
-  const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
-  TIMED(KK_POST_U, launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu1, pu, nullptr,
-                     nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
-  TIMED(KK_POST_TAU, launch_post(ln, lm, true, tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, mu2, pt,
-                     p->f, p->lam3, mu3, au_tr, p->tau0, p->mask, p->partials, ctl, p->st));
+  const PostArgs pu{u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, (float)mu1, phi_args(p, 2, false)};
+  const PostArgs pt{tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, (float)mu2,
+                    phi_args(p, 2, true)};
+  TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->f, p->lam3, mu3, au_tr, p->tau0, p->mask,
+                                    p->partials, ctl, p->st));
   TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1, p->st));
   return CNLOS_OK;
 }

@@ -171,9 +171,26 @@ struct PhiArgs {
 };
 hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
                         float* v, double mu, const DevCtl* ctl, hipStream_t st);
-hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
-                        const float* tau0, const uint8_t* mask, float* f, double lambda,
-                        double mu3, const DevCtl* ctl, hipStream_t st);
+// one side (u or tau) of the post-step update
+struct PostArgs {
+  const float* xn;   // x+ (accepted)
+  const float* xo;   // x^k
+  const float* v;    // v (u side) or w (tau side)
+  float* lam;        // Lambda or Lambda2, updated in place
+  float* xbar;       // extrapolated point, written
+  float* phi;        // curvature weight, written
+  float mu;
+  PhiArgs pa;
+};
+hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* lam,
+                           const float* phi, float* v, double mu1, const float* taubar,
+                           const float* lam2, const float* phi_tau, float* w, double mu2,
+                           const float* lam3, const float* tau0, const uint8_t* mask, float* f,
+                           double lambda, double mu3, const DevCtl* ctl, hipStream_t st);
+hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
+                            const float* f, float* lam3, double mu3, const float* au,
+                            const float* tau0, const uint8_t* mask, double* partials,
+                            const DevCtl* ctl, hipStream_t st);
 hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
                         const float* lam, double mu, const DevCtl* ctl, hipStream_t st);
 hipError_t launch_rhs_tau(int logn, int logm, const float* au, const float* f, const float* lam3,

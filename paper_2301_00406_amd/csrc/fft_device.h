@@ -159,20 +159,20 @@ __device__ __forceinline__ void dif_xstage(float2 (&x)[E], int s, const float2* 
 }
 
 // One cross-lane DIT stage of span D.  Lower lane: a + b conj(w); upper
-// lane: a - b conj(w); branch-free: y = (upper ? mine : other) conj(w),
-// result = (upper ? other : mine) + sgn y.
+// lane: a - b conj(w).  The upper lane scales its own value by conj(w) before
+// the exchange (the lower lane by 1), so both results are o + sgn t with t
+// the lane's scaled value and o the partner's: no selects per element.
 template <int D, int E>
 __device__ __forceinline__ void dit_xstage(float2 (&x)[E], int s, const float2* __restrict__ twc) {
   const bool upper = (s & D) != 0;
-  const float2 w = twc[D + (s & (D - 1))];
+  const float2 tw_ = twc[D + (s & (D - 1))];
+  const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
   const float sg = upper ? -1.f : 1.f;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const float2 o = lane_xor2<D>(x[r]);
-    const float2 b = upper ? x[r] : o;
-    const float2 a = upper ? o : x[r];
-    const float2 y = cmulc(b, w);
-    x[r] = make_float2(a.x + sg * y.x, a.y + sg * y.y);
+    const float2 t = cmulc(x[r], w);
+    const float2 o = lane_xor2<D>(t);
+    x[r] = make_float2(o.x + sg * t.x, o.y + sg * t.y);
   }
 }
 
@@ -260,6 +260,39 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
       partials[(size_t)slots[s] * max_blocks + blockIdx.x] = acc;
     }
   }
+}
+
+// Sums of K partial arrays partials[slot[k]][0..nb[k]) by one block, all K
+// loaded and reduced together, each in a fixed order; results valid in thread 0.
+template <int K>
+__device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ partials,
+                                                     const int (&slot)[K], const int (&nb)[K],
+                                                     int max_blocks, double (&out)[K]) {
+  __shared__ double red[K][16];
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    acc[k] = 0.0;
+    for (int i = threadIdx.x; i < nb[k]; i += blockDim.x)
+      acc[k] += partials[(size_t)slot[k] * max_blocks + i];
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double w = wave_sum(acc[k]);
+    if (lane == 0) red[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double tot = 0.0;
+      for (int j = 0; j < nw; ++j) tot += red[k][j];
+      out[k] = tot;
+    }
+  }
+  __syncthreads();
 }
 
 // Sum of partials[slot][0..nb) by one block, in a fixed order; result valid in

@@ -79,40 +79,53 @@ __device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_
   return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
 }
 
-// v = shrink(grad ubar - Lambda/mu, phi/mu), isotropic over the three components (eq. (7))
+// v = shrink(grad xbar - Lambda/mu, phi/mu) at voxel g, isotropic over the
+// three components (eq. (7); the w-step of Algorithm 2 is the same on taubar)
+__device__ __forceinline__ void vstep_at(const float* __restrict__ xb, const float* __restrict__ lam,
+                                         const float* __restrict__ phi, float* __restrict__ v,
+                                         float inv_mu, size_t g, size_t V, const Nbr& nb) {
+  float gx, gy, gt;
+  grad_at(xb, g, nb.xp, nb.yp, nb.tp, gx, gy, gt);
+  const float ax = gx - lam[g] * inv_mu;
+  const float ay = gy - lam[V + g] * inv_mu;
+  const float at = gt - lam[2 * V + g] * inv_mu;
+  const float nrm = sqrtf(ax * ax + ay * ay + at * at);
+  const float thr = phi[g] * inv_mu;
+  const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
+  v[g] = ax * s;
+  v[V + g] = ay * s;
+  v[2 * V + g] = at * s;
+}
+
 __global__ void __launch_bounds__(kStencilThreads)
 k_vstep(const float* __restrict__ ub, const float* __restrict__ lam, const float* __restrict__ phi,
         float* __restrict__ v, float inv_mu, int logn, int logm, const DevCtl* ctl) {
   if (ctl->halt) return;
   const size_t V = (size_t)1 << (2 * logn + logm);
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    float gx, gy, gt;
-    grad_at(ub, g, nb.xp, nb.yp, nb.tp, gx, gy, gt);
-    const float ax = gx - lam[g] * inv_mu;
-    const float ay = gy - lam[V + g] * inv_mu;
-    const float at = gt - lam[2 * V + g] * inv_mu;
-    const float nrm = sqrtf(ax * ax + ay * ay + at * at);
-    const float thr = phi[g] * inv_mu;
-    const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
-    v[g] = ax * s;
-    v[V + g] = ay * s;
-    v[2 * V + g] = at * s;
-  }
+       g += (size_t)gridDim.x * blockDim.x)
+    vstep_at(ub, lam, phi, v, inv_mu, g, V, neighbours(g, logn, logm));
 }
 
-// f: pointwise minimizer of lambda/2 |f - tau0|^2 on kept points + <Lambda3, f - taubar>
-//    + mu3/2 |f - taubar|^2
+// Algorithm 2's pointwise steps before the u update, in one pass: v on ubar,
+// w on taubar, and f, the pointwise minimizer of lambda/2 |f - tau0|^2 on kept
+// points + <Lambda3, f - taubar> + mu3/2 |f - taubar|^2.
 __global__ void __launch_bounds__(kStencilThreads)
-k_fstep(const float* __restrict__ taubar, const float* __restrict__ lam3,
-        const float* __restrict__ tau0, const uint8_t* __restrict__ mask, float* __restrict__ f,
-        float lambda, float mu3, int logn, int logm, const DevCtl* ctl) {
+k_pre_dual(const float* __restrict__ ub, const float* __restrict__ lam,
+           const float* __restrict__ phi, float* __restrict__ v, float inv_mu1,
+           const float* __restrict__ taubar, const float* __restrict__ lam2,
+           const float* __restrict__ phi_tau, float* __restrict__ w, float inv_mu2,
+           const float* __restrict__ lam3, const float* __restrict__ tau0,
+           const uint8_t* __restrict__ mask, float* __restrict__ f, float lambda, float mu3,
+           int logn, int logm, const DevCtl* ctl) {
   if (ctl->halt) return;
   const size_t V = (size_t)1 << (2 * logn + logm);
   const float inv_kept = 1.f / (lambda + mu3), inv_mu3 = 1.f / mu3;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    vstep_at(ub, lam, phi, v, inv_mu1, g, V, nb);
+    vstep_at(taubar, lam2, phi_tau, w, inv_mu2, g, V, nb);
     const float tb = taubar[g], l3 = lam3[g];
     f[g] = mask[g >> logm] ? (lambda * tau0[g] + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
   }
@@ -162,6 +175,48 @@ k_rhs_tau(const float* __restrict__ au, const float* __restrict__ f, const float
 // tau mode: Lambda2 += mu2 (w - grad tau+), Lambda3 += mu3 (f - tau+), taubar,
 //           phi_tau; partials TV_TAU, FIT (|A u+ - tau+|^2), FID (|D(tau+ - tau0)|^2).
 template <bool TAU>
+__device__ __forceinline__ void post_at(const float* __restrict__ xn, const float* __restrict__ xo,
+                                        const float* __restrict__ v, float* __restrict__ lam,
+                                        float* __restrict__ xbar, float* __restrict__ phi,
+                                        float mu, const PhiArgs& pa, float eta2, float beta,
+                                        const float* __restrict__ f, float* __restrict__ lam3,
+                                        float mu3, const float* __restrict__ au,
+                                        const float* __restrict__ tau0,
+                                        const uint8_t* __restrict__ mask, size_t g, size_t V,
+                                        const Nbr& nb, int logn, int logm, double& s_tv,
+                                        double& s_a, double& s_b) {
+  float gx, gy, gt;
+  const float kappa = curvature_at(xn, g, nb, logn, logm, eta2, gx, gy, gt);
+  const float ph = phi_eval(kappa, pa);
+  phi[g] = ph;
+  const float vx = v[g], vy = v[V + g], vt = v[2 * V + g];
+  lam[g] += mu * (vx - gx);
+  lam[V + g] += mu * (vy - gy);
+  lam[2 * V + g] += mu * (vt - gt);
+  const float x0 = xn[g];
+  const float d0 = x0 - xo[g];
+  xbar[g] = x0 + beta * d0;
+  const float gn = sqrtf(gx * gx + gy * gy + gt * gt);
+  s_tv += (double)ph * (double)gn;
+  if (!TAU) {
+    const float rx = vx - gx, ry = vy - gy, rt = vt - gt;
+    s_a += (double)rx * rx + (double)ry * ry + (double)rt * rt;
+    const float dx = (xn[nb.xp] - xo[nb.xp]) - d0;
+    const float dy = (xn[nb.yp] - xo[nb.yp]) - d0;
+    const float dt = (xn[nb.tp] - xo[nb.tp]) - d0;
+    s_b += (double)dx * dx + (double)dy * dy + (double)dt * dt;
+  } else {
+    lam3[g] += mu3 * (f[g] - x0);
+    const float r = au[g] - x0;
+    s_a += (double)r * r;
+    if (mask[g >> logm]) {
+      const float e = x0 - tau0[g];
+      s_b += (double)e * e;
+    }
+  }
+}
+
+template <bool TAU>
 __global__ void __launch_bounds__(kStencilThreads)
 k_post(const float* __restrict__ xn, const float* __restrict__ xo, const float* __restrict__ v,
        float* __restrict__ lam, float* __restrict__ xbar, float* __restrict__ phi, float mu,
@@ -177,38 +232,9 @@ k_post(const float* __restrict__ xn, const float* __restrict__ xo, const float* 
   const float eta2 = pa.eta * pa.eta;
   double s_tv = 0.0, s_a = 0.0, s_b = 0.0;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    float gx, gy, gt;
-    const float kappa = curvature_at(xn, g, nb, logn, logm, eta2, gx, gy, gt);
-    const float ph = phi_eval(kappa, pa);
-    phi[g] = ph;
-    const float vx = v[g], vy = v[V + g], vt = v[2 * V + g];
-    lam[g] += mu * (vx - gx);
-    lam[V + g] += mu * (vy - gy);
-    lam[2 * V + g] += mu * (vt - gt);
-    const float x0 = xn[g];
-    const float d0 = x0 - xo[g];
-    xbar[g] = x0 + beta * d0;
-    const float gn = sqrtf(gx * gx + gy * gy + gt * gt);
-    s_tv += (double)ph * (double)gn;
-    if (!TAU) {
-      const float rx = vx - gx, ry = vy - gy, rt = vt - gt;
-      s_a += (double)rx * rx + (double)ry * ry + (double)rt * rt;
-      const float dx = (xn[nb.xp] - xo[nb.xp]) - d0;
-      const float dy = (xn[nb.yp] - xo[nb.yp]) - d0;
-      const float dt = (xn[nb.tp] - xo[nb.tp]) - d0;
-      s_b += (double)dx * dx + (double)dy * dy + (double)dt * dt;
-    } else {
-      lam3[g] += mu3 * (f[g] - x0);
-      const float r = au[g] - x0;
-      s_a += (double)r * r;
-      if (mask[g >> logm]) {
-        const float e = x0 - tau0[g];
-        s_b += (double)e * e;
-      }
-    }
-  }
+       g += (size_t)gridDim.x * blockDim.x)
+    post_at<TAU>(xn, xo, v, lam, xbar, phi, mu, pa, eta2, beta, f, lam3, mu3, au, tau0, mask, g,
+                 V, neighbours(g, logn, logm), logn, logm, s_tv, s_a, s_b);
   double vals[3] = {s_tv, s_a, s_b};
   if (!TAU) {
     const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
@@ -219,6 +245,31 @@ k_post(const float* __restrict__ xn, const float* __restrict__ xo, const float* 
   }
 }
 
+// Algorithm 2's updates after the accepted step, u side and tau side in one pass.
+__global__ void __launch_bounds__(kStencilThreads)
+k_post_dual(PostArgs pu, PostArgs pt, const float* __restrict__ f, float* __restrict__ lam3,
+            float mu3, const float* __restrict__ au, const float* __restrict__ tau0,
+            const uint8_t* __restrict__ mask, double* __restrict__ partials, int logn, int logm,
+            const DevCtl* ctl) {
+  if (ctl->halt) return;
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  const double t = ctl->t;
+  const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+  const float beta = (float)((t - 1.0) / tn);
+  const float eu = pu.pa.eta * pu.pa.eta, et = pt.pa.eta * pt.pa.eta;
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const Nbr nb = neighbours(g, logn, logm);
+    post_at<false>(pu.xn, pu.xo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eu, beta, nullptr,
+                   nullptr, 0.f, nullptr, nullptr, nullptr, g, V, nb, logn, logm, s[0], s[1], s[2]);
+    post_at<true>(pt.xn, pt.xo, pt.v, pt.lam, pt.xbar, pt.phi, pt.mu, pt.pa, et, beta, f, lam3,
+                  mu3, au, tau0, mask, g, V, nb, logn, logm, s[3], s[4], s[5]);
+  }
+  const int slots[6] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_TV_TAU, SL_FIT, SL_FID};
+  block_sum_store<6>(s, partials, slots, kMaxBlocks);
+}
+
 // phi = phi(kappa(x)) (warm-start hand-over and resets)
 __global__ void __launch_bounds__(kStencilThreads)
 k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int logn, int logm) {
@@ -227,7 +278,7 @@ k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int l
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
     const Nbr nb = neighbours(g, logn, logm);
-    float gx, gy, gt;
+  float gx, gy, gt;
     phi[g] = phi_eval(curvature_at(x, g, nb, logn, logm, eta2, gx, gy, gt), pa);
   }
 }
@@ -240,8 +291,10 @@ k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int l
 __global__ void __launch_bounds__(kCtlThreads)
 k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on) {
   if (ctl->halt) return;
-  const double s_chk = block_sum_partials(partials, SL_CHECK, nb_conv, kMaxBlocks);
-  const double s_step = block_sum_partials(partials, SL_STEP, nb_step, kMaxBlocks);
+  const int slots[2] = {SL_CHECK, SL_STEP}, nbs[2] = {nb_conv, nb_step};
+  double sums[2];
+  block_sum_partials_k<2>(partials, slots, nbs, kMaxBlocks, sums);
+  const double s_chk = sums[0], s_step = sums[1];
   if (threadIdx.x == 0) {
     if (!isfinite(s_chk) || !isfinite(s_step)) {
       ctl->halt = 1;
@@ -265,18 +318,23 @@ __global__ void __launch_bounds__(kCtlThreads)
 k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
            int nb_conv, int nb_sten, int dual, double lambda, double mu_res) {
   if (ctl->halt) return;
-  const double tv_u = block_sum_partials(partials, SL_TV_U, nb_sten, kMaxBlocks);
-  const double prim = block_sum_partials(partials, SL_PRIMAL, nb_sten, kMaxBlocks);
-  const double dres = block_sum_partials(partials, SL_DUAL, nb_sten, kMaxBlocks);
-  double E;
+  double E, prim, dres;
   if (!dual) {
-    const double data = block_sum_partials(partials, SL_DATA, nb_conv, kMaxBlocks);
-    E = 0.5 * data + tv_u;
+    const int slots[4] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_DATA};
+    const int nbs[4] = {nb_sten, nb_sten, nb_sten, nb_conv};
+    double v[4];
+    block_sum_partials_k<4>(partials, slots, nbs, kMaxBlocks, v);
+    prim = v[1];
+    dres = v[2];
+    E = 0.5 * v[3] + v[0];
   } else {
-    const double fit = block_sum_partials(partials, SL_FIT, nb_sten, kMaxBlocks);
-    const double fid = block_sum_partials(partials, SL_FID, nb_sten, kMaxBlocks);
-    const double tv_t = block_sum_partials(partials, SL_TV_TAU, nb_sten, kMaxBlocks);
-    E = 0.5 * fit + 0.5 * lambda * fid + tv_u + tv_t;
+    const int slots[6] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_FIT, SL_FID, SL_TV_TAU};
+    const int nbs[6] = {nb_sten, nb_sten, nb_sten, nb_sten, nb_sten, nb_sten};
+    double v[6];
+    block_sum_partials_k<6>(partials, slots, nbs, kMaxBlocks, v);
+    prim = v[1];
+    dres = v[2];
+    E = 0.5 * v[3] + 0.5 * lambda * v[4] + v[0] + v[5];
   }
   if (threadIdx.x == 0) {
     if (!isfinite(E)) {
@@ -325,7 +383,7 @@ k_transition_fields(const DevCtl* ctl, const float* __restrict__ u, float* __res
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
     const Nbr nb = neighbours(g, logn, logm);
-    float gx, gy, gt;
+  float gx, gy, gt;
     phi_u[g] = phi_eval(curvature_at(u, g, nb, logn, logm, eta2, gx, gy, gt), pa);
     ubar[g] = u[g];
     phi_tau[g] = phi_tau0;
@@ -446,13 +504,26 @@ hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam,
   return hipGetLastError();
 }
 
-hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
-                        const float* tau0, const uint8_t* mask, float* f, double lambda,
-                        double mu3, const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_fstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, taubar, lam3, tau0,
+hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* lam,
+                           const float* phi, float* v, double mu1, const float* taubar,
+                           const float* lam2, const float* phi_tau, float* w, double mu2,
+                           const float* lam3, const float* tau0, const uint8_t* mask, float* f,
+                           double lambda, double mu3, const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_pre_dual, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, lam, phi, v,
+                     (float)(1.0 / mu1), taubar, lam2, phi_tau, w, (float)(1.0 / mu2), lam3, tau0,
                      mask, f, (float)lambda, (float)mu3, logn, logm, ctl);
   return hipGetLastError();
 }
+
+hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
+                            const float* f, float* lam3, double mu3, const float* au,
+                            const float* tau0, const uint8_t* mask, double* partials,
+                            const DevCtl* ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_post_dual, sgrid(logn, logm), dim3(kStencilThreads), 0, st, pu, pt, f, lam3,
+                     (float)mu3, au, tau0, mask, partials, logn, logm, ctl);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
                         const float* lam, double mu, const DevCtl* ctl, hipStream_t st) {

@@ -57,8 +57,9 @@ __device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
 // t pass, forward, convolution: x -> R_z x -> zero-pad to 2m -> R2C -> planes.
 // The real length-2m transform is a complex length-m transform of the packed
 // pairs (x[2p], x[2p+1]); its upper half is zero, so the first DIF stage is a
-// twist.
-template <int LOGM>
+// twist.  With PK the two real bins kt = 0 and kt = m share plane 0 as
+// X_0 + i X_m, so the transform fills exactly m planes.
+template <int LOGM, bool PK>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl) {
@@ -148,19 +149,23 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
     const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
     if (r < E) X[r] = v; else XM = v;
   }
+  // X_0 and X_m are real (their imaginary parts vanish identically)
+  if (PK && s == 0) X[0].y = XM.x;
   __syncthreads();                                 // staging overwrites the columns
 #pragma unroll
   for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
-  if (s == 0) lds[stg<J>(M, b)] = XM;
+  if (!PK && s == 0) lds[stg<J>(M, b)] = XM;
   __syncthreads();
-  for (int it = tid; it < (M + 1) * J; it += NT) {
+  constexpr int NP = PK ? M : M + 1;
+  for (int it = tid; it < NP * J; it += NT) {
     const int bb = it % J, k = it / J;
     spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
   }
 }
 
 // t pass, inverse, convolution: planes -> C2R (length 2m) -> crop -> S^T -> epilogue
-template <int LOGM, int EPI>
+// (PK: plane 0 holds X_0 + i X_m, as written by the forward pass)
+template <int LOGM, int EPI, bool PK>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
             const float2* __restrict__ tw, const float2* __restrict__ twcg, ConvEpi ep, float scale,
@@ -187,7 +192,8 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   }
   const int4* scol = STAGE ? scol_l : S.cols;
   const float* sval = STAGE ? sval_l : S.cvals;
-  for (int it = tid; it < (M + 1) * J; it += NT) {
+  constexpr int NP = PK ? M : M + 1;
+  for (int it = tid; it < NP * J; it += NT) {
     const int bb = it % J, k = it / J;
     lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
   }
@@ -198,8 +204,12 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = brev(G * r + s, LOGM);
-    const float2 Xk = lds[stg<J>(k, b)];
-    const float2 Xm = lds[stg<J>(M - k, b)];
+    float2 Xk = lds[stg<J>(k, b)];
+    float2 Xm = lds[stg<J>(PK ? (M - k) & (M - 1) : M - k, b)];
+    if (PK && k == 0) {
+      Xm = make_float2(Xk.y, 0.f);
+      Xk.y = 0.f;
+    }
     const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
     const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
     const float2 wo = cmulc(o, tws[k]);
@@ -346,12 +356,88 @@ k_plane_conv(float2* __restrict__ spec, const float2* __restrict__ hq,
 // multiply by H^ (or its conjugate) at the position's frequency, transform
 // back and keep the first n rows.  Rows again: inverse, keep the first n.
 // LDS is touched three times per element; every butterfly runs in registers.
+//
+// Block 0 holds the two real planes kt = 0 and kt = m packed as
+// Z = P_0 + i P_m.  H^ is real on both (h is even in x and y, and the t phase
+// is +-1), so after the row pass the two planes' row spectra separate as
+//   R_0(ky) = (R(ky) + conj R(-ky)) / 2,  R_m(ky) = (R(ky) - conj R(-ky)) / 2i,
+// each column pair is transformed, multiplied by its own H^, recombined as
+// Y_0 + i Y_m and transformed back; the result is conv(P_0) + i conv(P_m).
 // ---------------------------------------------------------------------------
 template <int LOGN>
 struct PlaneRegCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 8 * N;
   static constexpr int RE = L / 8, YS = L + 8;
 };
+
+// forward column transform of a zero-padded column whose first n entries are
+// in c[0 .. RE/2): twist (folded first stage), then the remaining DIF stages
+template <int LOGN>
+__device__ __forceinline__ void col_fwd(float2 (&c)[PlaneRegCfg<LOGN>::RE], int s,
+                                        const float2* tws, const float2* twc) {
+  constexpr int RE = PlaneRegCfg<LOGN>::RE;
+#pragma unroll
+  for (int r = 0; r < RE / 2; ++r) c[r + RE / 2] = cmul(c[r], tws[8 * r + s]);
+  dif_inlane<8, RE, RE / 4>(c, s, twc);
+  dif_xlane<8, RE>(c, s, twc);
+}
+
+// inverse column transform, keeping the first n outputs in c[0 .. RE/2)
+template <int LOGN>
+__device__ __forceinline__ void col_inv(float2 (&c)[PlaneRegCfg<LOGN>::RE], int s,
+                                        const float2* tws, const float2* twc) {
+  constexpr int RE = PlaneRegCfg<LOGN>::RE;
+  dit_xlane<8, RE>(c, s, twc);
+  dit_inlane<8, RE, RE / 4>(c, s, twc);
+#pragma unroll
+  for (int r = 0; r < RE / 2; ++r) c[r] = cadd(c[r], cmulc(c[r + RE / 2], tws[8 * r + s]));
+}
+
+// quarter-spectrum index of the frequency at bit-reversed positions (px, py)
+template <int LOGN>
+__device__ __forceinline__ int hq_index(int px, int py) {
+  constexpr int N = 1 << LOGN, L = 2 * N;
+  int kx = brev(px, LOGN + 1), ky = brev(py, LOGN + 1);
+  kx = kx <= N ? kx : L - kx;
+  ky = ky <= N ? ky : L - ky;
+  return kx * (N + 1) + ky;
+}
+
+// column pass of block 0 (the packed real planes kt = 0 and kt = m)
+template <int LOGN>
+__device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* H0, const float2* Hm,
+                                                       const float2* tws, const float2* twc,
+                                                       int tid) {
+  using PC = PlaneRegCfg<LOGN>;
+  constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, RE = PC::RE, YS = PC::YS;
+  const int s = tid & 7;
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    // -ky has the parity of ky, so a column and its partner lie in the same half
+    const int col = (tid >> 3) + half * N;
+    const int colp = brev((L - brev(col, LOGL)) & (L - 1), LOGL);
+    float2 a0[RE], am[RE];
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) {
+      const float2 c = Y[(8 * r + s) * YS + col];
+      const float2 d = Y[(8 * r + s) * YS + colp];
+      a0[r] = make_float2(0.5f * (c.x + d.x), 0.5f * (c.y - d.y));
+      am[r] = make_float2(0.5f * (c.y + d.y), 0.5f * (d.x - c.x));
+    }
+    __syncthreads();                               // partners read before any write-back
+    col_fwd<LOGN>(a0, s, tws, twc);
+    col_fwd<LOGN>(am, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const int q = hq_index<LOGN>(8 * r + s, col);
+      const float2 y0 = cscale(a0[r], H0[q].x), ym = cscale(am[r], Hm[q].x);
+      a0[r] = make_float2(y0.x - ym.y, y0.y + ym.x);
+    }
+    col_inv<LOGN>(a0, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = a0[r];
+  }
+}
 
 template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneRegCfg<LOGN>::NT)
@@ -383,7 +469,9 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
     for (int r = 0; r < RE; ++r) Y[row * YS + 8 * r + s] = x[r];
   }
   __syncthreads();
-  {
+  if (blockIdx.x == 0) {
+    plane_conv_cols_packed<LOGN>(Y, hq, hq + (size_t)gridDim.x * N1 * N1, tws, twc, tid);
+  } else {
     // 2n spectrum columns, 8 lanes each, two columns per lane group
     const int s = tid & 7;
 #pragma unroll 1
@@ -392,23 +480,13 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
       float2 c[RE];
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
-#pragma unroll
-      for (int r = 0; r < RE / 2; ++r) c[r + RE / 2] = cmul(c[r], tws[8 * r + s]);
-      dif_inlane<8, RE, RE / 4>(c, s, twc);
-      dif_xlane<8, RE>(c, s, twc);
-      int ky = brev(col, LOGL);
-      ky = ky <= N ? ky : L - ky;
+      col_fwd<LOGN>(c, s, tws, twc);
 #pragma unroll
       for (int r = 0; r < RE; ++r) {
-        int kx = brev(8 * r + s, LOGL);
-        kx = kx <= N ? kx : L - kx;
-        const float2 h = Hp[kx * N1 + ky];
+        const float2 h = Hp[hq_index<LOGN>(8 * r + s, col)];
         c[r] = ADJ ? cmulc(c[r], h) : cmul(c[r], h);
       }
-      dit_xlane<8, RE>(c, s, twc);
-      dit_inlane<8, RE, RE / 4>(c, s, twc);
-#pragma unroll
-      for (int r = 0; r < RE / 2; ++r) c[r] = cadd(c[r], cmulc(c[r + RE / 2], tws[8 * r + s]));
+      col_inv<LOGN>(c, s, tws, twc);
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = c[r];
     }
@@ -463,14 +541,42 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
 #pragma unroll
   for (int r = 0; r < E; ++r) Y[g * YS + 8 * r + s] = x[r];
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = Y[(8 * r + s) * YS + g];
-  dif_inlane<8, E, E / 2>(x, s, twc);
-  dif_xlane<8, E>(x, s, twc);
   const float c = c_dev ? (float)(*c_dev) : c_val;
-  const float base = c + mu * (sig_t[plane] + sg[brev(g, LOGN)]);
+  if (plane == 0) {
+    // the real planes kt = 0 and kt = m/2, packed as P_0 + i P_{m/2}: separate
+    // their row spectra with the partner column -ky, divide each by its own
+    // eigenvalue, recombine as Y_0 + i Y_{m/2}
+    const int gp = brev((N - brev(g, LOGN)) & (N - 1), LOGN);
+    float2 xh[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = cscale(x[r], 1.f / (base + mu * sg[brev(8 * r + s, LOGN)]));
+    for (int r = 0; r < E; ++r) {
+      const float2 a = Y[(8 * r + s) * YS + g];
+      const float2 d = Y[(8 * r + s) * YS + gp];
+      x[r] = make_float2(0.5f * (a.x + d.x), 0.5f * (a.y - d.y));
+      xh[r] = make_float2(0.5f * (a.y + d.y), 0.5f * (d.x - a.x));
+    }
+    __syncthreads();                               // partners read before any write-back
+    dif_inlane<8, E, E / 2>(x, s, twc);
+    dif_xlane<8, E>(x, s, twc);
+    dif_inlane<8, E, E / 2>(xh, s, twc);
+    dif_xlane<8, E>(xh, s, twc);
+    const float base0 = c + mu * (sig_t[0] + sg[brev(g, LOGN)]);
+    const float baseh = c + mu * (sig_t[gridDim.x] + sg[brev(g, LOGN)]);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const float sk = mu * sg[brev(8 * r + s, LOGN)];
+      const float2 y0 = cscale(x[r], 1.f / (base0 + sk)), yh = cscale(xh[r], 1.f / (baseh + sk));
+      x[r] = make_float2(y0.x - yh.y, y0.y + yh.x);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r) x[r] = Y[(8 * r + s) * YS + g];
+    dif_inlane<8, E, E / 2>(x, s, twc);
+    dif_xlane<8, E>(x, s, twc);
+    const float base = c + mu * (sig_t[plane] + sg[brev(g, LOGN)]);
+#pragma unroll
+    for (int r = 0; r < E; ++r) x[r] = cscale(x[r], 1.f / (base + mu * sg[brev(8 * r + s, LOGN)]));
+  }
   dit_xlane<8, E>(x, s, twc);
   dit_inlane<8, E, E / 2>(x, s, twc);
 #pragma unroll
@@ -489,7 +595,8 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
 // t pass forward (R2C, length m), plane (2-D FFT, divide, inverse), t pass inverse.
 // ---------------------------------------------------------------------------
 // t pass, forward, diagonal solve: real length m -> complex length m/2 of the
-// packed pairs -> untangle -> planes kt = 0 .. m/2.
+// packed pairs -> untangle -> planes kt = 0 .. m/2 - 1, the two real bins
+// kt = 0 and kt = m/2 sharing plane 0 as X_0 + i X_{m/2}.
 template <int LOGM>
 __global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
 k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
@@ -532,18 +639,19 @@ k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
     const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
     if (r < E) X[r] = v; else XH = v;
   }
+  if (s == 0) X[0].y = XH.x;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
-  if (s == 0) lds[stg<J>(H, b)] = XH;
   __syncthreads();
-  for (int it = tid; it < (H + 1) * J; it += NT) {
+  for (int it = tid; it < H * J; it += NT) {
     const int bb = it % J, k = it / J;
     spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
   }
 }
 
-// t pass, inverse, diagonal solve: planes kt = 0 .. m/2 -> C2R (length m).
+// t pass, inverse, diagonal solve: planes kt = 0 .. m/2 - 1 (plane 0 packed
+// as above) -> C2R (length m).
 template <int LOGM>
 __global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
 k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__ tw,
@@ -559,7 +667,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
   for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
-  for (int it = tid; it < (H + 1) * J; it += NT) {
+  for (int it = tid; it < H * J; it += NT) {
     const int bb = it % J, k = it / J;
     lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
   }
@@ -568,8 +676,12 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = brev(G * r + s, LOGH);
-    const float2 Xk = lds[stg<J>(k, b)];
-    const float2 Xm = lds[stg<J>(H - k, b)];
+    float2 Xk = lds[stg<J>(k, b)];
+    float2 Xm = lds[stg<J>((H - k) & (H - 1), b)];
+    if (k == 0) {
+      Xm = make_float2(Xk.y, 0.f);
+      Xk.y = 0.f;
+    }
     const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
     const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
     const float2 wo = cmulc(o, tws[2 * k]);
@@ -668,20 +780,22 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
                             int epi, const ConvEpi& ep, const DevCtl* ctl, hipStream_t st,
                             Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
+  // the register plane kernel takes the real planes kt = 0, m packed in one
+  constexpr bool PK = LOGN <= 6;
   using TG = TGeo<LOGM>;
   const int nb = NN / TG::J;
   CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
-              hipLaunchKernelGGL(k_tfwd_conv<LOGM>, dim3(nb), dim3(TG::NT), 0, st, src, tb.S,
+              hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb), dim3(TG::NT), 0, st, src, tb.S,
                                  tb.tw_t, tb.twc_t, spec, NN, ctl));
   if constexpr (LOGN <= 6) {
     constexpr int LN = LOGN;
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M + 1),
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M),
                                      dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M + 1),
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M),
                                      dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
   } else {
     if (adjoint)
@@ -697,22 +811,22 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   switch (epi) {
     case EPI_PLAIN:
       CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_PLAIN>), dim3(nb), dim3(TG::NT), 0, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_PLAIN, PK>), dim3(nb), dim3(TG::NT), 0, st,
                                      spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     case EPI_FWD_OBJ:
       CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_OBJ>), dim3(nb), dim3(TG::NT), 0, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_OBJ, PK>), dim3(nb), dim3(TG::NT), 0, st,
                                      spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     case EPI_FWD_DUAL:
       CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_DUAL>), dim3(nb), dim3(TG::NT), 0,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_DUAL, PK>), dim3(nb), dim3(TG::NT), 0,
                                      st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
     default:
       CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_NORM>), dim3(nb), dim3(TG::NT), 0, st,
+                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_NORM, PK>), dim3(nb), dim3(TG::NT), 0, st,
                                      spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
       break;
   }
@@ -730,7 +844,7 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, c
               hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb), dim3(TG::NT), 0, st, rhs, tb.tw_t,
                                  tb.twc_t, spec, NN, ctl));
   CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
-              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2 + 1),
+              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2),
                                  dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
                                  tb.sig_t, c_dev, (float)c_val, (float)mu, ctl));
   const float scale = (float)(2.0 / ((double)NN * (double)M));
