@@ -137,6 +137,8 @@ typedef struct cnlos_report {
   double energy;            /* E(u) (object) or E(u, tau) (dual) after the call */
   double primal_res;        /* ||v - grad u||                                   */
   double dual_res;          /* mu ||grad(u^{k+1} - u^k)||                       */
+  int32_t status;           /* this problem's cnlos_status for the call         */
+  int32_t reserved;
 } cnlos_report;
 
 typedef struct cnlos_info {
@@ -272,6 +274,57 @@ cnlos_status cnlos_destroy(cnlos_problem* p);
 
 /* Thread-local message for the last failing call on this thread ("" if none). */
 const char* cnlos_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batches: several problems that advance together, one kernel launch per
+ * step of the iteration for all of them (launch grid z = problem).  The
+ * scenes are independent reconstructions (Sections 3 and 4.1 per scene); the
+ * batch changes where they run, not what they compute: each member's result
+ * is bitwise the result of running it alone (fixed-order reductions).
+ *
+ * Members must agree on nx, ny, nt, model, phi, falloff, the weights a_u,
+ * b_u, a_tau, b_tau, warm_a, warm_b, the penalties mu, mu1, mu2, mu3, lambda,
+ * eta_curv and backtracking; they may differ in the wall extent, bin width,
+ * mask, measurement, max_iters, init_iters, eps_stop, bt_factor,
+ * bt_max_trials, L0, L0_dual and power_iters.
+ * ------------------------------------------------------------------------ */
+typedef struct cnlos_batch cnlos_batch;   /* opaque */
+
+/* Device bytes for a batch of `count` problems shaped like cfg: count equal
+ * slices of cnlos_workspace_bytes(cfg) each. */
+cnlos_status cnlos_batch_workspace_bytes(const cnlos_config* cfg, int32_t count, uint64_t* bytes);
+
+/* Create `count` member problems from cfgs[count] and masks_host[count]
+ * (host [nx][ny] arrays) in one caller-owned workspace (256-byte aligned),
+ * each built as cnlos_create builds one (H^ and step constants per member).
+ * All work goes to hip_stream.  EINVAL if the members disagree on a field
+ * that must match.  On error after the handle exists, *out is set and must
+ * be destroyed. */
+cnlos_status cnlos_batch_create(const cnlos_config* cfgs, int32_t count,
+                                const uint8_t* const* masks_host, void* workspace_dev,
+                                uint64_t workspace_bytes, void* hip_stream, cnlos_batch** out);
+
+/* Member i as a problem handle (owned by the batch: do not destroy it).  It
+ * accepts every problem call: set_measurement, apply_A/AT, get/set field,
+ * info, log, reset, and cnlos_run, which runs that member alone. */
+cnlos_status cnlos_batch_member(cnlos_batch* b, int32_t i, cnlos_problem** out);
+
+/* Run every member (iters > 0: that many more iterations each; else each
+ * member's configured count).  Members that stop early or fail drop out while
+ * the others continue; reports[count] (nullable) receive each member's
+ * report with its own status.  Returns the first member error, else OK.
+ * Every member needs a measurement.  Synchronizes the stream. */
+cnlos_status cnlos_batch_run(cnlos_batch* b, int32_t iters, cnlos_report* reports);
+
+/* Run several batches at once, each on its own stream (the stream given at
+ * its creation): every round enqueues work for all of them before waiting,
+ * so batches of different shapes overlap on the device.  reports holds one
+ * array per batch (the array, or an entry, may be NULL). */
+cnlos_status cnlos_batch_run_many(cnlos_batch* const* batches, int32_t count, int32_t iters,
+                                  cnlos_report* const* reports);
+
+/* Release the batch and its members (the workspace stays the caller's). */
+cnlos_status cnlos_batch_destroy(cnlos_batch* b);
 
 #ifdef __cplusplus
 }

@@ -49,7 +49,8 @@ class Config(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("iters_done", c_int32), ("total_iters", c_int32), ("stopped_early", c_int32),
                 ("bt_rejects", c_int32), ("L_final", c_double), ("energy", c_double),
-                ("primal_res", c_double), ("dual_res", c_double)]
+                ("primal_res", c_double), ("dual_res", c_double), ("status", c_int32),
+                ("reserved", c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -100,6 +101,13 @@ def load() -> ctypes.CDLL:
         "cnlos_profile_enable": ([P, ctypes.c_uint32], c_int32),
         "cnlos_profile_read": ([P, POINTER(c_double), POINTER(ctypes.c_int64), c_int32], c_int32),
         "cnlos_destroy": ([P], c_int32),
+        "cnlos_batch_workspace_bytes": ([POINTER(Config), c_int32, POINTER(c_uint64)], c_int32),
+        "cnlos_batch_create": ([POINTER(Config), c_int32, POINTER(POINTER(c_uint8)), P, c_uint64, P,
+                                POINTER(P)], c_int32),
+        "cnlos_batch_member": ([P, c_int32, POINTER(P)], c_int32),
+        "cnlos_batch_run": ([P, c_int32, POINTER(Report)], c_int32),
+        "cnlos_batch_run_many": ([POINTER(P), c_int32, c_int32, POINTER(POINTER(Report))], c_int32),
+        "cnlos_batch_destroy": ([P], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -157,9 +165,21 @@ def _dev_f32(t, shape, device):
 class Problem:
     """One reconstruction problem in a device workspace owned by this object."""
 
-    def __init__(self, cfg: Config, mask, device=None, stream=None, workspace=None):
+    def __init__(self, cfg: Config, mask, device=None, stream=None, workspace=None, _member=None):
         import torch
         self._lib = load()
+        self._owned = _member is None
+        if _member is not None:           # a batch member: the batch owns handle and memory
+            h, owner = _member
+            self.cfg = cfg
+            self.device = owner.device
+            self.shape = (cfg.nx, cfg.ny, cfg.nt)
+            self.workspace = owner.workspace
+            self.stream = owner.stream
+            self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+            self._owner = owner
+            self._h = h
+            return
         self.cfg = cfg
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
@@ -189,7 +209,8 @@ class Problem:
 
     # -- lifetime
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value is not None:
+        if (getattr(self, "_owned", False) and getattr(self, "_h", None) is not None
+                and self._h.value is not None):
             self._lib.cnlos_destroy(self._h)
         self._h = None
 
@@ -291,3 +312,83 @@ class Problem:
         n = c_int32()
         check(self._lib.cnlos_get_log(self._h, buf.ctypes.data_as(POINTER(c_double)), cap, byref(n)))
         return buf[: n.value].copy()
+
+
+def _report_dict(rep):
+    return {f: getattr(rep, f) for f, _ in Report._fields_}
+
+
+class Batch:
+    """Problems of one shape and one set of solver parameters that advance
+    together: every kernel of an iteration is one launch for all members."""
+
+    def __init__(self, cfgs, masks, device=None, stream=None):
+        import torch
+        self._lib = load()
+        self._h = None
+        cfgs = list(cfgs)
+        if len(cfgs) != len(masks) or not cfgs:
+            raise ValueError("need one mask per config")
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = len(cfgs)
+        arr = (Config * n)(*cfgs)
+        nbytes = c_uint64()
+        check(self._lib.cnlos_batch_workspace_bytes(arr, n, byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._masks = [np.ascontiguousarray(m, dtype=np.uint8) for m in masks]
+        for c, m in zip(cfgs, self._masks):
+            if m.shape != (c.nx, c.ny):
+                raise ValueError(f"mask must be {(c.nx, c.ny)}")
+        mp = (POINTER(c_uint8) * n)(*[m.ctypes.data_as(POINTER(c_uint8)) for m in self._masks])
+        h = c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._lib.cnlos_batch_create(arr, n, mp, c_void_p(self.workspace.data_ptr()),
+                                              nbytes, c_void_p(self.stream.cuda_stream), byref(h))
+        self._h = h
+        if st != OK:
+            msg = last_error()
+            self.close()
+            raise CnlosError(st, msg)
+        self.members = []
+        for i in range(n):
+            mh = c_void_p()
+            check(self._lib.cnlos_batch_member(self._h, i, byref(mh)))
+            self.members.append(Problem(cfgs[i], self._masks[i], _member=(mh, self)))
+
+    def __len__(self):
+        return len(self.members)
+
+    def run(self, iters=0):
+        """Advance every member; returns (status, [report dict per member])."""
+        n = len(self.members)
+        reps = (Report * n)()
+        st = self._lib.cnlos_batch_run(self._h, int(iters), reps)
+        return st, [_report_dict(r) for r in reps]
+
+    def close(self):
+        if self._h is not None and self._h.value is not None:
+            for m in getattr(self, "members", []):
+                m._h = None
+            self._lib.cnlos_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run_many(batches, iters=0):
+    """Advance several batches at once (each on its own stream, overlapping on
+    the device); returns (status, [[report dict per member] per batch])."""
+    lib = load()
+    k = len(batches)
+    hs = (c_void_p * k)(*[b._h for b in batches])
+    arrs = [(Report * len(b.members))() for b in batches]
+    ptrs = (POINTER(Report) * k)(*[ctypes.cast(a, POINTER(Report)) for a in arrs])
+    st = lib.cnlos_batch_run_many(hs, k, int(iters), ptrs)
+    return st, [[_report_dict(r) for r in a] for a in arrs]

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -47,7 +48,17 @@ struct Carver {
   }
 };
 
+cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
+                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out);
+cnlos_status destroy_problem(cnlos_problem* p);
+
 }  // namespace
+
+struct cnlos_batch {
+  std::vector<cnlos_problem*> mem;
+  size_t stride = 0;
+  hipStream_t st = nullptr;
+};
 
 struct cnlos_problem {
   cnlos_config cfg;
@@ -59,6 +70,8 @@ struct cnlos_problem {
   uint64_t ws_bytes = 0;
   bool poisoned = false;
   bool has_meas = false;
+  bool in_batch = false;      // owned by a cnlos_batch
+  size_t carve_bytes = 0;
   int iter_host = 0;
   DevCtl* ctl = nullptr;
   DevCtl* ctl_host = nullptr;   // pinned mirror
@@ -146,7 +159,7 @@ void Prof::release() {
     pool.push_back(pd.b);
   }
   pending.clear();
-  for (hipEvent_t e : pool) hipEventDestroy(e);
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   pool.clear();
 }
 
@@ -337,10 +350,13 @@ cnlos_status ctl_push(cnlos_problem* p) {
   return CNLOS_OK;
 }
 
+inline Vol fixed(const float* q) { return Vol{{const_cast<float*>(q), nullptr, nullptr}, -1}; }
+
 // One padded convolution of the problem (forward or adjoint).
 hipError_t conv(cnlos_problem* p, const ConvSrc& src, bool adjoint, int epi, const ConvEpi& ep,
                 const DevCtl* ctl) {
-  return launch_conv(p->logn, p->logm, p->tb, src, p->spec, adjoint, epi, ep, ctl, p->st, &p->prof);
+  return launch_conv(p->logn, p->logm, p->tb, src, p->spec, adjoint, epi, ep, ctl, kSingle, p->st,
+                     &p->prof);
 }
 
 // ||B||^2 by power iteration (B = A_D when masked, else A), from the ones vector.
@@ -350,19 +366,25 @@ cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
   HIPCHK(launch_fill(X, p->V, (float)(1.0 / sqrt((double)p->V)), p->st));
   for (int it = 0; it < p->cfg.power_iters; ++it) {
     ConvSrc s1{};
-    s1.a = X;
+    s1.a = fixed(X);
+    s1.b = fixed(nullptr);
     s1.scale_div = it > 0 ? &p->ctl->pow_est : nullptr;
     ConvEpi e1{};
-    e1.out = Y;
+    e1.out = fixed(Y);
+    e1.au = fixed(nullptr);
+    e1.au_prev = fixed(nullptr);
     e1.w = p->wk;
     e1.mask = masked ? p->mask : nullptr;
     HIPCHK(conv(p, s1, false, EPI_PLAIN, e1, nullptr));
     ConvSrc s2{};
-    s2.a = Y;
+    s2.a = fixed(Y);
+    s2.b = fixed(nullptr);
     s2.w = p->wk;
     s2.mask = masked ? p->mask : nullptr;
     ConvEpi e2{};
-    e2.out = X;
+    e2.out = fixed(X);
+    e2.au = fixed(nullptr);
+    e2.au_prev = fixed(nullptr);
     e2.partials = p->partials;
     HIPCHK(conv(p, s2, true, EPI_NORM, e2, nullptr));
     HIPCHK(launch_pow_finalize(p->ctl, p->partials, p->nb_conv, p->st));
@@ -402,138 +424,187 @@ cnlos_status reset_state(cnlos_problem* p) {
   c.bt_rejects = 0;
   c.stage = 1;
   c.log_count = 0;
+  c.target = 0;
+  c.reject = 0;
+  c.stage1_end = p->cfg.model == CNLOS_MODEL_DUAL ? p->cfg.init_iters : 0x7fffffff;
+  c.slot[R_U_CUR] = 0;
+  c.slot[R_U_TR] = 1;
+  c.slot[R_AU_CUR] = 0;
+  c.slot[R_AU_PREV] = 2;
+  c.slot[R_AU_TR] = 1;
+  c.slot[R_T_CUR] = 0;
+  c.slot[R_T_TR] = 1;
+  c.slot_pad = 0;
   p->iter_host = 0;
   return ctl_push(p);
 }
 
-// Enqueue ADMM iteration number k (0-based) assuming iterations 0..k-1 were
-// accepted; buffer roles rotate with k.
-cnlos_status enqueue_iteration(cnlos_problem* p, int k) {
+// Sequences of one iteration slot.  Every kernel carries a phase gate, so a
+// slot may hold sequences that some (or all) scenes skip: a scene runs the
+// Algorithm-1 sequence while in the warm start (or the object model), the
+// hand-over once its warm start is done, and the Algorithm-2 sequence after.
+enum SlotSeq : int { SEQ_S1 = 1, SEQ_TR = 2, SEQ_S2 = 4 };
+
+
+// Enqueue one iteration slot for the scenes of `bt` (p: the first scene; the
+// others follow at the workspace stride).
+cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
   const cnlos_config& c = p->cfg;
   const int ln = p->logn, lm = p->logm;
-  const bool dual_model = c.model == CNLOS_MODEL_DUAL;
-  const int stage = (dual_model && k >= c.init_iters) ? 2 : 1;
-  float* u_cur = p->U[k & 1];
-  float* u_tr = p->U[(k + 1) & 1];
-  float* au_cur = p->AU[k % 3];
-  float* au_prev = p->AU[(k + 2) % 3];
-  float* au_tr = p->AU[(k + 1) % 3];
   DevCtl* ctl = p->ctl;
   const size_t V = p->V;
+  auto gated = [&](int g) {
+    Batch b = bt;
+    b.gate = g;
+    return b;
+  };
+  auto role = [&](int r) {
+    Vol v{{nullptr, nullptr, nullptr}, r};
+    if (r == R_U_CUR || r == R_U_TR) {
+      v.p[0] = p->U[0];
+      v.p[1] = p->U[1];
+    } else if (r == R_T_CUR || r == R_T_TR) {
+      v.p[0] = p->T[0];
+      v.p[1] = p->T[1];
+    } else {
+      v.p[0] = p->AU[0];
+      v.p[1] = p->AU[1];
+      v.p[2] = p->AU[2];
+    }
+    return v;
+  };
 
-  if (stage == 2 && k == c.init_iters) {
-    const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
-    float* zf[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3, p->w, p->lam2, p->lam};
-    size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V, 3 * V};
-    TIMED(KK_OTHER, launch_transition(ln, lm, ctl, u_cur, p->ubar, p->phi, pu, p->phi_tau, phi_at_zero(pt),
-                             zf, zc, 8, p->st));
-  }
-
-  if (stage == 1) {
+  if (seqs & SEQ_S1) {
     const double mu = c.mu;
-    TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, p->st));
+    const int G = G_STAGE1;
+    TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, gated(G | G_FIRST), p->st));
     ConvSrc sa{};
-    sa.a = au_cur;
-    sa.b = au_prev;
+    sa.a = role(R_AU_CUR);
+    sa.b = role(R_AU_PREV);
     sa.c = p->tau0;
     sa.w = p->wk;
     sa.mask = p->mask;
     sa.lincache = 1;
     ConvEpi ea{};
-    ea.out = p->gf;
-    HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
-    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, p->st));
+    ea.out = fixed(p->gf);
+    ea.au = fixed(nullptr);
+    ea.au_prev = fixed(nullptr);
+    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
+    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, gated(G), p->st));
     SolveEpi se{};
-    se.out = u_tr;
+    se.out = role(R_U_TR);
     se.ref = p->ubar;
     se.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, p->st, &p->prof));
+    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, gated(G), p->st,
+                        &p->prof));
     ConvSrc sf{};
-    sf.a = u_tr;
+    sf.a = role(R_U_TR);
+    sf.b = fixed(nullptr);
     ConvEpi ef{};
-    ef.out = au_tr;
+    ef.out = role(R_AU_TR);
     ef.w = p->wk;
     ef.mask = p->mask;
-    ef.au = au_cur;
-    ef.au_prev = au_prev;
+    ef.au = role(R_AU_CUR);
+    ef.au_prev = role(R_AU_PREV);
     ef.tau0 = p->tau0;
     ef.partials = p->partials;
-    HIPCHK(conv(p, sf, false, EPI_FWD_OBJ, ef, ctl));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0, p->st));
-    const PhiArgs pa = phi_args(p, 1, false);
-    TIMED(KK_POST_U, launch_post(ln, lm, false, u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, mu, pa, nullptr,
-                       nullptr, 0.0, nullptr, nullptr, nullptr, p->partials, ctl, p->st));
+    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_OBJ, ef, ctl, gated(G), p->st, &p->prof));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
+                                   gated(G), p->st));
+    const PostArgs pa{role(R_U_TR), role(R_U_CUR), p->v, p->lam, p->ubar, p->phi, (float)mu,
+                      phi_args(p, 1, false)};
+    TIMED(KK_POST_U, launch_post(ln, lm, pa, p->partials, ctl, gated(G | G_AFTER_CHECK), p->st));
     // the data term of the energy comes from the forward pass (SL_DATA)
-    TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu, p->st));
-    return CNLOS_OK;
+    TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu,
+                                      gated(G | G_AFTER_CHECK), p->st));
+  }
+  if (c.model != CNLOS_MODEL_DUAL) return CNLOS_OK;
+
+  if (seqs & SEQ_TR) {
+    const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
+    float* zf[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3, p->w, p->lam2, p->lam};
+    size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V, 3 * V};
+    TIMED(KK_OTHER, launch_transition(ln, lm, ctl, role(R_U_CUR), p->ubar, p->phi, pu, p->phi_tau,
+                                      phi_at_zero(pt), zf,
+                                      zc, 8, bt, p->st));
   }
 
-  // Algorithm 2
-  const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
-  float* tau_cur = p->T[k & 1];
-  float* tau_tr = p->T[(k + 1) & 1];
-  TIMED(KK_VSTEP, launch_pre_dual(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, p->taubar, p->lam2,
-                                  p->phi_tau, p->w, mu2, p->lam3, p->tau0, p->mask, p->f, lam, mu3,
-                                  ctl, p->st));
-  ConvSrc sa{};
-  sa.a = au_cur;
-  sa.b = au_prev;
-  sa.c = p->taubar;
-  sa.w = p->wk;
-  sa.lincache = 1;
-  ConvEpi ea{};
-  ea.out = p->gf;
-  HIPCHK(conv(p, sa, true, EPI_PLAIN, ea, ctl));
-  TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, p->st));
-  SolveEpi se{};
-  se.out = u_tr;
-  se.ref = p->ubar;
-  se.partials = p->partials;
-  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, p->st, &p->prof));
-  ConvSrc sf{};
-  sf.a = u_tr;
-  ConvEpi ef{};
-  ef.out = au_tr;
-  ef.w = p->wk;
-  ef.au = au_cur;
-  ef.au_prev = au_prev;
-  ef.partials = p->partials;
-  HIPCHK(conv(p, sf, false, EPI_FWD_DUAL, ef, ctl));
-  TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0, p->st));
-  TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, au_tr, p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3, ctl, p->st));
-  SolveEpi st2{};
-  st2.out = tau_tr;
-  st2.partials = p->partials;
-  HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, p->st,
-                      &p->prof));
-  const PostArgs pu{u_tr, u_cur, p->v, p->lam, p->ubar, p->phi, (float)mu1, phi_args(p, 2, false)};
-  const PostArgs pt{tau_tr, tau_cur, p->w, p->lam2, p->taubar, p->phi_tau, (float)mu2,
-                    phi_args(p, 2, true)};
-  TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->f, p->lam3, mu3, au_tr, p->tau0, p->mask,
-                                    p->partials, ctl, p->st));
-  TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1, p->st));
+  if (seqs & SEQ_S2) {
+    // Algorithm 2
+    const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
+    const int G = G_STAGE2;
+    TIMED(KK_VSTEP, launch_pre_dual(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, p->taubar, p->lam2,
+                                    p->phi_tau, p->w, mu2, p->lam3, p->tau0, p->mask, p->f, lam, mu3,
+                                    ctl, gated(G | G_FIRST), p->st));
+    ConvSrc sa{};
+    sa.a = role(R_AU_CUR);
+    sa.b = role(R_AU_PREV);
+    sa.c = p->taubar;
+    sa.w = p->wk;
+    sa.lincache = 1;
+    ConvEpi ea{};
+    ea.out = fixed(p->gf);
+    ea.au = fixed(nullptr);
+    ea.au_prev = fixed(nullptr);
+    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
+    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, gated(G), p->st));
+    SolveEpi se{};
+    se.out = role(R_U_TR);
+    se.ref = p->ubar;
+    se.partials = p->partials;
+    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, gated(G), p->st,
+                        &p->prof));
+    ConvSrc sf{};
+    sf.a = role(R_U_TR);
+    sf.b = fixed(nullptr);
+    ConvEpi ef{};
+    ef.out = role(R_AU_TR);
+    ef.w = p->wk;
+    ef.au = role(R_AU_CUR);
+    ef.au_prev = role(R_AU_PREV);
+    ef.partials = p->partials;
+    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st, &p->prof));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
+                                   gated(G), p->st));
+    const int GA = G | G_AFTER_CHECK;
+    TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, role(R_AU_TR), p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3,
+                                     ctl, gated(GA), p->st));
+    SolveEpi st2{};
+    st2.out = role(R_T_TR);
+    st2.partials = p->partials;
+    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, gated(GA),
+                        p->st, &p->prof));
+    const PostArgs pu{role(R_U_TR), role(R_U_CUR), p->v, p->lam, p->ubar, p->phi, (float)mu1,
+                      phi_args(p, 2, false)};
+    const PostArgs pt{role(R_T_TR), role(R_T_CUR), p->w, p->lam2, p->taubar, p->phi_tau, (float)mu2,
+                      phi_args(p, 2, true)};
+    TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->f, p->lam3, mu3, role(R_AU_TR), p->tau0, p->mask,
+                                      p->partials, ctl, gated(GA), p->st));
+    TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1,
+                                      gated(GA), p->st));
+  }
   return CNLOS_OK;
 }
 
 float* field_ptr(cnlos_problem* p, int field, size_t* count) {
   const size_t V = p->V;
-  const int k = p->iter_host;
+  const DevCtl& h = *p->ctl_host;
   const bool dual = p->cfg.model == CNLOS_MODEL_DUAL;
   *count = V;
   switch (field) {
-    case CNLOS_FIELD_U: return p->U[k & 1];
+    case CNLOS_FIELD_U: return p->U[h.slot[R_U_CUR]];
     case CNLOS_FIELD_UBAR: return p->ubar;
     case CNLOS_FIELD_V: *count = 3 * V; return p->v;
     case CNLOS_FIELD_LAM: *count = 3 * V; return p->lam;
     case CNLOS_FIELD_PHI: return p->phi;
-    case CNLOS_FIELD_AU: return p->AU[k % 3];
-    case CNLOS_FIELD_AU_PREV: return p->AU[(k + 2) % 3];
+    case CNLOS_FIELD_AU: return p->AU[h.slot[R_AU_CUR]];
+    case CNLOS_FIELD_AU_PREV: return p->AU[h.slot[R_AU_PREV]];
     case CNLOS_FIELD_TAU0: return p->tau0;
     default: break;
   }
   if (!dual) return nullptr;
   switch (field) {
-    case CNLOS_FIELD_TAU: return p->T[k & 1];
+    case CNLOS_FIELD_TAU: return p->T[h.slot[R_T_CUR]];
     case CNLOS_FIELD_TAUBAR: return p->taubar;
     case CNLOS_FIELD_W: *count = 3 * V; return p->w;
     case CNLOS_FIELD_LAM2: *count = 3 * V; return p->lam2;
@@ -542,6 +613,179 @@ float* field_ptr(cnlos_problem* p, int field, size_t* count) {
     case CNLOS_FIELD_PHI_TAU: return p->phi_tau;
     default: return nullptr;
   }
+}
+
+// A group of scenes advanced by the same launches (one scene, or a batch at
+// a workspace stride), on the stream of its first scene.
+struct Group {
+  cnlos_problem* lead = nullptr;
+  std::vector<cnlos_problem*> mem;
+  Batch bt = kSingle;
+};
+
+struct SceneRun {
+  int start = 0, goal = 0, rejects0 = 0;
+  bool active = false, stopped = false;
+  cnlos_status status = CNLOS_OK;
+};
+
+// pull every member's controller with one stream synchronization
+cnlos_status group_pull(Group& g) {
+  cnlos_problem* p = g.lead;
+  for (cnlos_problem* m : g.mem)
+    HIPCHK(hipMemcpyAsync(m->ctl_host, m->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  p->prof.harvest();
+  return CNLOS_OK;
+}
+
+cnlos_status group_push(Group& g) {
+  cnlos_problem* p = g.lead;
+  for (cnlos_problem* m : g.mem)
+    HIPCHK(hipMemcpyAsync(m->ctl, m->ctl_host, sizeof(DevCtl), hipMemcpyHostToDevice, p->st));
+  HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+// Run every scene of every group to its goal (iters > 0: that many more
+// iterations; else the configured count).  Groups run on their own streams:
+// each round enqueues a batch of iteration slots on every group before it
+// waits for any, so the groups' work overlaps on the device.
+cnlos_status run_groups(std::vector<Group>& gs, int32_t iters, std::vector<cnlos_report*>* reps) {
+  std::vector<std::vector<SceneRun>> runs(gs.size());
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    Group& g = gs[gi];
+    cnlos_status s = group_pull(g);
+    if (s != CNLOS_OK) return s;
+    runs[gi].resize(g.mem.size());
+    for (size_t i = 0; i < g.mem.size(); ++i) {
+      cnlos_problem* m = g.mem[i];
+      const cnlos_config& c = m->cfg;
+      DevCtl& h = *m->ctl_host;
+      SceneRun& r = runs[gi][i];
+      const int planned = c.max_iters + (c.model == CNLOS_MODEL_DUAL ? c.init_iters : 0);
+      r.start = h.iter;
+      r.goal = iters > 0 ? h.iter + iters : planned;
+      r.rejects0 = h.bt_rejects;
+      r.active = h.iter < r.goal;
+      h.target = r.goal;
+      h.reject = 0;
+      h.halt = 0;
+      h.reason = HR_NONE;
+      h.trials = 0;
+    }
+    s = group_push(g);
+    if (s != CNLOS_OK) return s;
+  }
+  int batch = 2;
+  for (;;) {
+    bool any = false;
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+      Group& g = gs[gi];
+      cnlos_problem* p = g.lead;
+      // the slots' sequences from the members' last known iteration counts
+      int lo1 = 0x7fffffff, need = 0;
+      bool s1 = false, s2 = false;
+      int to_s1end = 0x7fffffff;
+      for (size_t i = 0; i < g.mem.size(); ++i) {
+        if (!runs[gi][i].active) continue;
+        const DevCtl& h = *g.mem[i]->ctl_host;
+        need = std::max(need, runs[gi][i].goal - h.iter);
+        if (h.stage == 1 && h.iter < h.stage1_end) {
+          s1 = true;
+          lo1 = std::min(lo1, h.iter);
+          to_s1end = std::min(to_s1end, h.stage1_end - h.iter);
+        } else {
+          s2 = true;
+        }
+      }
+      if (need <= 0) continue;
+      any = true;
+      int nb = std::min(batch, need);
+      // a warm-start batch ends where the first scene reaches the hand-over
+      if (s1 && !s2) nb = std::min(nb, to_s1end);
+      for (int j = 0; j < nb; ++j) {
+        int seq = 0;
+        for (size_t i = 0; i < g.mem.size(); ++i) {
+          if (!runs[gi][i].active) continue;
+          const DevCtl& h = *g.mem[i]->ctl_host;
+          if (h.stage == 1 && h.iter < h.stage1_end) {
+            seq |= SEQ_S1;
+            if (p->cfg.model == CNLOS_MODEL_DUAL && h.iter + j + 1 >= h.stage1_end) seq |= SEQ_TR | SEQ_S2;
+          } else if (h.stage == 1) {
+            seq |= SEQ_TR | SEQ_S2;       // warm start done, hand-over pending
+          } else {
+            seq |= SEQ_S2;
+          }
+        }
+        (void)lo1;
+        cnlos_status s = enqueue_slot(p, g.bt, seq);
+        if (s != CNLOS_OK) return s;
+      }
+    }
+    if (!any) break;
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+      Group& g = gs[gi];
+      bool act = false;
+      for (const SceneRun& r : runs[gi]) act = act || r.active;
+      if (!act) continue;
+      cnlos_status s = group_pull(g);
+      if (s != CNLOS_OK) return s;
+      bool dirty = false;
+      for (size_t i = 0; i < g.mem.size(); ++i) {
+        SceneRun& r = runs[gi][i];
+        if (!r.active) continue;
+        cnlos_problem* m = g.mem[i];
+        DevCtl& h = *m->ctl_host;
+        m->iter_host = h.iter;
+        if (h.halt) {
+          const int reason = h.reason;
+          h.halt = 0;
+          h.reason = HR_NONE;
+          h.trials = 0;
+          dirty = true;
+          r.active = false;
+          if (reason == HR_STOP) {
+            r.stopped = true;
+          } else if (reason == HR_BACKTRACK) {
+            r.status = fail(CNLOS_EBACKTRACK, "backtracking found no acceptable step");
+          } else {
+            r.status = fail(CNLOS_ENONFINITE, "non-finite residual or energy");
+          }
+        } else if (h.iter >= r.goal) {
+          r.active = false;
+        }
+      }
+      if (dirty) {
+        s = group_push(g);
+        if (s != CNLOS_OK) return s;
+      }
+    }
+    if (batch < 64) batch *= 2;
+  }
+  cnlos_status result = CNLOS_OK;
+  size_t flat = 0;
+  for (size_t gi = 0; gi < gs.size(); ++gi)
+    for (size_t i = 0; i < gs[gi].mem.size(); ++i, ++flat) {
+      const SceneRun& r = runs[gi][i];
+      cnlos_problem* m = gs[gi].mem[i];
+      const DevCtl& h = *m->ctl_host;
+      m->iter_host = h.iter;
+      if (result == CNLOS_OK && r.status != CNLOS_OK) result = r.status;
+      cnlos_report* out = (reps && flat < reps->size()) ? (*reps)[flat] : nullptr;
+      if (!out) continue;
+      out->iters_done = h.iter - r.start;
+      out->total_iters = h.iter;
+      out->stopped_early = r.stopped ? 1 : 0;
+      out->bt_rejects = h.bt_rejects - r.rejects0;
+      out->L_final = h.L;
+      out->energy = h.last_energy;
+      out->primal_res = h.last_primal;
+      out->dual_res = h.last_dual;
+      out->status = r.status;
+      out->reserved = 0;
+    }
+  return result;
 }
 
 #define CHECK_HANDLE(p)                                                      \
@@ -622,6 +866,15 @@ cnlos_status cnlos_workspace_bytes(const cnlos_config* cfg, uint64_t* bytes) {
 
 cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
                           uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
+  return create_into(cfg, mask_host, workspace_dev, workspace_bytes, hip_stream, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
+                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
   if (!out) return fail(CNLOS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
@@ -644,7 +897,7 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
   p->st = (hipStream_t)hip_stream;
   p->ws = (uint8_t*)workspace_dev;
   p->ws_bytes = workspace_bytes;
-  carve(p, *cfg, p->ws);
+  p->carve_bytes = carve(p, *cfg, p->ws);
   p->nb_conv = conv_blocks(p->logn, p->logm);
   p->nb_solve = solve_blocks(p->logn, p->logm);
   p->nb_sten = stencil_blocks(p->logn, p->logm);
@@ -827,6 +1080,10 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
   return reset_state(p);
 }
 
+}  // namespace
+
+extern "C" {
+
 cnlos_status cnlos_set_measurement(cnlos_problem* p, const float* tau0_dev) {
   CHECK_HANDLE(p);
   CHECK_SOLVER(p);
@@ -852,9 +1109,12 @@ cnlos_status cnlos_apply_A(cnlos_problem* p, const float* u_dev, float* tau_dev,
   if (!u_dev || !tau_dev) return fail(CNLOS_EINVAL, "NULL volume");
   if ((const void*)u_dev == (const void*)tau_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
   ConvSrc s{};
-  s.a = u_dev;
+  s.a = fixed(u_dev);
+  s.b = fixed(nullptr);
   ConvEpi e{};
-  e.out = tau_dev;
+  e.out = fixed(tau_dev);
+  e.au = fixed(nullptr);
+  e.au_prev = fixed(nullptr);
   e.w = p->wk;
   e.mask = masked ? p->mask : nullptr;
   HIPCHK(conv(p, s, false, EPI_PLAIN, e, nullptr));
@@ -866,11 +1126,14 @@ cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev
   if (!u_dev || !tau_dev) return fail(CNLOS_EINVAL, "NULL volume");
   if ((const void*)u_dev == (const void*)tau_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
   ConvSrc s{};
-  s.a = tau_dev;
+  s.a = fixed(tau_dev);
+  s.b = fixed(nullptr);
   s.w = p->wk;
   s.mask = masked ? p->mask : nullptr;
   ConvEpi e{};
-  e.out = u_dev;
+  e.out = fixed(u_dev);
+  e.au = fixed(nullptr);
+  e.au_prev = fixed(nullptr);
   HIPCHK(conv(p, s, true, EPI_PLAIN, e, nullptr));
   return CNLOS_OK;
 }
@@ -879,59 +1142,12 @@ cnlos_status cnlos_run(cnlos_problem* p, int32_t iters, cnlos_report* out) {
   CHECK_HANDLE(p);
   CHECK_SOLVER(p);
   if (!p->has_meas) return fail(CNLOS_ESTATE, "no measurement set");
-  const cnlos_config& c = p->cfg;
-  const int planned = c.max_iters + (c.model == CNLOS_MODEL_DUAL ? c.init_iters : 0);
-  const int start = p->iter_host;
-  const int goal = iters > 0 ? start + iters : planned;
-  cnlos_status s = ctl_pull(p);
-  if (s != CNLOS_OK) return s;
-  const int rejects0 = p->ctl_host->bt_rejects;
-  int batch = 2;
-  bool stopped = false;
-  cnlos_status result = CNLOS_OK;
-  while (p->iter_host < goal) {
-    const int nb = batch < goal - p->iter_host ? batch : goal - p->iter_host;
-    for (int k = p->iter_host; k < p->iter_host + nb; ++k) {
-      s = enqueue_iteration(p, k);
-      if (s != CNLOS_OK) return s;
-    }
-    s = ctl_pull(p);
-    if (s != CNLOS_OK) return s;
-    DevCtl& h = *p->ctl_host;
-    p->iter_host = h.iter;
-    if (h.halt) {
-      const int reason = h.reason;
-      h.halt = 0;
-      h.reason = HR_NONE;
-      if (reason == HR_BACKTRACK || reason == HR_NONFINITE) h.trials = 0;
-      s = ctl_push(p);
-      if (s != CNLOS_OK) return s;
-      if (reason == HR_REJECT) continue;
-      if (reason == HR_STOP) {
-        stopped = true;
-        break;
-      }
-      if (reason == HR_BACKTRACK) {
-        result = fail(CNLOS_EBACKTRACK, "backtracking found no acceptable step");
-        break;
-      }
-      result = fail(CNLOS_ENONFINITE, "non-finite residual or energy");
-      break;
-    }
-    if (batch < 64) batch *= 2;
-  }
-  if (out) {
-    const DevCtl& h = *p->ctl_host;
-    out->iters_done = p->iter_host - start;
-    out->total_iters = p->iter_host;
-    out->stopped_early = stopped ? 1 : 0;
-    out->bt_rejects = h.bt_rejects - rejects0;
-    out->L_final = h.L;
-    out->energy = h.last_energy;
-    out->primal_res = h.last_primal;
-    out->dual_res = h.last_dual;
-  }
-  return result;
+  std::vector<Group> gs(1);
+  gs[0].lead = p;
+  gs[0].mem.push_back(p);
+  gs[0].bt = kSingle;
+  std::vector<cnlos_report*> reps{out};
+  return run_groups(gs, iters, &reps);
 }
 
 cnlos_status cnlos_reset(cnlos_problem* p) {
@@ -952,6 +1168,8 @@ cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev) {
   CHECK_HANDLE(p);
   CHECK_SOLVER(p);
   if (!dst_dev) return fail(CNLOS_EINVAL, "destination is NULL");
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
   size_t n = 0;
   float* src = field_ptr(p, field, &n);
   if (!src) return fail(CNLOS_EINVAL, "field not available for this model");
@@ -964,6 +1182,8 @@ cnlos_status cnlos_set_field(cnlos_problem* p, int32_t field, const float* src_d
   CHECK_SOLVER(p);
   if (!src_dev) return fail(CNLOS_EINVAL, "source is NULL");
   if (field == CNLOS_FIELD_TAU0) return fail(CNLOS_EINVAL, "the measurement is set by cnlos_set_measurement");
+  cnlos_status s = ctl_pull(p);
+  if (s != CNLOS_OK) return s;
   size_t n = 0;
   float* dst = field_ptr(p, field, &n);
   if (!dst) return fail(CNLOS_EINVAL, "field not available for this model");
@@ -1060,13 +1280,130 @@ cnlos_status cnlos_profile_read(cnlos_problem* p, double* ms, int64_t* launches,
 
 cnlos_status cnlos_destroy(cnlos_problem* p) {
   if (!p) return CNLOS_OK;
+  if (p->in_batch) return fail(CNLOS_EINVAL, "a batch member is released with its batch");
+  return destroy_problem(p);
+}
+
+// ---------------------------------------------------------------- batches
+cnlos_status cnlos_batch_workspace_bytes(const cnlos_config* cfg, int32_t count, uint64_t* bytes) {
+  if (!bytes) return fail(CNLOS_EINVAL, "bytes is NULL");
+  if (count < 1) return fail(CNLOS_EINVAL, "count must be >= 1");
+  cnlos_status s = validate_cfg(cfg);
+  if (s != CNLOS_OK) return s;
+  if (cfg->model == CNLOS_MODEL_OPERATOR) return fail(CNLOS_EINVAL, "a batch needs a solver model");
+  *bytes = (uint64_t)carve(nullptr, *cfg, nullptr) * (uint64_t)count;
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_batch_create(const cnlos_config* cfgs, int32_t count,
+                                const uint8_t* const* masks_host, void* workspace_dev,
+                                uint64_t workspace_bytes, void* hip_stream, cnlos_batch** out) {
+  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || !masks_host) return fail(CNLOS_EINVAL, "configs or masks are NULL");
+  if (count < 1) return fail(CNLOS_EINVAL, "count must be >= 1");
+  const cnlos_config& a = cfgs[0];
+  for (int i = 0; i < count; ++i) {
+    cnlos_status s = cnlos_validate(&cfgs[i], masks_host[i]);
+    if (s != CNLOS_OK) return s;
+    if (!masks_host[i]) return fail(CNLOS_EINVAL, "mask is NULL");
+    const cnlos_config& b = cfgs[i];
+    const bool same = b.nx == a.nx && b.ny == a.ny && b.nt == a.nt && b.model == a.model &&
+                      b.phi == a.phi && b.falloff == a.falloff && b.a_u == a.a_u && b.b_u == a.b_u &&
+                      b.a_tau == a.a_tau && b.b_tau == a.b_tau && b.warm_a == a.warm_a &&
+                      b.warm_b == a.warm_b && b.mu == a.mu && b.mu1 == a.mu1 && b.mu2 == a.mu2 &&
+                      b.mu3 == a.mu3 && b.lambda == a.lambda && b.eta_curv == a.eta_curv &&
+                      b.backtracking == a.backtracking;
+    if (!same) return fail(CNLOS_EINVAL, "batch member " + std::to_string(i) + " differs in a shared field");
+  }
+  if (a.model == CNLOS_MODEL_OPERATOR) return fail(CNLOS_EINVAL, "a batch needs a solver model");
+  const size_t stride = carve(nullptr, a, nullptr);
+  if (!workspace_dev) return fail(CNLOS_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace_dev) % kAlign) return fail(CNLOS_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < stride * (uint64_t)count)
+    return fail(CNLOS_EINVAL, "workspace too small: need " + std::to_string(stride * (uint64_t)count) + " bytes");
+  cnlos_batch* b = new (std::nothrow) cnlos_batch();
+  if (!b) return fail(CNLOS_ENOMEM, "host allocation failed");
+  b->stride = stride;
+  b->st = (hipStream_t)hip_stream;
+  *out = b;
+  for (int i = 0; i < count; ++i) {
+    cnlos_problem* m = nullptr;
+    cnlos_status s = create_into(&cfgs[i], masks_host[i], (uint8_t*)workspace_dev + stride * i, stride,
+                                 hip_stream, &m);
+    if (m) {
+      m->in_batch = true;
+      b->mem.push_back(m);
+    }
+    if (s != CNLOS_OK) return s;
+  }
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_batch_member(cnlos_batch* b, int32_t i, cnlos_problem** out) {
+  if (!b || !out) return fail(CNLOS_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int32_t)b->mem.size()) return fail(CNLOS_EINVAL, "member index out of range");
+  *out = b->mem[i];
+  return CNLOS_OK;
+}
+
+static cnlos_status batch_group(cnlos_batch* b, Group* g) {
+  if (!b || b->mem.empty()) return fail(CNLOS_EINVAL, "empty batch");
+  for (cnlos_problem* m : b->mem) {
+    if (m->poisoned) return fail(CNLOS_ESTATE, "a member is poisoned by an earlier HIP failure");
+    if (!m->has_meas) return fail(CNLOS_ESTATE, "a member has no measurement");
+  }
+  g->lead = b->mem[0];
+  g->mem = b->mem;
+  g->bt = Batch{(int)b->mem.size(), b->stride, G_NONE};
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_batch_run(cnlos_batch* b, int32_t iters, cnlos_report* reports) {
+  std::vector<Group> gs(1);
+  cnlos_status s = batch_group(b, &gs[0]);
+  if (s != CNLOS_OK) return s;
+  std::vector<cnlos_report*> reps(b->mem.size(), nullptr);
+  if (reports)
+    for (size_t i = 0; i < reps.size(); ++i) reps[i] = reports + i;
+  return run_groups(gs, iters, &reps);
+}
+
+cnlos_status cnlos_batch_run_many(cnlos_batch* const* batches, int32_t count, int32_t iters,
+                                  cnlos_report* const* reports) {
+  if (!batches || count < 1) return fail(CNLOS_EINVAL, "no batches");
+  std::vector<Group> gs(count);
+  std::vector<cnlos_report*> reps;
+  for (int k = 0; k < count; ++k) {
+    cnlos_status s = batch_group(batches[k], &gs[k]);
+    if (s != CNLOS_OK) return s;
+    for (int j = 0; j < k; ++j)
+      if (batches[j] == batches[k]) return fail(CNLOS_EINVAL, "a batch appears twice");
+    cnlos_report* r = reports ? reports[k] : nullptr;
+    for (size_t i = 0; i < batches[k]->mem.size(); ++i) reps.push_back(r ? r + i : nullptr);
+  }
+  return run_groups(gs, iters, &reps);
+}
+
+cnlos_status cnlos_batch_destroy(cnlos_batch* b) {
+  if (!b) return CNLOS_OK;
+  for (cnlos_problem* m : b->mem) destroy_problem(m);
+  delete b;
+  return CNLOS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+cnlos_status destroy_problem(cnlos_problem* p) {
   if (p->ctl_host) {
-    if (!p->poisoned) hipStreamSynchronize(p->st);
-    hipHostFree(p->ctl_host);
+    if (!p->poisoned) (void)hipStreamSynchronize(p->st);
+    (void)hipHostFree(p->ctl_host);
   }
   p->prof.release();
   delete p;
   return CNLOS_OK;
 }
 
-}  // extern "C"
+}  // namespace

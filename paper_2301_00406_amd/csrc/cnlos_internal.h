@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <type_traits>
 #include <vector>
 
 namespace cnlos {
@@ -69,10 +70,34 @@ constexpr int kLogCols = 6;
 
 enum HaltReason : int { HR_NONE = 0, HR_REJECT = 1, HR_STOP = 2, HR_BACKTRACK = 3, HR_NONFINITE = 4 };
 
+// Volumes whose role rotates with the accepted-iteration count.  Each role
+// draws from a small set of buffers (u: 2, A u: 3, tau: 2); the controller
+// keeps which buffer currently plays each role (rotated by the finalize
+// kernel), so a kernel resolves it on the device and scenes at different
+// iteration counts can share one launch.
+enum Role : int {
+  R_U_CUR = 0,    // u^k
+  R_U_TR = 1,     // u^{k+1} trial
+  R_AU_CUR = 2,   // A u^k
+  R_AU_PREV = 3,  // A u^{k-1}
+  R_AU_TR = 4,    // A u^{k+1} trial
+  R_T_CUR = 5,    // tau^k
+  R_T_TR = 6,     // tau^{k+1} trial
+  R_COUNT = 7
+};
+
+// Phase gate of an iteration kernel (bits): which stage it belongs to and
+// whether it comes after the backtracking check of its iteration.
+enum Gate : int { G_NONE = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_AFTER_CHECK = 4, G_FIRST = 8 };
+
 // Scalars shared by the host driver and the kernels, resident in the workspace.
 // Every kernel of the ADMM iteration returns at once while `halt` is set, so a
-// batch of enqueued iterations stops cleanly at a rejected trial or a stop.
+// batch of enqueued iterations stops cleanly at an error or a stop; a rejected
+// trial only sets `reject`, which makes the rest of its iteration slot a no-op,
+// and the next slot retries the iteration with the larger L.
 struct DevCtl {
+  int32_t slot[R_COUNT];   // buffer index per role
+  int32_t slot_pad;
   double L;            // current step constant
   double t;            // FISTA t_k
   double beta;         // extrapolation weight that produced ubar^k
@@ -94,7 +119,49 @@ struct DevCtl {
   double eps_stop;
   double mu_dual;      // mu (object) or mu1 (dual) for the dual residual
   double lambda;
+  int32_t target;      // iteration kernels return once iter >= target
+  int32_t reject;      // the current slot's trial was rejected
+  int32_t stage1_end;  // dual model: iterations of the warm start; object: a large value
+  int32_t reserved_i;
 };
+
+// true when a kernel with phase gate `gate` has nothing to do for this scene
+__device__ __forceinline__ bool gated_off(const DevCtl* c, int gate) {
+  if (c == nullptr) return false;
+  if (c->halt) return true;
+  if (gate == G_NONE) return false;
+  if (c->iter >= c->target) return true;
+  const int stage = c->stage;
+  if ((gate & G_STAGE1) && (stage != 1 || c->iter >= c->stage1_end)) return true;
+  if ((gate & G_STAGE2) && stage != 2) return true;
+  if ((gate & G_AFTER_CHECK) && c->reject) return true;
+  return false;
+}
+
+// A volume operand: the fixed pointer p[0] (role < 0), or the buffer p[slot]
+// that the controller currently assigns to the role.
+struct Vol {
+  float* p[3];
+  int role;
+};
+
+// Scenes of a batch live in equal workspaces at a fixed byte stride; a kernel
+// launched over a batch (grid z = scene) shifts every workspace pointer by
+// blockIdx.z * stride.  Role pointers read from a shifted controller are the
+// scene's own already.
+template <typename T>
+__device__ __forceinline__ T* zsh(T* p, size_t off) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + off) : p;
+}
+
+// the buffer behind v for the scene whose controller is c (zo: its offset)
+__device__ __forceinline__ float* vol_resolve(const Vol& v, const DevCtl* c, size_t zo) {
+  if (v.role < 0) return zsh(v.p[0], zo);
+  const int k = c->slot[v.role];
+  float* q = k == 0 ? v.p[0] : (k == 1 ? v.p[1] : v.p[2]);
+  return zsh(q, zo);
+}
 
 // Sparse resampling table S (depth bin k -> squared-distance bin q) in both
 // orientations; ranges are contiguous so each row/column is (start, count, off).
@@ -110,8 +177,8 @@ struct ResampleTables {
 // with (ca, cb) = (1, 0) or, in the linearity-cache mode, (1 + beta, -beta)
 // with beta read from the controller.  Null pointers drop their factor.
 struct ConvSrc {
-  const float* a;
-  const float* b;
+  Vol a;
+  Vol b;
   const float* c;
   const float* w;
   const uint8_t* mask;
@@ -123,18 +190,18 @@ enum Epi : int { EPI_PLAIN = 0, EPI_FWD_OBJ = 1, EPI_FWD_DUAL = 2, EPI_NORM = 3 
 
 // Epilogue of the t-axis inverse pass of a convolution.
 struct ConvEpi {
-  float* out;              // [n][n][m]
+  Vol out;                 // [n][n][m]
   const float* w;          // per-bin output weight (nullable)
   const uint8_t* mask;     // output mask (EPI_PLAIN) / fidelity mask (EPI_FWD_OBJ)
-  const float* au;         // A u^k       (check)
-  const float* au_prev;    // A u^{k-1}   (check)
+  Vol au;                  // A u^k       (check)
+  Vol au_prev;             // A u^{k-1}   (check)
   const float* tau0;       // data (EPI_FWD_OBJ)
   double* partials;
 };
 
 // Epilogue of the t-axis inverse pass of a diagonal solve.
 struct SolveEpi {
-  float* out;
+  Vol out;
   const float* ref;        // ||out - ref||^2 into SL_STEP when not null
   double* partials;
 };
@@ -152,12 +219,21 @@ struct Tables {
 
 // ---------------------------------------------------------------- launchers
 // All launchers return hipGetLastError() of their launch.
+// Launch geometry of a batch: nz scenes at a workspace stride of zs bytes
+// (nz = 1, zs = 0 for a single problem), and the phase gate of the launch.
+struct Batch {
+  int nz;
+  size_t zs;
+  int gate;
+};
+constexpr Batch kSingle{1, 0, G_NONE};
+
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       hipStream_t st, Prof* prof);
+                       const Batch& bt, hipStream_t st, Prof* prof);
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
                         const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, hipStream_t st, Prof* prof);
+                        const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof);
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
                            const double* cosn, double invZ, hipStream_t st);
 int conv_blocks(int logn, int logm);          // blocks of the convolution t passes
@@ -170,11 +246,11 @@ struct PhiArgs {
   float eta;
 };
 hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
-                        float* v, double mu, const DevCtl* ctl, hipStream_t st);
+                        float* v, double mu, const DevCtl* ctl, const Batch& bt, hipStream_t st);
 // one side (u or tau) of the post-step update
 struct PostArgs {
-  const float* xn;   // x+ (accepted)
-  const float* xo;   // x^k
+  Vol xn;            // x+ (accepted)
+  Vol xo;            // x^k
   const float* v;    // v (u side) or w (tau side)
   float* lam;        // Lambda or Lambda2, updated in place
   float* xbar;       // extrapolated point, written
@@ -186,30 +262,30 @@ hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* l
                            const float* phi, float* v, double mu1, const float* taubar,
                            const float* lam2, const float* phi_tau, float* w, double mu2,
                            const float* lam3, const float* tau0, const uint8_t* mask, float* f,
-                           double lambda, double mu3, const DevCtl* ctl, hipStream_t st);
+                           double lambda, double mu3, const DevCtl* ctl, const Batch& bt,
+                           hipStream_t st);
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
-                            const float* f, float* lam3, double mu3, const float* au,
+                            const float* f, float* lam3, double mu3, Vol au,
                             const float* tau0, const uint8_t* mask, double* partials,
-                            const DevCtl* ctl, hipStream_t st);
+                            const DevCtl* ctl, const Batch& bt, hipStream_t st);
 hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
-                        const float* lam, double mu, const DevCtl* ctl, hipStream_t st);
-hipError_t launch_rhs_tau(int logn, int logm, const float* au, const float* f, const float* lam3,
+                        const float* lam, double mu, const DevCtl* ctl, const Batch& bt,
+                        hipStream_t st);
+hipError_t launch_rhs_tau(int logn, int logm, Vol au, const float* f, const float* lam3,
                           const float* w, const float* lam2, float* rhs, double mu2, double mu3,
-                          const DevCtl* ctl, hipStream_t st);
-hipError_t launch_post(int logn, int logm, bool tau_mode, const float* xnew, const float* xold,
-                       const float* v, float* lam, float* xbar, float* phi, double mu,
-                       const PhiArgs& pa, const float* f, float* lam3, double mu3,
-                       const float* au, const float* tau0, const uint8_t* mask, double* partials,
-                       const DevCtl* ctl, hipStream_t st);
+                          const DevCtl* ctl, const Batch& bt, hipStream_t st);
+hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
+                       const DevCtl* ctl, const Batch& bt, hipStream_t st);
 int stencil_blocks(int logn, int logm);
 hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
-                        hipStream_t st);
+                        const Batch& bt, hipStream_t st);
 hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
-                           int nb_sten, int dual, double lambda, double mu_res, hipStream_t st);
-hipError_t launch_transition(int logn, int logm, DevCtl* ctl, const float* u, float* ubar,
+                           int nb_sten, int dual, double lambda, double mu_res, const Batch& bt,
+                           hipStream_t st);
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, float* ubar,
                              float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
                              float* const* zero_fields, const size_t* zero_counts, int nzero,
-                             hipStream_t st);
+                             const Batch& bt, hipStream_t st);
 hipError_t launch_fill(float* x, size_t n, float val, hipStream_t st);
 hipError_t launch_copy(float* dst, const float* src, size_t n, hipStream_t st);
 hipError_t launch_phi_of_u(int logn, int logm, const float* u, float* phi, const PhiArgs& pa,

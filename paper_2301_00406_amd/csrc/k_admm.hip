@@ -97,10 +97,28 @@ __device__ __forceinline__ void vstep_at(const float* __restrict__ xb, const flo
   v[2 * V + g] = at * s;
 }
 
+// Common head of the iteration kernels: shift the controller to this launch's
+// scene, apply the phase gate, and (first kernel of an iteration slot) clear
+// the previous slot's rejection.
+__device__ __forceinline__ bool iter_head(DevCtl*& ctl, size_t zo, int gate) {
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return false;
+  if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
+  return true;
+}
+__device__ __forceinline__ float* vol_at(const Vol& v, const DevCtl* c, size_t zo) {
+  return vol_resolve(v, c, zo);
+}
+
 __global__ void __launch_bounds__(kStencilThreads)
 k_vstep(const float* __restrict__ ub, const float* __restrict__ lam, const float* __restrict__ phi,
-        float* __restrict__ v, float inv_mu, int logn, int logm, const DevCtl* ctl) {
-  if (ctl->halt) return;
+        float* __restrict__ v, float inv_mu, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  ub = zsh(ub, zo);
+  lam = zsh(lam, zo);
+  phi = zsh(phi, zo);
+  v = zsh(v, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x)
@@ -117,8 +135,21 @@ k_pre_dual(const float* __restrict__ ub, const float* __restrict__ lam,
            const float* __restrict__ phi_tau, float* __restrict__ w, float inv_mu2,
            const float* __restrict__ lam3, const float* __restrict__ tau0,
            const uint8_t* __restrict__ mask, float* __restrict__ f, float lambda, float mu3,
-           int logn, int logm, const DevCtl* ctl) {
-  if (ctl->halt) return;
+           int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  ub = zsh(ub, zo);
+  lam = zsh(lam, zo);
+  phi = zsh(phi, zo);
+  v = zsh(v, zo);
+  taubar = zsh(taubar, zo);
+  lam2 = zsh(lam2, zo);
+  phi_tau = zsh(phi_tau, zo);
+  w = zsh(w, zo);
+  lam3 = zsh(lam3, zo);
+  tau0 = zsh(tau0, zo);
+  mask = zsh(mask, zo);
+  f = zsh(f, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   const float inv_kept = 1.f / (lambda + mu3), inv_mu3 = 1.f / mu3;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
@@ -134,8 +165,14 @@ k_pre_dual(const float* __restrict__ ub, const float* __restrict__ lam,
 // rhs = L ubar - grad f + nabla^*(mu v + Lambda)   (eq. (10)/(11) right-hand side), in place
 __global__ void __launch_bounds__(kStencilThreads)
 k_rhs_u(const float* __restrict__ ub, float* __restrict__ gf_rhs, const float* __restrict__ v,
-        const float* __restrict__ lam, float mu, int logn, int logm, const DevCtl* ctl) {
-  if (ctl->halt) return;
+        const float* __restrict__ lam, float mu, int logn, int logm, DevCtl* ctl, size_t zs,
+        int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  ub = zsh(ub, zo);
+  gf_rhs = zsh(gf_rhs, zo);
+  v = zsh(v, zo);
+  lam = zsh(lam, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   const float L = (float)ctl->L;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
@@ -152,10 +189,17 @@ k_rhs_u(const float* __restrict__ ub, float* __restrict__ gf_rhs, const float* _
 
 // rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem of Algorithm 2)
 __global__ void __launch_bounds__(kStencilThreads)
-k_rhs_tau(const float* __restrict__ au, const float* __restrict__ f, const float* __restrict__ lam3,
+k_rhs_tau(Vol au_v, const float* __restrict__ f, const float* __restrict__ lam3,
           const float* __restrict__ w, const float* __restrict__ lam2, float* __restrict__ rhs,
-          float mu2, float mu3, int logn, int logm, const DevCtl* ctl) {
-  if (ctl->halt) return;
+          float mu2, float mu3, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  const float* __restrict__ au = vol_at(au_v, ctl, zo);
+  f = zsh(f, zo);
+  lam3 = zsh(lam3, zo);
+  w = zsh(w, zo);
+  lam2 = zsh(lam2, zo);
+  rhs = zsh(rhs, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
@@ -216,42 +260,61 @@ __device__ __forceinline__ void post_at(const float* __restrict__ xn, const floa
   }
 }
 
-template <bool TAU>
+// Algorithm 1's updates after the accepted step (u side).
 __global__ void __launch_bounds__(kStencilThreads)
-k_post(const float* __restrict__ xn, const float* __restrict__ xo, const float* __restrict__ v,
-       float* __restrict__ lam, float* __restrict__ xbar, float* __restrict__ phi, float mu,
-       PhiArgs pa, const float* __restrict__ f, float* __restrict__ lam3, float mu3,
-       const float* __restrict__ au, const float* __restrict__ tau0,
-       const uint8_t* __restrict__ mask, double* __restrict__ partials, int logn, int logm,
-       const DevCtl* ctl) {
-  if (ctl->halt) return;
+k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs,
+       int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  const float* xn = vol_at(pu.xn, ctl, zo);
+  const float* xo = vol_at(pu.xo, ctl, zo);
+  pu.v = zsh(pu.v, zo);
+  pu.lam = zsh(pu.lam, zo);
+  pu.xbar = zsh(pu.xbar, zo);
+  pu.phi = zsh(pu.phi, zo);
+  partials = zsh(partials, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)((t - 1.0) / tn);
-  const float eta2 = pa.eta * pa.eta;
+  const float eta2 = pu.pa.eta * pu.pa.eta;
   double s_tv = 0.0, s_a = 0.0, s_b = 0.0;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x)
-    post_at<TAU>(xn, xo, v, lam, xbar, phi, mu, pa, eta2, beta, f, lam3, mu3, au, tau0, mask, g,
-                 V, neighbours(g, logn, logm), logn, logm, s_tv, s_a, s_b);
+    post_at<false>(xn, xo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eta2, beta, nullptr,
+                   nullptr, 0.f, nullptr, nullptr, nullptr, g, V, neighbours(g, logn, logm), logn,
+                   logm, s_tv, s_a, s_b);
   double vals[3] = {s_tv, s_a, s_b};
-  if (!TAU) {
-    const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
-    block_sum_store<3>(vals, partials, slots, kMaxBlocks);
-  } else {
-    const int slots[3] = {SL_TV_TAU, SL_FIT, SL_FID};
-    block_sum_store<3>(vals, partials, slots, kMaxBlocks);
-  }
+  const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
+  block_sum_store<3>(vals, partials, slots, kMaxBlocks);
 }
 
 // Algorithm 2's updates after the accepted step, u side and tau side in one pass.
 __global__ void __launch_bounds__(kStencilThreads)
 k_post_dual(PostArgs pu, PostArgs pt, const float* __restrict__ f, float* __restrict__ lam3,
-            float mu3, const float* __restrict__ au, const float* __restrict__ tau0,
+            float mu3, Vol au_v, const float* __restrict__ tau0,
             const uint8_t* __restrict__ mask, double* __restrict__ partials, int logn, int logm,
-            const DevCtl* ctl) {
-  if (ctl->halt) return;
+            DevCtl* ctl, size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  const float* uxn = vol_at(pu.xn, ctl, zo);
+  const float* uxo = vol_at(pu.xo, ctl, zo);
+  const float* txn = vol_at(pt.xn, ctl, zo);
+  const float* txo = vol_at(pt.xo, ctl, zo);
+  const float* au = vol_at(au_v, ctl, zo);
+  pu.v = zsh(pu.v, zo);
+  pu.lam = zsh(pu.lam, zo);
+  pu.xbar = zsh(pu.xbar, zo);
+  pu.phi = zsh(pu.phi, zo);
+  pt.v = zsh(pt.v, zo);
+  pt.lam = zsh(pt.lam, zo);
+  pt.xbar = zsh(pt.xbar, zo);
+  pt.phi = zsh(pt.phi, zo);
+  f = zsh(f, zo);
+  lam3 = zsh(lam3, zo);
+  tau0 = zsh(tau0, zo);
+  mask = zsh(mask, zo);
+  partials = zsh(partials, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
@@ -261,9 +324,9 @@ k_post_dual(PostArgs pu, PostArgs pt, const float* __restrict__ f, float* __rest
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
     const Nbr nb = neighbours(g, logn, logm);
-    post_at<false>(pu.xn, pu.xo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eu, beta, nullptr,
+    post_at<false>(uxn, uxo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eu, beta, nullptr,
                    nullptr, 0.f, nullptr, nullptr, nullptr, g, V, nb, logn, logm, s[0], s[1], s[2]);
-    post_at<true>(pt.xn, pt.xo, pt.v, pt.lam, pt.xbar, pt.phi, pt.mu, pt.pa, et, beta, f, lam3,
+    post_at<true>(txn, txo, pt.v, pt.lam, pt.xbar, pt.phi, pt.mu, pt.pa, et, beta, f, lam3,
                   mu3, au, tau0, mask, g, V, nb, logn, logm, s[3], s[4], s[5]);
   }
   const int slots[6] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_TV_TAU, SL_FIT, SL_FID};
@@ -289,8 +352,11 @@ k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int l
 // (object) or A (dual); the left side comes from the difference of A u+ and
 // the cached A ubar, free of the cancellation of the literal form.
 __global__ void __launch_bounds__(kCtlThreads)
-k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on) {
-  if (ctl->halt) return;
+k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on,
+        size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  partials = zsh(partials, zo);
   const int slots[2] = {SL_CHECK, SL_STEP}, nbs[2] = {nb_conv, nb_step};
   double sums[2];
   block_sum_partials_k<2>(partials, slots, nbs, kMaxBlocks, sums);
@@ -302,11 +368,12 @@ k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_st
     } else if (bt_on && !(s_chk <= ctl->L * s_step)) {
       ctl->trials += 1;
       ctl->bt_rejects += 1;
-      ctl->halt = 1;
       if (ctl->trials > ctl->bt_max_trials) {
+        ctl->halt = 1;
         ctl->reason = HR_BACKTRACK;
       } else {
-        ctl->reason = HR_REJECT;
+        // the rest of this slot is skipped; the next slot redoes the iteration
+        ctl->reject = 1;
         ctl->L *= ctl->bt_factor;
       }
     }
@@ -316,8 +383,11 @@ k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_st
 // Energy, residuals, log row, FISTA t update, stopping rule.
 __global__ void __launch_bounds__(kCtlThreads)
 k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
-           int nb_conv, int nb_sten, int dual, double lambda, double mu_res) {
-  if (ctl->halt) return;
+           int nb_conv, int nb_sten, int dual, double lambda, double mu_res, size_t zs, int gate) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  if (!iter_head(ctl, zo, gate)) return;
+  logbuf = zsh(logbuf, zo);
+  partials = zsh(partials, zo);
   double E, prim, dres;
   if (!dual) {
     const int slots[4] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_DATA};
@@ -359,6 +429,17 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
     ctl->t = tn;
     ctl->iter += 1;
     ctl->trials = 0;
+    // the trial becomes the current iterate
+    int r = ctl->slot[R_U_CUR];
+    ctl->slot[R_U_CUR] = ctl->slot[R_U_TR];
+    ctl->slot[R_U_TR] = r;
+    r = ctl->slot[R_AU_PREV];
+    ctl->slot[R_AU_PREV] = ctl->slot[R_AU_CUR];
+    ctl->slot[R_AU_CUR] = ctl->slot[R_AU_TR];
+    ctl->slot[R_AU_TR] = r;
+    r = ctl->slot[R_T_CUR];
+    ctl->slot[R_T_CUR] = ctl->slot[R_T_TR];
+    ctl->slot[R_T_TR] = r;
     ctl->energy_prev = E;
     ctl->last_energy = E;
     ctl->last_primal = primal;
@@ -370,14 +451,26 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
   }
 }
 
-// Hand-over from the Algorithm-1 warm start to Algorithm 2 (idempotent: only
-// acts while stage == 1).  ubar = u, phi_u = phi(kappa(u)), phi_tau = phi(0),
-// tau, taubar, w, f and the multipliers zeroed.
+// Hand-over from the Algorithm-1 warm start to Algorithm 2, due once the warm
+// start's iterations are done and before the first Algorithm-2 iteration
+// (idempotent: the last of its kernels leaves stage 1).
+__device__ __forceinline__ bool transition_due(const DevCtl* c) {
+  return !c->halt && c->stage == 1 && c->iter == c->stage1_end && c->iter < c->target;
+}
+
+// ubar = u, phi_u = phi(kappa(u)), phi_tau = phi(0); tau, taubar, w, f and the
+// multipliers are zeroed by k_zero_if_stage1.
 __global__ void __launch_bounds__(kStencilThreads)
-k_transition_fields(const DevCtl* ctl, const float* __restrict__ u, float* __restrict__ ubar,
+k_transition_fields(const DevCtl* ctl, Vol u_v, float* __restrict__ ubar,
                     float* __restrict__ phi_u, PhiArgs pa, float* __restrict__ phi_tau,
-                    float phi_tau0, int logn, int logm) {
-  if (ctl->halt || ctl->stage != 1) return;
+                    float phi_tau0, int logn, int logm, size_t zs) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (!transition_due(ctl)) return;
+  const float* __restrict__ u = vol_resolve(u_v, ctl, zo);
+  ubar = zsh(ubar, zo);
+  phi_u = zsh(phi_u, zo);
+  phi_tau = zsh(phi_tau, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
   const float eta2 = pa.eta * pa.eta;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
@@ -391,15 +484,19 @@ k_transition_fields(const DevCtl* ctl, const float* __restrict__ u, float* __res
 }
 
 __global__ void __launch_bounds__(kStencilThreads)
-k_zero_if_stage1(const DevCtl* ctl, float* __restrict__ x, size_t n) {
-  if (ctl->halt || ctl->stage != 1) return;
+k_zero_if_stage1(const DevCtl* ctl, float* __restrict__ x, size_t n, size_t zs) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (!transition_due(ctl)) return;
+  x = zsh(x, zo);
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
        g += (size_t)gridDim.x * blockDim.x)
     x[g] = 0.f;
 }
 
-__global__ void k_transition_scalars(DevCtl* ctl) {
-  if (ctl->halt || ctl->stage != 1) return;
+__global__ void k_transition_scalars(DevCtl* ctl, size_t zs) {
+  ctl = zsh(ctl, (size_t)blockIdx.z * zs);
+  if (!transition_due(ctl)) return;
   ctl->stage = 2;
   ctl->t = 1.0;
   ctl->beta = 0.0;
@@ -497,10 +594,14 @@ __global__ void k_clear_halt(DevCtl* ctl) {
 // ---------------------------------------------------------------- launchers
 static dim3 sgrid(int logn, int logm) { return dim3(stencil_blocks(logn, logm)); }
 
+static dim3 sgrid_z(int logn, int logm, const Batch& bt) {
+  return dim3(stencil_blocks(logn, logm), 1, bt.nz);
+}
+
 hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
-                        float* v, double mu, const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_vstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, lam, phi, v,
-                     (float)(1.0 / mu), logn, logm, ctl);
+                        float* v, double mu, const DevCtl* ctl, const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_vstep, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, lam, phi,
+                     v, (float)(1.0 / mu), logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
@@ -508,81 +609,77 @@ hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* l
                            const float* phi, float* v, double mu1, const float* taubar,
                            const float* lam2, const float* phi_tau, float* w, double mu2,
                            const float* lam3, const float* tau0, const uint8_t* mask, float* f,
-                           double lambda, double mu3, const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_pre_dual, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, lam, phi, v,
-                     (float)(1.0 / mu1), taubar, lam2, phi_tau, w, (float)(1.0 / mu2), lam3, tau0,
-                     mask, f, (float)lambda, (float)mu3, logn, logm, ctl);
+                           double lambda, double mu3, const DevCtl* ctl, const Batch& bt,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_pre_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, lam,
+                     phi, v, (float)(1.0 / mu1), taubar, lam2, phi_tau, w, (float)(1.0 / mu2), lam3,
+                     tau0, mask, f, (float)lambda, (float)mu3, logn, logm,
+                     const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
-                            const float* f, float* lam3, double mu3, const float* au,
+                            const float* f, float* lam3, double mu3, Vol au,
                             const float* tau0, const uint8_t* mask, double* partials,
-                            const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_post_dual, sgrid(logn, logm), dim3(kStencilThreads), 0, st, pu, pt, f, lam3,
-                     (float)mu3, au, tau0, mask, partials, logn, logm, ctl);
+                            const DevCtl* ctl, const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_post_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pu, pt, f,
+                     lam3, (float)mu3, au, tau0, mask, partials, logn, logm,
+                     const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
-
 
 hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
-                        const float* lam, double mu, const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_u, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ubar, gf_rhs, v, lam,
-                     (float)mu, logn, logm, ctl);
+                        const float* lam, double mu, const DevCtl* ctl, const Batch& bt,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_u, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, gf_rhs,
+                     v, lam, (float)mu, logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_tau(int logn, int logm, const float* au, const float* f, const float* lam3,
+hipError_t launch_rhs_tau(int logn, int logm, Vol au, const float* f, const float* lam3,
                           const float* w, const float* lam2, float* rhs, double mu2, double mu3,
-                          const DevCtl* ctl, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_tau, sgrid(logn, logm), dim3(kStencilThreads), 0, st, au, f, lam3, w,
-                     lam2, rhs, (float)mu2, (float)mu3, logn, logm, ctl);
+                          const DevCtl* ctl, const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_tau, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, au, f, lam3,
+                     w, lam2, rhs, (float)mu2, (float)mu3, logn, logm, const_cast<DevCtl*>(ctl),
+                     bt.zs, bt.gate);
   return hipGetLastError();
 }
 
-hipError_t launch_post(int logn, int logm, bool tau_mode, const float* xnew, const float* xold,
-                       const float* v, float* lam, float* xbar, float* phi, double mu,
-                       const PhiArgs& pa, const float* f, float* lam3, double mu3,
-                       const float* au, const float* tau0, const uint8_t* mask, double* partials,
-                       const DevCtl* ctl, hipStream_t st) {
-  if (tau_mode)
-    hipLaunchKernelGGL(k_post<true>, sgrid(logn, logm), dim3(kStencilThreads), 0, st, xnew, xold, v,
-                       lam, xbar, phi, (float)mu, pa, f, lam3, (float)mu3, au, tau0, mask, partials,
-                       logn, logm, ctl);
-  else
-    hipLaunchKernelGGL(k_post<false>, sgrid(logn, logm), dim3(kStencilThreads), 0, st, xnew, xold,
-                       v, lam, xbar, phi, (float)mu, pa, f, lam3, (float)mu3, au, tau0, mask,
-                       partials, logn, logm, ctl);
+hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
+                       const DevCtl* ctl, const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_post, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pa, partials,
+                     logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
 hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
-                        hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(kCtlThreads), 0, st, ctl, partials, nb_conv, nb_step,
-                     bt_on);
+                        const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_check, dim3(1, 1, bt.nz), dim3(kCtlThreads), 0, st, ctl, partials, nb_conv,
+                     nb_step, bt_on, bt.zs, bt.gate);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
-                           int nb_sten, int dual, double lambda, double mu_res, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kCtlThreads), 0, st, ctl, log, partials, nb_conv,
-                     nb_sten, dual, lambda, mu_res);
+                           int nb_sten, int dual, double lambda, double mu_res, const Batch& bt,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1, 1, bt.nz), dim3(kCtlThreads), 0, st, ctl, log, partials,
+                     nb_conv, nb_sten, dual, lambda, mu_res, bt.zs, bt.gate);
   return hipGetLastError();
 }
 
-hipError_t launch_transition(int logn, int logm, DevCtl* ctl, const float* u, float* ubar,
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, float* ubar,
                              float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
                              float* const* zero_fields, const size_t* zero_counts, int nzero,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_transition_fields, sgrid(logn, logm), dim3(kStencilThreads), 0, st, ctl, u,
-                     ubar, phi_u, pa_u, phi_tau, (float)phi_tau0, logn, logm);
+                             const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_transition_fields, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st,
+                     ctl, u, ubar, phi_u, pa_u, phi_tau, (float)phi_tau0, logn, logm, bt.zs);
   for (int i = 0; i < nzero; ++i) {
     size_t nb = (zero_counts[i] + kStencilThreads - 1) / kStencilThreads;
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_zero_if_stage1, dim3((unsigned)nb), dim3(kStencilThreads), 0, st, ctl,
-                       zero_fields[i], zero_counts[i]);
+    hipLaunchKernelGGL(k_zero_if_stage1, dim3((unsigned)nb, 1, bt.nz), dim3(kStencilThreads), 0,
+                       st, ctl, zero_fields[i], zero_counts[i], bt.zs);
   }
-  hipLaunchKernelGGL(k_transition_scalars, dim3(1), dim3(1), 0, st, ctl);
+  hipLaunchKernelGGL(k_transition_scalars, dim3(1, 1, bt.nz), dim3(1), 0, st, ctl, bt.zs);
   return hipGetLastError();
 }
 

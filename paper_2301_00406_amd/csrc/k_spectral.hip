@@ -18,6 +18,20 @@
 
 namespace cnlos {
 
+// the volume behind v for this launch's scene (zo: the scene's byte offset)
+__device__ __forceinline__ const float* vol_in(const Vol& v, const DevCtl* c, size_t zo) {
+  return vol_resolve(v, c, zo);
+}
+__device__ __forceinline__ float* vol_out(const Vol& v, const DevCtl* c, size_t zo) {
+  return vol_resolve(v, c, zo);
+}
+__device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
+  S.rows = zsh(S.rows, zo);
+  S.rvals = zsh(S.rvals, zo);
+  S.cols = zsh(S.cols, zo);
+  S.cvals = zsh(S.cvals, zo);
+}
+
 // ---------------------------------------------------------------------------
 // launch shapes
 // ---------------------------------------------------------------------------
@@ -62,7 +76,8 @@ __device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
 template <int LOGM, bool PK>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
-            const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl) {
+            const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl,
+            size_t zs, int gate) {
   using T = TGeo<LOGM>;
   constexpr int M = 1 << LOGM, G = T::G, E = T::E, J = T::J, NT = T::NT;
   constexpr int ZS = M + M / 8 + 4;               // per-column LDS stride (float2)
@@ -75,7 +90,19 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   __shared__ float2 twc[M];
   __shared__ int4 srow_l[STAGE ? M : 1];
   __shared__ float sval_l[NNZ];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  zsh_tables(S, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  spec = zsh(spec, zo);
+  const float* sa = vol_in(src.a, ctl, zo);
+  const float* sb = vol_in(src.b, ctl, zo);
+  src.c = zsh(src.c, zo);
+  src.w = zsh(src.w, zo);
+  src.mask = zsh(src.mask, zo);
+  src.scale_div = zsh(src.scale_div, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) {
@@ -102,8 +129,8 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   for (int r = 0; r < E; ++r) {
     const int k = G * r + s;
     const size_t g = (size_t)col * M + k;
-    float x = ca * src.a[g];
-    if (src.b) x += cb * src.b[g];
+    float x = ca * sa[g];
+    if (sb) x += cb * sb[g];
     if (src.c) x -= src.c[g];
     if (src.w) x *= src.w[k];
     xf[k] = x * sc * mk;
@@ -169,7 +196,7 @@ template <int LOGM, int EPI, bool PK>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
             const float2* __restrict__ tw, const float2* __restrict__ twcg, ConvEpi ep, float scale,
-            const DevCtl* ctl) {
+            const DevCtl* ctl, size_t zs, int gate) {
   using T = TGeo<LOGM>;
   constexpr int M = 1 << LOGM, H = M / 2, G = T::G, E = T::E, J = T::J, NT = T::NT;
   constexpr bool STAGE = M <= 1024;
@@ -179,7 +206,21 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   __shared__ float2 twc[M];
   __shared__ int4 scol_l[STAGE ? M : 1];
   __shared__ float sval_l[NNZ];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  zsh_tables(S, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  spec = zsh(spec, zo);
+  float* eout = vol_out(ep.out, ctl, zo);
+  const float* eau = (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au, ctl, zo) : nullptr;
+  const float* eaup =
+      (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au_prev, ctl, zo) : nullptr;
+  ep.w = zsh(ep.w, zo);
+  ep.mask = zsh(ep.mask, zo);
+  ep.tau0 = zsh(ep.tau0, zo);
+  ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) {
@@ -244,11 +285,11 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
     const size_t gi = (size_t)col * M + k;
     if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
       tk *= mk;
-      ep.out[gi] = tk;
+      eout[gi] = tk;
       if (EPI == EPI_NORM) acc0 += (double)tk * (double)tk;
     } else {
-      ep.out[gi] = tk;
-      const float d = tk - (ca * ep.au[gi] + cb * ep.au_prev[gi]);
+      eout[gi] = tk;
+      const float d = tk - (ca * eau[gi] + cb * eaup[gi]);
       if (EPI == EPI_FWD_OBJ) {
         if (mk != 0.f) {
           acc0 += (double)d * (double)d;
@@ -283,12 +324,17 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneCfg<LOGN>::NT)
 k_plane_conv(float2* __restrict__ spec, const float2* __restrict__ hq,
-             const float2* __restrict__ tw, const DevCtl* ctl) {
+             const float2* __restrict__ tw, const DevCtl* ctl, size_t zs, int gate) {
   constexpr int N = 1 << LOGN, NP = N + 1, NN = N * N, N1 = N + 1;
   constexpr int NT = PlaneCfg<LOGN>::NT, PER = PlaneCfg<LOGN>::PER;
   __shared__ float2 A[N * NP];
   __shared__ float2 tws[N];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  spec = zsh(spec, zo);
+  hq = zsh(hq, zo);
+  tw = zsh(tw, zo);
   const int tid = threadIdx.x;
   const int plane = blockIdx.x;
   float2* P = spec + (size_t)plane * NN;
@@ -359,10 +405,9 @@ k_plane_conv(float2* __restrict__ spec, const float2* __restrict__ hq,
 //
 // Block 0 holds the two real planes kt = 0 and kt = m packed as
 // Z = P_0 + i P_m.  H^ is real on both (h is even in x and y, and the t phase
-// is +-1), so after the row pass the two planes' row spectra separate as
-//   R_0(ky) = (R(ky) + conj R(-ky)) / 2,  R_m(ky) = (R(ky) - conj R(-ky)) / 2i,
-// each column pair is transformed, multiplied by its own H^, recombined as
-// Y_0 + i Y_m and transformed back; the result is conv(P_0) + i conv(P_m).
+// is +-1), and the spectra of the real planes are Hermitian, so the product
+// separates with the partner frequency -k (see plane_conv_cols_packed); the
+// result is conv(P_0) + i conv(P_m).
 // ---------------------------------------------------------------------------
 template <int LOGN>
 struct PlaneRegCfg {
@@ -403,7 +448,11 @@ __device__ __forceinline__ int hq_index(int px, int py) {
   return kx * (N + 1) + ky;
 }
 
-// column pass of block 0 (the packed real planes kt = 0 and kt = m)
+// column pass of block 0 (the packed real planes kt = 0 and kt = m).  The
+// forward column spectra Z^ of all 2n columns go to LDS (2n rows), then each
+// position combines its own value with the partner at (-kx, -ky):
+//   Y(k) = Z^(k) (H_0 + H_m)/2 + conj(Z^(-k)) (H_0 - H_m)/2,
+// the spectrum of conv(P_0) + i conv(P_m) (H_0, H_m real and even).
 template <int LOGN>
 __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* H0, const float2* Hm,
                                                        const float2* tws, const float2* twc,
@@ -413,43 +462,60 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
   const int s = tid & 7;
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
-    // -ky has the parity of ky, so a column and its partner lie in the same half
+    const int col = (tid >> 3) + half * N;
+    float2 c[RE];
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
+    col_fwd<LOGN>(c, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RE; ++r) Y[(8 * r + s) * YS + col] = c[r];
+  }
+  __syncthreads();
+  float2 w[2][RE];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
     const int col = (tid >> 3) + half * N;
     const int colp = brev((L - brev(col, LOGL)) & (L - 1), LOGL);
-    float2 a0[RE], am[RE];
-#pragma unroll
-    for (int r = 0; r < RE / 2; ++r) {
-      const float2 c = Y[(8 * r + s) * YS + col];
-      const float2 d = Y[(8 * r + s) * YS + colp];
-      a0[r] = make_float2(0.5f * (c.x + d.x), 0.5f * (c.y - d.y));
-      am[r] = make_float2(0.5f * (c.y + d.y), 0.5f * (d.x - c.x));
-    }
-    __syncthreads();                               // partners read before any write-back
-    col_fwd<LOGN>(a0, s, tws, twc);
-    col_fwd<LOGN>(am, s, tws, twc);
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
-      const int q = hq_index<LOGN>(8 * r + s, col);
-      const float2 y0 = cscale(a0[r], H0[q].x), ym = cscale(am[r], Hm[q].x);
-      a0[r] = make_float2(y0.x - ym.y, y0.y + ym.x);
+      const int p = 8 * r + s;
+      const int pp = brev((L - brev(p, LOGL)) & (L - 1), LOGL);
+      const float2 own = Y[p * YS + col], par = Y[pp * YS + colp];
+      const int q = hq_index<LOGN>(p, col);
+      const float h0 = H0[q].x, hm = Hm[q].x;
+      const float a = 0.5f * (h0 + hm), b = 0.5f * (h0 - hm);
+      w[half][r] = make_float2(a * own.x + b * par.x, a * own.y - b * par.y);
     }
-    col_inv<LOGN>(a0, s, tws, twc);
+  }
+  __syncthreads();                                 // every partner read before write-back
 #pragma unroll
-    for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = a0[r];
+  for (int half = 0; half < 2; ++half) {
+    const int col = (tid >> 3) + half * N;
+    col_inv<LOGN>(w[half], s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = w[half][r];
   }
 }
 
 template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneRegCfg<LOGN>::NT)
 k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
-                 const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl) {
+                 const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
+                 size_t zs, int gate) {
   using PC = PlaneRegCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, NT = PC::NT;
   constexpr int RE = PC::RE, YS = PC::YS, N1 = N + 1;
-  __shared__ float2 Y[N * YS];
+  // n rows of row spectra; block 0 uses all 2n rows for its column spectra
+  __shared__ float2 Y[2 * N * YS];
   __shared__ float2 tws[N];
   __shared__ float2 twc[L];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  spec = zsh(spec, zo);
+  hq = zsh(hq, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
   const int tid = threadIdx.x;
   float2* P = spec + (size_t)blockIdx.x * N * N;
   const float2* Hp = hq + (size_t)blockIdx.x * N1 * N1;
@@ -517,13 +583,21 @@ template <int LOGN>
 __global__ void __launch_bounds__(PlaneSolveCfg<LOGN>::NT)
 k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
                   const float* __restrict__ sig_xy, const float* __restrict__ sig_t,
-                  const double* c_dev, float c_val, float mu, const DevCtl* ctl) {
+                  const double* c_dev, float c_val, float mu, const DevCtl* ctl, size_t zs,
+                  int gate) {
   using PC = PlaneSolveCfg<LOGN>;
   constexpr int N = PC::N, NT = PC::NT, E = PC::E, YS = PC::YS;
   __shared__ float2 Y[N * YS];
   __shared__ float2 twc[N];
   __shared__ float sg[N];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  spec = zsh(spec, zo);
+  twcg = zsh(twcg, zo);
+  sig_xy = zsh(sig_xy, zo);
+  sig_t = zsh(sig_t, zo);
+  c_dev = zsh(c_dev, zo);
   const int tid = threadIdx.x;
   const int plane = blockIdx.x;
   float2* P = spec + (size_t)plane * N * N;
@@ -600,7 +674,8 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
 template <int LOGM>
 __global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
 k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
-             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl) {
+             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl,
+             size_t zs, int gate) {
   using T = TGeo<LOGM - 1>;
   constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
   constexpr int G = T::G, E = T::E, J = T::J, NT = T::NT, ZS = H + H / 8 + 4;
@@ -608,7 +683,13 @@ k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
   __shared__ float2 lds[LDS2];
   __shared__ float2 tws[M];
   __shared__ float2 twc[H];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  src = zsh(src, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  spec = zsh(spec, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
@@ -655,14 +736,23 @@ k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
 template <int LOGM>
 __global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
 k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__ tw,
-             const float2* __restrict__ twcg, SolveEpi ep, float scale, const DevCtl* ctl) {
+             const float2* __restrict__ twcg, SolveEpi ep, float scale, const DevCtl* ctl,
+             size_t zs, int gate) {
   using T = TGeo<LOGM - 1>;
   constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
   constexpr int G = T::G, E = T::E, J = T::J, NT = T::NT;
   __shared__ float2 lds[stg_size<J>(H + 1)];
   __shared__ float2 tws[M];
   __shared__ float2 twc[H];
-  if (ctl != nullptr && ctl->halt) return;
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  spec = zsh(spec, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  float* eout = vol_out(ep.out, ctl, zo);
+  ep.ref = zsh(ep.ref, zo);
+  ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
@@ -690,7 +780,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   dit_xlane<G, E>(x, s, twc);
   dit_inlane<G, E, E / 2>(x, s, twc);
   double acc = 0.0;
-  float2* out2 = reinterpret_cast<float2*>(ep.out) + (size_t)col * H;
+  float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
   const float2* ref2 = ep.ref ? reinterpret_cast<const float2*>(ep.ref) + (size_t)col * H : nullptr;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -777,80 +867,77 @@ int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / (logm - 1 >= 1
 
 template <int LOGN, int LOGM>
 static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, bool adjoint,
-                            int epi, const ConvEpi& ep, const DevCtl* ctl, hipStream_t st,
-                            Prof* prof) {
+                            int epi, const ConvEpi& ep, const DevCtl* ctl, const Batch& bt,
+                            hipStream_t st, Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   // the register plane kernel takes the real planes kt = 0, m packed in one
   constexpr bool PK = LOGN <= 6;
   using TG = TGeo<LOGM>;
   const int nb = NN / TG::J;
+  const int nz = bt.nz, g = bt.gate;
+  const size_t zs = bt.zs;
   CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
-              hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb), dim3(TG::NT), 0, st, src, tb.S,
-                                 tb.tw_t, tb.twc_t, spec, NN, ctl));
+              hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, st, src,
+                                 tb.S, tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
   if constexpr (LOGN <= 6) {
     constexpr int LN = LOGN;
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M),
-                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M, 1, nz),
+                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
+                                     tb.twc_xy, ctl, zs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M),
-                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl));
+                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M, 1, nz),
+                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
+                                     tb.twc_xy, ctl, zs, g));
   } else {
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv<LOGN, true>), dim3(M + 1),
-                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl));
+                  hipLaunchKernelGGL((k_plane_conv<LOGN, true>), dim3(M + 1, 1, nz),
+                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl,
+                                     zs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv<LOGN, false>), dim3(M + 1),
-                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl));
+                  hipLaunchKernelGGL((k_plane_conv<LOGN, false>), dim3(M + 1, 1, nz),
+                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl,
+                                     zs, g));
   }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
+#define CNLOS_TINV(E)                                                                         \
+  CNLOS_TIMED(prof, KK_T_INV_CONV, st,                                                        \
+              hipLaunchKernelGGL((k_tinv_conv<LOGM, E, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, \
+                                 st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl, zs, g))
   switch (epi) {
-    case EPI_PLAIN:
-      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_PLAIN, PK>), dim3(nb), dim3(TG::NT), 0, st,
-                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
-      break;
-    case EPI_FWD_OBJ:
-      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_OBJ, PK>), dim3(nb), dim3(TG::NT), 0, st,
-                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
-      break;
-    case EPI_FWD_DUAL:
-      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_FWD_DUAL, PK>), dim3(nb), dim3(TG::NT), 0,
-                                     st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
-      break;
-    default:
-      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                  hipLaunchKernelGGL((k_tinv_conv<LOGM, EPI_NORM, PK>), dim3(nb), dim3(TG::NT), 0, st,
-                                     spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, ctl));
-      break;
+    case EPI_PLAIN: CNLOS_TINV(EPI_PLAIN); break;
+    case EPI_FWD_OBJ: CNLOS_TINV(EPI_FWD_OBJ); break;
+    case EPI_FWD_DUAL: CNLOS_TINV(EPI_FWD_DUAL); break;
+    default: CNLOS_TINV(EPI_NORM); break;
   }
+#undef CNLOS_TINV
   return hipGetLastError();
 }
 
 template <int LOGN, int LOGM>
 static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, const double* c_dev,
                              double c_val, double mu, const SolveEpi& ep, const DevCtl* ctl,
-                             hipStream_t st, Prof* prof) {
+                             const Batch& bt, hipStream_t st, Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   using TG = TGeo<LOGM - 1>;
   const int nb = NN / TG::J;
+  const int nz = bt.nz, g = bt.gate;
+  const size_t zs = bt.zs;
   CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
-              hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb), dim3(TG::NT), 0, st, rhs, tb.tw_t,
-                                 tb.twc_t, spec, NN, ctl));
+              hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb, 1, nz), dim3(TG::NT), 0, st, rhs,
+                                 tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
   CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
-              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2),
+              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2, 1, nz),
                                  dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
-                                 tb.sig_t, c_dev, (float)c_val, (float)mu, ctl));
+                                 tb.sig_t, c_dev, (float)c_val, (float)mu, ctl, zs, g));
   const float scale = (float)(2.0 / ((double)NN * (double)M));
   CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
-              hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb), dim3(TG::NT), 0, st, spec, NN,
-                                 tb.tw_t, tb.twc_t, ep, scale, ctl));
+              hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb, 1, nz), dim3(TG::NT), 0, st, spec,
+                                 NN, tb.tw_t, tb.twc_t, ep, scale, ctl, zs, g));
   return hipGetLastError();
 }
 
@@ -879,14 +966,14 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, c
 
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       hipStream_t st, Prof* prof) {
-  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, st, prof)
+                       const Batch& bt, hipStream_t st, Prof* prof) {
+  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof)
 }
 
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
                         const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, hipStream_t st, Prof* prof) {
-  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, spec, c_dev, c_val, mu, ep, ctl, st, prof)
+                        const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof) {
+  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof)
 }
 
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,

@@ -23,7 +23,7 @@ def header_functions():
 def test_library_exports_every_declared_function():
     lib = C.load()
     names = header_functions()
-    assert len(names) == 21
+    assert len(names) == 27
     for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
@@ -133,3 +133,48 @@ def test_create_rejects_before_touching_the_device():
     # null handles are rejected, destroy(NULL) is fine
     assert lib.cnlos_run(None, 1, None) == C.EINVAL
     assert lib.cnlos_destroy(None) == C.OK
+
+
+def _batch_create_status(cfgs, masks, ws_bytes=0):
+    lib = C.load()
+    n = len(cfgs)
+    arr = (C.Config * n)(*cfgs)
+    ms = [np.ascontiguousarray(m, dtype=np.uint8) for m in masks]
+    mp = (ctypes.POINTER(ctypes.c_uint8) * n)(*[m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+                                                for m in ms])
+    h = ctypes.c_void_p()
+    return lib.cnlos_batch_create(arr, n, mp, None, ctypes.c_uint64(ws_bytes), None, ctypes.byref(h))
+
+
+def test_batch_workspace_is_count_slices():
+    cfg = C.default_config(nx=32, ny=32, nt=256, model=C.MODEL_DUAL)
+    one = C.workspace_bytes(cfg)
+    n = ctypes.c_uint64()
+    assert C.load().cnlos_batch_workspace_bytes(ctypes.byref(cfg), 5, ctypes.byref(n)) == C.OK
+    assert n.value == 5 * one and one % 256 == 0
+    assert C.load().cnlos_batch_workspace_bytes(ctypes.byref(cfg), 0, ctypes.byref(n)) == C.EINVAL
+    op = C.default_config(model=C.MODEL_OPERATOR)
+    assert C.load().cnlos_batch_workspace_bytes(ctypes.byref(op), 2, ctypes.byref(n)) == C.EINVAL
+
+
+@pytest.mark.parametrize("field,value", [("nt", 256), ("mu", 0.2), ("model", C.MODEL_DUAL),
+                                         ("a_u", 1e-3), ("phi", C.PHI_TAC), ("backtracking", 0)])
+def test_batch_members_must_share_kernel_parameters(field, value):
+    a = C.default_config()
+    b = C.default_config()
+    setattr(b, field, value)
+    mask = np.ones((16, 16), np.uint8)
+    assert _batch_create_status([a, b], [mask, mask]) == C.EINVAL
+    assert "differs" in C.last_error()
+
+
+def test_batch_members_may_differ_in_geometry_and_budget():
+    a = C.default_config()
+    b = C.default_config(wall_w_m=0.7, wall_h_m=0.7, bin_ps=16.0, max_iters=7, eps_stop=1e-6)
+    mask = np.ones((16, 16), np.uint8)
+    # passes the shared-field checks and stops at the missing workspace
+    assert _batch_create_status([a, b], [mask, mask]) == C.EINVAL
+    assert "workspace is NULL" in C.last_error()
+    empty = np.zeros((16, 16), np.uint8)
+    assert _batch_create_status([a, b], [mask, empty]) == C.EINVAL
+    assert "mask" in C.last_error()
