@@ -1,5 +1,5 @@
 // Device building blocks shared by the spectral kernels: complex arithmetic,
-// a batched in-place radix-2^R FFT over LDS, and deterministic FP64 block
+// register-resident lane-split FFT stages, and deterministic FP64 block
 // reductions.
 //
 // FFT convention.  The forward transform is decimation in frequency (DIF): it
@@ -9,8 +9,9 @@
 // transform, a pointwise spectral operation that knows each position's
 // frequency, and an inverse transform therefore need no reordering pass.
 //
-// Twiddles come from a table tw[i] = exp(-2 pi i * i / T), i in [0, T/2),
-// computed in FP64 on the host; T = 2^logT must be at least the length.
+// Butterfly twiddles come from a per-span table twc[d + k] = exp(-pi i k / d)
+// (d = 1, 2, 4, ..., k < d), computed in FP64 on the host; one table of size
+// 2^b serves every transform of length up to 2^b.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,85 +32,6 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 __device__ __forceinline__ int brev(int x, int bits) {
   return bits == 0 ? 0 : (int)(__brev((unsigned)x) >> (32 - bits));
 }
-
-// One group of R radix-2 stages on every sequence of the batch.
-// Element e of sequence b lives at d[b * bs + e * es].  The group touches the
-// 2^R elements j + m*h (m < 2^R) of each block of 2^R * h elements.
-//   DIF: spans 2^(R-1) h down to h;  DIT: spans h up to 2^(R-1) h.
-// Work items are (b, block, j) with b fastest so that neighbouring lanes touch
-// neighbouring sequences.
-template <int R, bool INV>
-__device__ __forceinline__ void fft_group(float2* __restrict__ d, int B, int bs, int es,
-                                          const float2* __restrict__ tw, int logT, int logL,
-                                          int logh, int tid, int nthr) {
-  constexpr int P = 1 << R;
-  const int h = 1 << logh;
-  const int items = B << (logL - R);
-  for (int it = tid; it < items; it += nthr) {
-    const int b = it % B;
-    const int rest = it / B;
-    const int j = rest & (h - 1);
-    const int blk = rest >> logh;
-    const int base = b * bs + ((blk << (logh + R)) + j) * es;
-    const int step = h * es;
-    float2 x[P];
-#pragma unroll
-    for (int m = 0; m < P; ++m) x[m] = d[base + m * step];
-    if (!INV) {
-#pragma unroll
-      for (int e = R - 1; e >= 0; --e) {
-        const int half = 1 << e;
-        const int sh = logT - 1 - e - logh;   // T / (2 * span)
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-          if (m & half) continue;
-          const int pos = j + (m & (half - 1)) * h;
-          const float2 w = tw[pos << sh];
-          const float2 a = x[m], c = x[m + half];
-          x[m] = cadd(a, c);
-          x[m + half] = cmul(csub(a, c), w);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < R; ++e) {
-        const int half = 1 << e;
-        const int sh = logT - 1 - e - logh;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-          if (m & half) continue;
-          const int pos = j + (m & (half - 1)) * h;
-          const float2 w = tw[pos << sh];
-          const float2 a = x[m], c = cmulc(x[m + half], w);
-          x[m] = cadd(a, c);
-          x[m + half] = csub(a, c);
-        }
-      }
-    }
-#pragma unroll
-    for (int m = 0; m < P; ++m) d[base + m * step] = x[m];
-  }
-}
-
-// Runs the stages DONE .. STOP-1 of a length-2^LOGL transform in groups of at
-// most MAXR stages, with a barrier after each group.  For DIF stage s has span
-// 2^(LOGL-1-s); for DIT stage s has span 2^s.
-template <int LOGL, int DONE, int STOP, int MAXR, bool INV>
-struct FftRun {
-  static __device__ __forceinline__ void go(float2* d, int B, int bs, int es, const float2* tw,
-                                            int logT, int tid, int nthr) {
-    constexpr int REM = STOP - DONE;
-    constexpr int R = REM < MAXR ? REM : MAXR;
-    constexpr int LOGH = INV ? DONE : (LOGL - DONE - R);
-    fft_group<R, INV>(d, B, bs, es, tw, logT, LOGL, LOGH, tid, nthr);
-    __syncthreads();
-    FftRun<LOGL, DONE + R, STOP, MAXR, INV>::go(d, B, bs, es, tw, logT, tid, nthr);
-  }
-};
-template <int LOGL, int STOP, int MAXR, bool INV>
-struct FftRun<LOGL, STOP, STOP, MAXR, INV> {
-  static __device__ __forceinline__ void go(float2*, int, int, int, const float2*, int, int, int) {}
-};
 
 // ---------------------------------------------------------------------------
 // Lane-split register FFT.  A group of LANES consecutive lanes holds one

@@ -10,9 +10,11 @@
 //   t pass   : per scan column, complex-to-real inverse FFT along t, crop,
 //              R_t^{-1} (S^T and the falloff weight), fused epilogue.
 // The t axis of the convolution is padded to 2m and the real input makes only
-// kt = 0..m necessary; the (x, y) padding to 2n x 2n is done inside the plane
-// kernel by splitting the padded grid into its four parity quadrants, each an
-// n x n transform with a twist, so an n x n plane never leaves registers/LDS.
+// kt = 0..m necessary (the two real bins kt = 0, m share one plane for n <= 64);
+// the (x, y) padding to 2n x 2n lives only inside the plane kernel: rows and
+// columns are transformed with their zero halves folded into twists, and the
+// n x n crop is taken before anything leaves the CU (n = 128 splits the plane
+// by ky parity to fit LDS).
 #include "cnlos_internal.h"
 #include "fft_device.h"
 
@@ -35,12 +37,6 @@ __device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
 // ---------------------------------------------------------------------------
 // launch shapes
 // ---------------------------------------------------------------------------
-template <int LOGN>
-struct PlaneCfg {
-  static constexpr int NN = 1 << (2 * LOGN);
-  static constexpr int NT = (NN / 16) > 256 ? (NN / 16) : 256;
-  static constexpr int PER = (NN / NT) > 0 ? (NN / NT) : 1;
-};
 
 // ---------------------------------------------------------------------------
 // t passes.  A block handles J = 8 scan columns; each column's FFT lives in
@@ -317,84 +313,6 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 }
 
 // ---------------------------------------------------------------------------
-// plane kernel of the convolution: padded 2n x 2n transform of an n x n plane
-// via its four parity quadrants, times H^ (or conj H^), cropped back to n x n.
-// The output is unnormalized; the inverse t pass applies the scale.
-// ---------------------------------------------------------------------------
-template <int LOGN, bool ADJ>
-__global__ void __launch_bounds__(PlaneCfg<LOGN>::NT)
-k_plane_conv(float2* __restrict__ spec, const float2* __restrict__ hq,
-             const float2* __restrict__ tw, const DevCtl* ctl, size_t zs, int gate) {
-  constexpr int N = 1 << LOGN, NP = N + 1, NN = N * N, N1 = N + 1;
-  constexpr int NT = PlaneCfg<LOGN>::NT, PER = PlaneCfg<LOGN>::PER;
-  __shared__ float2 A[N * NP];
-  __shared__ float2 tws[N];
-  const size_t zo = (size_t)blockIdx.z * zs;
-  ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return;
-  spec = zsh(spec, zo);
-  hq = zsh(hq, zo);
-  tw = zsh(tw, zo);
-  const int tid = threadIdx.x;
-  const int plane = blockIdx.x;
-  float2* P = spec + (size_t)plane * NN;
-  const float2* Hp = hq + (size_t)plane * N1 * N1;
-  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
-  float2 X[PER], OUT[PER];
-#pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int e = tid + s * NT;
-    X[s] = e < NN ? P[e] : make_float2(0.f, 0.f);
-    OUT[s] = make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    const int px = q & 1, py = q >> 1;
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + s * NT;
-      if (e < NN) {
-        const int i = e >> LOGN, j = e & (N - 1);
-        const int n = px * i + py * j;
-        const float2 w = n < N ? tws[n] : make_float2(-tws[n - N].x, -tws[n - N].y);
-        A[i * NP + j] = cmul(X[s], w);
-      }
-    }
-    __syncthreads();
-    FftRun<LOGN, 0, LOGN, 3, false>::go(A, N, NP, 1, tws, LOGN + 1, tid, NT);
-    FftRun<LOGN, 0, LOGN, 3, false>::go(A, N, 1, NP, tws, LOGN + 1, tid, NT);
-    for (int e = tid; e < NN; e += NT) {
-      const int pi = e >> LOGN, pj = e & (N - 1);
-      int kx = 2 * brev(pi, LOGN) + px, ky = 2 * brev(pj, LOGN) + py;
-      kx = kx <= N ? kx : 2 * N - kx;
-      ky = ky <= N ? ky : 2 * N - ky;
-      const float2 h = Hp[kx * N1 + ky];
-      const float2 a = A[pi * NP + pj];
-      A[pi * NP + pj] = ADJ ? cmulc(a, h) : cmul(a, h);
-    }
-    __syncthreads();
-    FftRun<LOGN, 0, LOGN, 3, true>::go(A, N, 1, NP, tws, LOGN + 1, tid, NT);
-    FftRun<LOGN, 0, LOGN, 3, true>::go(A, N, NP, 1, tws, LOGN + 1, tid, NT);
-#pragma unroll
-    for (int s = 0; s < PER; ++s) {
-      const int e = tid + s * NT;
-      if (e < NN) {
-        const int i = e >> LOGN, j = e & (N - 1);
-        const int n = px * i + py * j;
-        const float2 w = n < N ? tws[n] : make_float2(-tws[n - N].x, -tws[n - N].y);
-        OUT[s] = cadd(OUT[s], cmulc(A[i * NP + j], w));
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int s = 0; s < PER; ++s) {
-    const int e = tid + s * NT;
-    if (e < NN) P[e] = OUT[s];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Register-resident plane kernel of the convolution (n <= 64).  Rows: 8 lanes
 // per row transform the zero-padded row (length 2n) with the upper half of
 // the first stage folded into a twist; the 2n spectrum positions go to LDS.
@@ -569,6 +487,159 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
     for (int r = 0; r < RE / 2; ++r) x[r] = cadd(x[r], cmulc(x[r + RE / 2], tws[8 * r + s]));
 #pragma unroll
     for (int r = 0; r < RE / 2; ++r) P[row * N + 8 * r + s] = x[r];
+  }
+}
+
+// Plane kernel of the convolution for n = 128, where one padded 2n x 2n
+// plane does not fit in LDS.  The padded transform is split by the parity h
+// of ky: the even and odd ky rows of the spectrum are n-point transforms of
+// each row (the odd ones after the twist W_2n^y), so each half is
+//   rows:    n-point DIF per row (twisted for h = 1) -> LDS [x][ky_h]
+//   columns: zero-padded 2n-point transform per ky_h column, times H^ (or its
+//            conjugate), inverse, keep the first n rows
+//   rows:    n-point DIT back (untwisted for h = 1), accumulated in registers
+// and the sum over both halves is the cropped padded convolution.  A lane
+// group of 8 handles two rows / columns in turn.
+template <int LOGN>
+struct PlaneHalfCfg {
+  static constexpr int N = 1 << LOGN, L = 2 * N, NT = 4 * N, G = NT / 8;
+  static constexpr int RN = N / 8, YS = N + 8;
+};
+
+// rows of the half-split plane kernel: forward n-point DIF of the two rows
+// of a lane group (twisted by W_2n^y for the odd half) into LDS
+template <int LOGN>
+__device__ __forceinline__ void half_rows_fwd(float2 (&v)[2][PlaneHalfCfg<LOGN>::RN], int h,
+                                              float2* Y, const float2* tws, const float2* twc,
+                                              int g, int s) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int RN = PC::RN, YS = PC::YS, G = PC::G;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (h) {
+#pragma unroll
+      for (int r = 0; r < RN; ++r) v[i][r] = cmul(v[i][r], tws[8 * r + s]);
+    }
+    dif_inlane<8, RN, RN / 2>(v[i], s, twc);
+    dif_xlane<8, RN>(v[i], s, twc);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) Y[(g + G * i) * YS + 8 * r + s] = v[i][r];
+  }
+}
+
+// columns of the half-split plane kernel: padded 2n-point transform of each
+// ky_h column, H^ product, inverse, first n rows back to LDS
+template <int LOGN, bool ADJ>
+__device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, const float2* tws,
+                                          const float2* twc, int g, int s) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int N = PC::N, L = PC::L, YS = PC::YS, G = PC::G, N1 = N + 1;
+  constexpr int RE = PlaneRegCfg<LOGN>::RE;
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    const int col = g + G * i;
+    float2 c[RE];
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
+    col_fwd<LOGN>(c, s, tws, twc);
+    int ky = 2 * brev(col, LOGN) + h;
+    ky = ky <= N ? ky : L - ky;
+    // H^ in chunks of 8, so that its loads do not all stay live at once
+#pragma unroll
+    for (int r0 = 0; r0 < RE; r0 += 8) {
+#pragma unroll
+      for (int r = r0; r < r0 + 8; ++r) {
+        int kx = brev(8 * r + s, LOGN + 1);
+        kx = kx <= N ? kx : L - kx;
+        const float2 hv = Hp[kx * N1 + ky];
+        c[r] = ADJ ? cmulc(c[r], hv) : cmul(c[r], hv);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    col_inv<LOGN>(c, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = c[r];
+  }
+}
+
+// inverse rows: n-point DIT of a row from LDS (untwisted for the odd half)
+template <int LOGN>
+__device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN], int h, int x,
+                                             const float2* Y, const float2* tws, const float2* twc,
+                                             int s) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int RN = PC::RN, YS = PC::YS;
+#pragma unroll
+  for (int r = 0; r < RN; ++r) v[r] = Y[x * YS + 8 * r + s];
+  dit_xlane<8, RN>(v, s, twc);
+  dit_inlane<8, RN, RN / 2>(v, s, twc);
+  if (h) {
+#pragma unroll
+    for (int r = 0; r < RN; ++r) v[r] = cmulc(v[r], tws[8 * r + s]);
+  }
+}
+
+template <int LOGN, bool ADJ>
+__global__ void __launch_bounds__(PlaneHalfCfg<LOGN>::NT)
+k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
+                  const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
+                  size_t zs, int gate) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, RN = PC::RN, YS = PC::YS;
+  constexpr int N1 = N + 1;
+  static_assert(2 * G == N, "two rows per lane group");
+  __shared__ float2 Y[N * YS];
+  __shared__ float2 tws[N];
+  __shared__ float2 twc[L];
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  if (gated_off(ctl, gate)) return;
+  spec = zsh(spec, zo);
+  hq = zsh(hq, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  const int tid = threadIdx.x, g = tid >> 3, s = tid & 7;
+  float2* P = spec + (size_t)blockIdx.x * N * N;
+  const float2* Hp = hq + (size_t)blockIdx.x * N1 * N1;
+  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
+  for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
+  __syncthreads();
+  // even ky half; each thread owns plane elements (g + G i, 8 r + s) throughout
+  float2 v[2][RN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
+  half_rows_fwd<LOGN>(v, 0, Y, tws, twc, g, s);
+  __syncthreads();
+  half_cols<LOGN, ADJ>(0, Y, Hp, tws, twc, g, s);
+  __syncthreads();
+  // the odd half's input, then the even half's output in its place
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    float2 o[RN];
+    half_row_inv<LOGN>(o, 0, g + G * i, Y, tws, twc, s);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) P[(g + G * i) * N + 8 * r + s] = o[r];
+  }
+  __syncthreads();                                 // Y is rewritten by the odd half
+  half_rows_fwd<LOGN>(v, 1, Y, tws, twc, g, s);
+  __syncthreads();
+  half_cols<LOGN, ADJ>(1, Y, Hp, tws, twc, g, s);
+  __syncthreads();
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    float2 o[RN];
+    half_row_inv<LOGN>(o, 1, g + G * i, Y, tws, twc, s);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      float2* q = P + (g + G * i) * N + 8 * r + s;
+      *q = cadd(*q, o[r]);
+    }
   }
 }
 
@@ -894,14 +965,14 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   } else {
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv<LOGN, true>), dim3(M + 1, 1, nz),
-                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl,
-                                     zs, g));
+                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, true>), dim3(M + 1, 1, nz),
+                                     dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
+                                     tb.twc_xy, ctl, zs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv<LOGN, false>), dim3(M + 1, 1, nz),
-                                     dim3(PlaneCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, ctl,
-                                     zs, g));
+                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, false>), dim3(M + 1, 1, nz),
+                                     dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
+                                     tb.twc_xy, ctl, zs, g));
   }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
 #define CNLOS_TINV(E)                                                                         \

@@ -24,6 +24,7 @@ SHAPES = [
     (32, 64, 0.6, 32.0),
     (8, 256, 0.3, 16.0),
     (16, 2048, 1.0, 8.0),
+    (128, 32, 2.0, 64.0),     # the n = 128 plane kernel (split by ky parity), full volume
 ]
 
 
