@@ -326,6 +326,61 @@ cnlos_status cnlos_batch_run_many(cnlos_batch* const* batches, int32_t count, in
 /* Release the batch and its members (the workspace stays the caller's). */
 cnlos_status cnlos_batch_destroy(cnlos_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Serving with continuous batching.  Requests of any supported shape are
+ * queued; each step admits queued requests into free slots of a slot group of
+ * their shape (a batch that keeps running while its members change), creating
+ * a group when the HBM arena has room, advances every group on its own
+ * stream (groups overlap on the device), and retires finished requests,
+ * whose slots take new requests at the next step.  A request's result is
+ * bitwise the result of running it alone (cnlos_create + cnlos_run).
+ * All device memory comes from one caller-owned arena; the server never
+ * allocates device memory.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct cnlos_server cnlos_server;   /* opaque */
+
+typedef struct cnlos_request {
+  cnlos_config cfg;           /* shape, model, weights and iteration budget         */
+  const uint8_t* mask_host;   /* [nx][ny]; copied at submit                         */
+  const float* tau0_dev;      /* raw measurement [nx][ny][nt]; read at admission,   */
+                              /* so it must stay valid until the request completes  */
+  float* out_dev;             /* receives u [nx][ny][nt] when the request completes */
+  int64_t id;                 /* caller's tag, returned in the completion           */
+} cnlos_request;
+
+typedef struct cnlos_completion {
+  int64_t id;
+  int32_t status;             /* cnlos_status of the request                        */
+  int32_t iters;              /* iterations accepted                                */
+  double energy;              /* final energy                                       */
+  double queued_steps;        /* steps between submit and admission                 */
+  double served_steps;        /* steps between admission and completion             */
+} cnlos_completion;
+
+/* arena: device memory for every slot group (256-byte aligned); slots: slots
+ * per group (1..64); rounds: iteration slots enqueued per group per step. */
+cnlos_status cnlos_server_create(void* arena_dev, uint64_t arena_bytes, int32_t slots,
+                                 int32_t rounds, cnlos_server** out);
+
+/* Queue a request (validated now; EINVAL/EUNSUPPORTED on a bad config or mask,
+ * ENOMEM if one slot group of its shape can never fit the arena). */
+cnlos_status cnlos_server_submit(cnlos_server* s, const cnlos_request* r);
+
+/* One scheduling step: retire, admit, advance.  active / queued (nullable)
+ * receive the number of requests in slots and waiting after the step.
+ * Synchronizes every group stream. */
+cnlos_status cnlos_server_step(cnlos_server* s, int32_t* active, int32_t* queued);
+
+/* Completions since the last poll (up to cap; *n receives the count). */
+cnlos_status cnlos_server_poll(cnlos_server* s, cnlos_completion* out, int32_t cap, int32_t* n);
+
+/* Arena bytes in use by slot groups, and the number of groups. */
+cnlos_status cnlos_server_usage(cnlos_server* s, uint64_t* bytes_used, int32_t* groups);
+
+/* Release everything (in-flight requests are dropped; the arena stays the
+ * caller's). */
+cnlos_status cnlos_server_destroy(cnlos_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,6 +60,16 @@ class Info(ctypes.Structure):
                 ("has_measurement", c_int32)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("cfg", Config), ("mask_host", POINTER(c_uint8)), ("tau0_dev", c_void_p),
+                ("out_dev", c_void_p), ("id", ctypes.c_int64)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", c_int32), ("iters", c_int32),
+                ("energy", c_double), ("queued_steps", c_double), ("served_steps", c_double)]
+
+
 class CnlosError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
@@ -108,6 +118,12 @@ def load() -> ctypes.CDLL:
         "cnlos_batch_run": ([P, c_int32, POINTER(Report)], c_int32),
         "cnlos_batch_run_many": ([POINTER(P), c_int32, c_int32, POINTER(POINTER(Report))], c_int32),
         "cnlos_batch_destroy": ([P], c_int32),
+        "cnlos_server_create": ([P, c_uint64, c_int32, c_int32, POINTER(P)], c_int32),
+        "cnlos_server_submit": ([P, POINTER(Request)], c_int32),
+        "cnlos_server_step": ([P, POINTER(c_int32), POINTER(c_int32)], c_int32),
+        "cnlos_server_poll": ([P, POINTER(Completion), c_int32, POINTER(c_int32)], c_int32),
+        "cnlos_server_usage": ([P, POINTER(c_uint64), POINTER(c_int32)], c_int32),
+        "cnlos_server_destroy": ([P], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -392,3 +408,67 @@ def run_many(batches, iters=0):
     ptrs = (POINTER(Report) * k)(*[ctypes.cast(a, POINTER(Report)) for a in arrs])
     st = lib.cnlos_batch_run_many(hs, k, int(iters), ptrs)
     return st, [[_report_dict(r) for r in a] for a in arrs]
+
+
+class Server:
+    """Continuous-batching request loop of the library: requests of any
+    supported shape are admitted into slot groups of their shape as slots and
+    arena memory free up; every step advances all groups, each on its own
+    stream.  The arena (HBM budget) is one device allocation made here."""
+
+    def __init__(self, arena_bytes, slots=8, rounds=8, device=None):
+        import torch
+        self._lib = load()
+        self._h = None
+        self.device = torch.device(device if device is not None else "cuda")
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        self._keep = {}
+        h = c_void_p()
+        check(self._lib.cnlos_server_create(c_void_p(self.arena.data_ptr()), c_uint64(self.arena.numel()),
+                                            int(slots), int(rounds), byref(h)))
+        self._h = h
+
+    def submit(self, cfg, mask, tau0, out, rid):
+        """Queue a request; tau0 and out (device float32 [nx][ny][nt]) are kept
+        alive here until the request completes."""
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        req = Request()
+        req.cfg = cfg
+        req.mask_host = m.ctypes.data_as(POINTER(c_uint8))
+        req.tau0_dev = c_void_p(tau0.data_ptr())
+        req.out_dev = c_void_p(out.data_ptr())
+        req.id = int(rid)
+        check(self._lib.cnlos_server_submit(self._h, byref(req)))
+        self._keep[int(rid)] = (tau0, out)
+
+    def step(self):
+        a, q = c_int32(), c_int32()
+        check(self._lib.cnlos_server_step(self._h, byref(a), byref(q)))
+        return a.value, q.value
+
+    def poll(self, cap=1024):
+        buf = (Completion * cap)()
+        n = c_int32()
+        check(self._lib.cnlos_server_poll(self._h, buf, cap, byref(n)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            out.append({f: getattr(c, f) for f, _ in Completion._fields_})
+            self._keep.pop(int(c.id), None)
+        return out
+
+    def usage(self):
+        b, g = c_uint64(), c_int32()
+        check(self._lib.cnlos_server_usage(self._h, byref(b), byref(g)))
+        return int(b.value), int(g.value)
+
+    def close(self):
+        if self._h is not None and self._h.value is not None:
+            self._lib.cnlos_server_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -54,10 +54,91 @@ cnlos_status destroy_problem(cnlos_problem* p);
 
 }  // namespace
 
+namespace {
+// progress of one scene within a run
+struct SceneRun {
+  int start = 0, goal = 0, rejects0 = 0;
+  bool active = false, stopped = false;
+  cnlos_status status = CNLOS_OK;
+};
+}  // namespace
+
 struct cnlos_batch {
   std::vector<cnlos_problem*> mem;
   size_t stride = 0;
   hipStream_t st = nullptr;
+};
+
+// ------------------------------------------------------------ serving state
+namespace {
+
+// First-fit allocator over the caller's device arena (offsets only).
+struct Arena {
+  uint8_t* base = nullptr;
+  uint64_t bytes = 0, used = 0;
+  std::vector<std::pair<uint64_t, uint64_t>> holes;   // (offset, size), sorted by offset
+  bool take(uint64_t n, uint64_t* off) {
+    for (size_t i = 0; i < holes.size(); ++i) {
+      if (holes[i].second < n) continue;
+      *off = holes[i].first;
+      holes[i].first += n;
+      holes[i].second -= n;
+      if (holes[i].second == 0) holes.erase(holes.begin() + i);
+      used += n;
+      return true;
+    }
+    return false;
+  }
+  void give(uint64_t off, uint64_t n) {
+    used -= n;
+    size_t i = 0;
+    while (i < holes.size() && holes[i].first < off) ++i;
+    holes.insert(holes.begin() + i, {off, n});
+    if (i + 1 < holes.size() && holes[i].first + holes[i].second == holes[i + 1].first) {
+      holes[i].second += holes[i + 1].second;
+      holes.erase(holes.begin() + i + 1);
+    }
+    if (i > 0 && holes[i - 1].first + holes[i - 1].second == holes[i].first) {
+      holes[i - 1].second += holes[i].second;
+      holes.erase(holes.begin() + i);
+    }
+  }
+};
+
+struct SrvReq {
+  cnlos_request r;
+  std::vector<uint8_t> mask;
+  long long submitted = 0;
+};
+
+// A slot group: a batch whose members change while it runs.
+struct SrvGroup {
+  cnlos_config proto;
+  size_t stride = 0;
+  int K = 0;
+  uint64_t off = 0;
+  hipStream_t st = nullptr;
+  cnlos_problem* layout = nullptr;       // buffer layout of slot 0 (no device state of its own)
+  std::vector<cnlos_problem*> slot;      // occupant per slot, or null
+  std::vector<SrvReq> req;
+  std::vector<SceneRun> run;
+  std::vector<long long> admitted;
+  int occupied() const {
+    int k = 0;
+    for (cnlos_problem* m : slot) k += m != nullptr;
+    return k;
+  }
+};
+
+}  // namespace
+
+struct cnlos_server {
+  Arena arena;
+  int K = 8, rounds = 8;
+  long long step_no = 0;
+  std::vector<SrvReq> queue;
+  std::vector<SrvGroup*> groups;
+  std::vector<cnlos_completion> done;
 };
 
 struct cnlos_problem {
@@ -350,6 +431,15 @@ cnlos_status ctl_push(cnlos_problem* p) {
   return CNLOS_OK;
 }
 
+// fields that the kernels of one launch share across a batch
+bool same_shared(const cnlos_config& b, const cnlos_config& a) {
+  return b.nx == a.nx && b.ny == a.ny && b.nt == a.nt && b.model == a.model && b.phi == a.phi &&
+         b.falloff == a.falloff && b.a_u == a.a_u && b.b_u == a.b_u && b.a_tau == a.a_tau &&
+         b.b_tau == a.b_tau && b.warm_a == a.warm_a && b.warm_b == a.warm_b && b.mu == a.mu &&
+         b.mu1 == a.mu1 && b.mu2 == a.mu2 && b.mu3 == a.mu3 && b.lambda == a.lambda &&
+         b.eta_curv == a.eta_curv && b.backtracking == a.backtracking;
+}
+
 inline Vol fixed(const float* q) { return Vol{{const_cast<float*>(q), nullptr, nullptr}, -1}; }
 
 // One padded convolution of the problem (forward or adjoint).
@@ -623,12 +713,6 @@ struct Group {
   Batch bt = kSingle;
 };
 
-struct SceneRun {
-  int start = 0, goal = 0, rejects0 = 0;
-  bool active = false, stopped = false;
-  cnlos_status status = CNLOS_OK;
-};
-
 // pull every member's controller with one stream synchronization
 cnlos_status group_pull(Group& g) {
   cnlos_problem* p = g.lead;
@@ -647,119 +731,150 @@ cnlos_status group_push(Group& g) {
   return CNLOS_OK;
 }
 
-// Run every scene of every group to its goal (iters > 0: that many more
-// iterations; else the configured count).  Groups run on their own streams:
-// each round enqueues a batch of iteration slots on every group before it
-// waits for any, so the groups' work overlaps on the device.
-cnlos_status run_groups(std::vector<Group>& gs, int32_t iters, std::vector<cnlos_report*>* reps) {
-  std::vector<std::vector<SceneRun>> runs(gs.size());
-  for (size_t gi = 0; gi < gs.size(); ++gi) {
-    Group& g = gs[gi];
-    cnlos_status s = group_pull(g);
-    if (s != CNLOS_OK) return s;
-    runs[gi].resize(g.mem.size());
+// Start a run of a group's members: goal per member (iters > 0: that many
+// more iterations; else the configured count), written to the controllers.
+cnlos_status group_start(Group& g, std::vector<SceneRun>& runs, int32_t iters) {
+  cnlos_status s = group_pull(g);
+  if (s != CNLOS_OK) return s;
+  runs.assign(g.mem.size(), SceneRun());
+  for (size_t i = 0; i < g.mem.size(); ++i) {
+    cnlos_problem* m = g.mem[i];
+    const cnlos_config& c = m->cfg;
+    DevCtl& h = *m->ctl_host;
+    SceneRun& r = runs[i];
+    const int planned = c.max_iters + (c.model == CNLOS_MODEL_DUAL ? c.init_iters : 0);
+    r.start = h.iter;
+    r.goal = iters > 0 ? h.iter + iters : planned;
+    r.rejects0 = h.bt_rejects;
+    r.active = h.iter < r.goal;
+    h.target = r.goal;
+    h.reject = 0;
+    h.halt = 0;
+    h.reason = HR_NONE;
+    h.trials = 0;
+  }
+  return group_push(g);
+}
+
+// Enqueue up to `batch` iteration slots for the group's active members (the
+// sequences each slot needs follow from the members' last known state).
+// Sets *enqueued to whether anything was enqueued.
+cnlos_status group_enqueue(Group& g, const std::vector<SceneRun>& runs, int batch, bool* enqueued) {
+  cnlos_problem* p = g.lead;
+  int need = 0, to_s1end = 0x7fffffff;
+  bool s1 = false, s2 = false;
+  for (size_t i = 0; i < g.mem.size(); ++i) {
+    if (!runs[i].active) continue;
+    const DevCtl& h = *g.mem[i]->ctl_host;
+    need = std::max(need, runs[i].goal - h.iter);
+    if (h.stage == 1 && h.iter < h.stage1_end) {
+      s1 = true;
+      to_s1end = std::min(to_s1end, h.stage1_end - h.iter);
+    } else {
+      s2 = true;
+    }
+  }
+  *enqueued = need > 0;
+  if (need <= 0) return CNLOS_OK;
+  int nb = std::min(batch, need);
+  // a warm-start batch ends where the first scene reaches the hand-over
+  if (s1 && !s2) nb = std::min(nb, to_s1end);
+  for (int j = 0; j < nb; ++j) {
+    int seq = 0;
     for (size_t i = 0; i < g.mem.size(); ++i) {
-      cnlos_problem* m = g.mem[i];
-      const cnlos_config& c = m->cfg;
-      DevCtl& h = *m->ctl_host;
-      SceneRun& r = runs[gi][i];
-      const int planned = c.max_iters + (c.model == CNLOS_MODEL_DUAL ? c.init_iters : 0);
-      r.start = h.iter;
-      r.goal = iters > 0 ? h.iter + iters : planned;
-      r.rejects0 = h.bt_rejects;
-      r.active = h.iter < r.goal;
-      h.target = r.goal;
-      h.reject = 0;
+      if (!runs[i].active) continue;
+      const DevCtl& h = *g.mem[i]->ctl_host;
+      if (h.stage == 1 && h.iter < h.stage1_end) {
+        seq |= SEQ_S1;
+        if (p->cfg.model == CNLOS_MODEL_DUAL && h.iter + j + 1 >= h.stage1_end) seq |= SEQ_TR | SEQ_S2;
+      } else if (h.stage == 1) {
+        seq |= SEQ_TR | SEQ_S2;       // warm start done, hand-over pending
+      } else {
+        seq |= SEQ_S2;
+      }
+    }
+    cnlos_status s = enqueue_slot(p, g.bt, seq);
+    if (s != CNLOS_OK) return s;
+  }
+  return CNLOS_OK;
+}
+
+// Wait for the group, then retire members that reached their goal, stopped
+// early or failed (their halt is cleared for later calls).
+cnlos_status group_absorb(Group& g, std::vector<SceneRun>& runs) {
+  cnlos_status s = group_pull(g);
+  if (s != CNLOS_OK) return s;
+  bool dirty = false;
+  for (size_t i = 0; i < g.mem.size(); ++i) {
+    SceneRun& r = runs[i];
+    cnlos_problem* m = g.mem[i];
+    DevCtl& h = *m->ctl_host;
+    m->iter_host = h.iter;
+    if (!r.active) continue;
+    if (h.halt) {
+      const int reason = h.reason;
+      // parked: the halt is cleared for later calls, the target keeps the
+      // member out of the rest of this run's launches
       h.halt = 0;
       h.reason = HR_NONE;
       h.trials = 0;
+      h.target = h.iter;
+      dirty = true;
+      r.active = false;
+      if (reason == HR_STOP) {
+        r.stopped = true;
+      } else if (reason == HR_BACKTRACK) {
+        r.status = fail(CNLOS_EBACKTRACK, "backtracking found no acceptable step");
+      } else {
+        r.status = fail(CNLOS_ENONFINITE, "non-finite residual or energy");
+      }
+    } else if (h.iter >= r.goal) {
+      r.active = false;
     }
-    s = group_push(g);
+  }
+  if (dirty) return group_push(g);
+  return CNLOS_OK;
+}
+
+void fill_report(const cnlos_problem* m, const SceneRun& r, cnlos_report* out) {
+  const DevCtl& h = *m->ctl_host;
+  out->iters_done = h.iter - r.start;
+  out->total_iters = h.iter;
+  out->stopped_early = r.stopped ? 1 : 0;
+  out->bt_rejects = h.bt_rejects - r.rejects0;
+  out->L_final = h.L;
+  out->energy = h.last_energy;
+  out->primal_res = h.last_primal;
+  out->dual_res = h.last_dual;
+  out->status = r.status;
+  out->reserved = 0;
+}
+
+// Run every scene of every group to its goal.  Groups run on their own
+// streams: each round enqueues a batch of iteration slots on every group
+// before it waits for any, so the groups' work overlaps on the device.
+cnlos_status run_groups(std::vector<Group>& gs, int32_t iters, std::vector<cnlos_report*>* reps) {
+  std::vector<std::vector<SceneRun>> runs(gs.size());
+  for (size_t gi = 0; gi < gs.size(); ++gi) {
+    cnlos_status s = group_start(gs[gi], runs[gi], iters);
     if (s != CNLOS_OK) return s;
   }
   int batch = 2;
   for (;;) {
     bool any = false;
+    std::vector<char> busy(gs.size(), 0);
     for (size_t gi = 0; gi < gs.size(); ++gi) {
-      Group& g = gs[gi];
-      cnlos_problem* p = g.lead;
-      // the slots' sequences from the members' last known iteration counts
-      int lo1 = 0x7fffffff, need = 0;
-      bool s1 = false, s2 = false;
-      int to_s1end = 0x7fffffff;
-      for (size_t i = 0; i < g.mem.size(); ++i) {
-        if (!runs[gi][i].active) continue;
-        const DevCtl& h = *g.mem[i]->ctl_host;
-        need = std::max(need, runs[gi][i].goal - h.iter);
-        if (h.stage == 1 && h.iter < h.stage1_end) {
-          s1 = true;
-          lo1 = std::min(lo1, h.iter);
-          to_s1end = std::min(to_s1end, h.stage1_end - h.iter);
-        } else {
-          s2 = true;
-        }
-      }
-      if (need <= 0) continue;
-      any = true;
-      int nb = std::min(batch, need);
-      // a warm-start batch ends where the first scene reaches the hand-over
-      if (s1 && !s2) nb = std::min(nb, to_s1end);
-      for (int j = 0; j < nb; ++j) {
-        int seq = 0;
-        for (size_t i = 0; i < g.mem.size(); ++i) {
-          if (!runs[gi][i].active) continue;
-          const DevCtl& h = *g.mem[i]->ctl_host;
-          if (h.stage == 1 && h.iter < h.stage1_end) {
-            seq |= SEQ_S1;
-            if (p->cfg.model == CNLOS_MODEL_DUAL && h.iter + j + 1 >= h.stage1_end) seq |= SEQ_TR | SEQ_S2;
-          } else if (h.stage == 1) {
-            seq |= SEQ_TR | SEQ_S2;       // warm start done, hand-over pending
-          } else {
-            seq |= SEQ_S2;
-          }
-        }
-        (void)lo1;
-        cnlos_status s = enqueue_slot(p, g.bt, seq);
-        if (s != CNLOS_OK) return s;
-      }
+      bool e = false;
+      cnlos_status s = group_enqueue(gs[gi], runs[gi], batch, &e);
+      if (s != CNLOS_OK) return s;
+      busy[gi] = e;
+      any = any || e;
     }
     if (!any) break;
     for (size_t gi = 0; gi < gs.size(); ++gi) {
-      Group& g = gs[gi];
-      bool act = false;
-      for (const SceneRun& r : runs[gi]) act = act || r.active;
-      if (!act) continue;
-      cnlos_status s = group_pull(g);
+      if (!busy[gi]) continue;
+      cnlos_status s = group_absorb(gs[gi], runs[gi]);
       if (s != CNLOS_OK) return s;
-      bool dirty = false;
-      for (size_t i = 0; i < g.mem.size(); ++i) {
-        SceneRun& r = runs[gi][i];
-        if (!r.active) continue;
-        cnlos_problem* m = g.mem[i];
-        DevCtl& h = *m->ctl_host;
-        m->iter_host = h.iter;
-        if (h.halt) {
-          const int reason = h.reason;
-          h.halt = 0;
-          h.reason = HR_NONE;
-          h.trials = 0;
-          dirty = true;
-          r.active = false;
-          if (reason == HR_STOP) {
-            r.stopped = true;
-          } else if (reason == HR_BACKTRACK) {
-            r.status = fail(CNLOS_EBACKTRACK, "backtracking found no acceptable step");
-          } else {
-            r.status = fail(CNLOS_ENONFINITE, "non-finite residual or energy");
-          }
-        } else if (h.iter >= r.goal) {
-          r.active = false;
-        }
-      }
-      if (dirty) {
-        s = group_push(g);
-        if (s != CNLOS_OK) return s;
-      }
     }
     if (batch < 64) batch *= 2;
   }
@@ -769,21 +884,10 @@ cnlos_status run_groups(std::vector<Group>& gs, int32_t iters, std::vector<cnlos
     for (size_t i = 0; i < gs[gi].mem.size(); ++i, ++flat) {
       const SceneRun& r = runs[gi][i];
       cnlos_problem* m = gs[gi].mem[i];
-      const DevCtl& h = *m->ctl_host;
-      m->iter_host = h.iter;
+      m->iter_host = m->ctl_host->iter;
       if (result == CNLOS_OK && r.status != CNLOS_OK) result = r.status;
       cnlos_report* out = (reps && flat < reps->size()) ? (*reps)[flat] : nullptr;
-      if (!out) continue;
-      out->iters_done = h.iter - r.start;
-      out->total_iters = h.iter;
-      out->stopped_early = r.stopped ? 1 : 0;
-      out->bt_rejects = h.bt_rejects - r.rejects0;
-      out->L_final = h.L;
-      out->energy = h.last_energy;
-      out->primal_res = h.last_primal;
-      out->dual_res = h.last_dual;
-      out->status = r.status;
-      out->reserved = 0;
+      if (out) fill_report(m, r, out);
     }
   return result;
 }
@@ -1307,14 +1411,7 @@ cnlos_status cnlos_batch_create(const cnlos_config* cfgs, int32_t count,
     cnlos_status s = cnlos_validate(&cfgs[i], masks_host[i]);
     if (s != CNLOS_OK) return s;
     if (!masks_host[i]) return fail(CNLOS_EINVAL, "mask is NULL");
-    const cnlos_config& b = cfgs[i];
-    const bool same = b.nx == a.nx && b.ny == a.ny && b.nt == a.nt && b.model == a.model &&
-                      b.phi == a.phi && b.falloff == a.falloff && b.a_u == a.a_u && b.b_u == a.b_u &&
-                      b.a_tau == a.a_tau && b.b_tau == a.b_tau && b.warm_a == a.warm_a &&
-                      b.warm_b == a.warm_b && b.mu == a.mu && b.mu1 == a.mu1 && b.mu2 == a.mu2 &&
-                      b.mu3 == a.mu3 && b.lambda == a.lambda && b.eta_curv == a.eta_curv &&
-                      b.backtracking == a.backtracking;
-    if (!same) return fail(CNLOS_EINVAL, "batch member " + std::to_string(i) + " differs in a shared field");
+    if (!same_shared(cfgs[i], a)) return fail(CNLOS_EINVAL, "batch member " + std::to_string(i) + " differs in a shared field");
   }
   if (a.model == CNLOS_MODEL_OPERATOR) return fail(CNLOS_EINVAL, "a batch needs a solver model");
   const size_t stride = carve(nullptr, a, nullptr);
@@ -1389,6 +1486,289 @@ cnlos_status cnlos_batch_destroy(cnlos_batch* b) {
   if (!b) return CNLOS_OK;
   for (cnlos_problem* m : b->mem) destroy_problem(m);
   delete b;
+  return CNLOS_OK;
+}
+
+// ---------------------------------------------------------------- serving
+}  // extern "C"
+
+namespace {
+
+cnlos_status srv_fail(cnlos_status st, const std::string& msg) { return fail(st, msg); }
+
+// a group's device state starts parked: every slot's controller halted
+cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup** out) {
+  *out = nullptr;
+  const size_t stride = carve(nullptr, cfg, nullptr);
+  uint64_t off = 0;
+  if (!sv->arena.take((uint64_t)stride * sv->K, &off)) return CNLOS_ENOMEM;
+  SrvGroup* g = new (std::nothrow) SrvGroup();
+  if (!g) {
+    sv->arena.give(off, (uint64_t)stride * sv->K);
+    return srv_fail(CNLOS_ENOMEM, "host allocation failed");
+  }
+  g->proto = cfg;
+  g->stride = stride;
+  g->K = sv->K;
+  g->off = off;
+  g->slot.assign(g->K, nullptr);
+  g->req.resize(g->K);
+  g->run.resize(g->K);
+  g->admitted.assign(g->K, 0);
+  cnlos_problem* p = new (std::nothrow) cnlos_problem();
+  if (!p || hipStreamCreate(&g->st) != hipSuccess) {
+    delete p;
+    sv->arena.give(off, (uint64_t)stride * sv->K);
+    delete g;
+    return srv_fail(CNLOS_EHIP, "stream creation failed");
+  }
+  uint8_t* ws = sv->arena.base + off;
+  p->cfg = cfg;
+  p->logn = ilog2(cfg.nx);
+  p->logm = ilog2(cfg.nt);
+  p->V = (size_t)cfg.nx * cfg.nx * cfg.nt;
+  p->nn = cfg.nx * cfg.nx;
+  p->st = g->st;
+  p->ws = ws;
+  p->ws_bytes = stride;
+  p->carve_bytes = carve(p, cfg, ws);
+  p->nb_conv = conv_blocks(p->logn, p->logm);
+  p->nb_solve = solve_blocks(p->logn, p->logm);
+  p->nb_sten = stencil_blocks(p->logn, p->logm);
+  p->tb.tw_t = p->tw_t;
+  p->tb.tw_xy = p->tw_xy;
+  p->tb.twc_t = p->twc_t;
+  p->tb.twc_xy = p->twc_xy;
+  p->tb.S.rows = p->srows;
+  p->tb.S.rvals = p->srvals;
+  p->tb.S.cols = p->scols;
+  p->tb.S.cvals = p->scvals;
+  p->tb.sig_xy = p->sig_xy;
+  p->tb.sig_t = p->sig_t;
+  p->tb.hq = p->hq;
+  g->layout = p;
+  DevCtl parked;
+  memset(&parked, 0, sizeof(parked));
+  parked.halt = 1;
+  for (int i = 0; i < g->K; ++i)
+    if (hipMemcpyAsync(ws + (size_t)i * stride, &parked, sizeof(DevCtl), hipMemcpyHostToDevice,
+                       g->st) != hipSuccess)
+      return srv_fail(CNLOS_EHIP, "controller initialization failed");
+  if (hipStreamSynchronize(g->st) != hipSuccess) return srv_fail(CNLOS_EHIP, "stream failed");
+  sv->groups.push_back(g);
+  *out = g;
+  return CNLOS_OK;
+}
+
+void srv_group_free(cnlos_server* sv, SrvGroup* g) {
+  for (cnlos_problem* m : g->slot)
+    if (m) destroy_problem(m);
+  if (g->st) {
+    (void)hipStreamSynchronize(g->st);
+    (void)hipStreamDestroy(g->st);
+  }
+  delete g->layout;
+  sv->arena.give(g->off, (uint64_t)g->stride * g->K);
+  delete g;
+}
+
+void srv_complete(cnlos_server* sv, SrvGroup* g, int i, cnlos_status st) {
+  cnlos_completion c{};
+  c.id = g->req[i].r.id;
+  c.status = st;
+  cnlos_problem* m = g->slot[i];
+  if (m && m->ctl_host) {
+    c.iters = m->ctl_host->iter;
+    c.energy = m->ctl_host->last_energy;
+  }
+  c.queued_steps = (double)(g->admitted[i] - g->req[i].submitted);
+  c.served_steps = (double)(sv->step_no - g->admitted[i]);
+  sv->done.push_back(c);
+  if (m) destroy_problem(m);
+  g->slot[i] = nullptr;
+}
+
+// place request q into free slot i of group g: tables, H^ and step constants
+// for its geometry, its measurement, and a fresh run toward its budget
+cnlos_status srv_admit(cnlos_server* sv, SrvGroup* g, int i, SrvReq& q) {
+  cnlos_problem* m = nullptr;
+  g->req[i] = q;
+  g->admitted[i] = sv->step_no;
+  cnlos_status st = create_into(&q.r.cfg, q.mask.data(), sv->arena.base + g->off + (size_t)i * g->stride,
+                                g->stride, g->st, &m);
+  if (m) m->in_batch = true;
+  g->slot[i] = m;
+  if (st == CNLOS_OK) st = cnlos_set_measurement(m, q.r.tau0_dev);
+  if (st == CNLOS_OK) {
+    Group one;
+    one.lead = m;
+    one.mem.push_back(m);
+    std::vector<SceneRun> runs;
+    st = group_start(one, runs, 0);
+    if (st == CNLOS_OK) g->run[i] = runs[0];
+  }
+  if (st != CNLOS_OK) {
+    // park the slot again before giving it back
+    if (m && !m->poisoned && m->ctl_host) {
+      m->ctl_host->halt = 1;
+      (void)hipMemcpyAsync(m->ctl, m->ctl_host, sizeof(DevCtl), hipMemcpyHostToDevice, g->st);
+      (void)hipStreamSynchronize(g->st);
+    }
+    srv_complete(sv, g, i, st);
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+cnlos_status cnlos_server_create(void* arena_dev, uint64_t arena_bytes, int32_t slots,
+                                 int32_t rounds, cnlos_server** out) {
+  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!arena_dev || ((uintptr_t)arena_dev) % kAlign) return fail(CNLOS_EINVAL, "arena must be non-NULL and 256-byte aligned");
+  if (slots < 1 || slots > 64) return fail(CNLOS_EINVAL, "slots must be in [1, 64]");
+  if (rounds < 1) return fail(CNLOS_EINVAL, "rounds must be >= 1");
+  cnlos_server* sv = new (std::nothrow) cnlos_server();
+  if (!sv) return fail(CNLOS_ENOMEM, "host allocation failed");
+  sv->arena.base = (uint8_t*)arena_dev;
+  sv->arena.bytes = arena_bytes & ~(uint64_t)(kAlign - 1);
+  sv->arena.holes.push_back({0, sv->arena.bytes});
+  sv->K = slots;
+  sv->rounds = rounds;
+  *out = sv;
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_submit(cnlos_server* sv, const cnlos_request* r) {
+  if (!sv || !r) return fail(CNLOS_EINVAL, "NULL argument");
+  cnlos_status st = cnlos_validate(&r->cfg, r->mask_host);
+  if (st != CNLOS_OK) return st;
+  if (!r->mask_host || !r->tau0_dev || !r->out_dev) return fail(CNLOS_EINVAL, "mask, measurement and output are required");
+  if (r->cfg.model == CNLOS_MODEL_OPERATOR) return fail(CNLOS_EINVAL, "a request needs a solver model");
+  if ((uint64_t)carve(nullptr, r->cfg, nullptr) * sv->K > sv->arena.bytes)
+    return fail(CNLOS_ENOMEM, "a slot group of this shape does not fit the arena");
+  SrvReq q;
+  q.r = *r;
+  q.mask.assign(r->mask_host, r->mask_host + (size_t)r->cfg.nx * r->cfg.ny);
+  q.r.mask_host = nullptr;
+  q.submitted = sv->step_no;
+  sv->queue.push_back(std::move(q));
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queued) {
+  if (!sv) return fail(CNLOS_EINVAL, "server is NULL");
+  // admission, first come first served within each shape
+  std::vector<SrvReq> wait;
+  for (SrvReq& q : sv->queue) {
+    SrvGroup* g = nullptr;
+    int free_slot = -1;
+    for (SrvGroup* c : sv->groups) {
+      if (!same_shared(c->proto, q.r.cfg)) continue;
+      for (int i = 0; i < c->K && free_slot < 0; ++i)
+        if (!c->slot[i]) free_slot = i;
+      if (free_slot >= 0) {
+        g = c;
+        break;
+      }
+    }
+    if (!g) {
+      cnlos_status st = srv_group_new(sv, q.r.cfg, &g);
+      if (st == CNLOS_ENOMEM && !g) {
+        // give back the arena of idle groups and try once more
+        for (size_t k = 0; k < sv->groups.size();) {
+          if (sv->groups[k]->occupied() == 0) {
+            srv_group_free(sv, sv->groups[k]);
+            sv->groups.erase(sv->groups.begin() + k);
+          } else {
+            ++k;
+          }
+        }
+        st = srv_group_new(sv, q.r.cfg, &g);
+      }
+      if (st == CNLOS_ENOMEM && !g) {
+        wait.push_back(std::move(q));
+        continue;
+      }
+      if (st != CNLOS_OK) return st;
+      free_slot = 0;
+    }
+    srv_admit(sv, g, free_slot, q);
+  }
+  sv->queue.swap(wait);
+  // advance every group with occupants; all groups are enqueued before any wait
+  std::vector<Group> views(sv->groups.size());
+  std::vector<std::vector<SceneRun>> runs(sv->groups.size());
+  std::vector<std::vector<int>> idx(sv->groups.size());
+  std::vector<char> busy(sv->groups.size(), 0);
+  for (size_t k = 0; k < sv->groups.size(); ++k) {
+    SrvGroup* g = sv->groups[k];
+    Group& v = views[k];
+    v.lead = g->layout;
+    v.bt = Batch{g->K, g->stride, G_NONE};
+    for (int i = 0; i < g->K; ++i)
+      if (g->slot[i]) {
+        v.mem.push_back(g->slot[i]);
+        runs[k].push_back(g->run[i]);
+        idx[k].push_back(i);
+      }
+    if (v.mem.empty()) continue;
+    bool e = false;
+    cnlos_status st = group_enqueue(v, runs[k], sv->rounds, &e);
+    if (st != CNLOS_OK) return st;
+    busy[k] = 1;
+  }
+  for (size_t k = 0; k < sv->groups.size(); ++k) {
+    if (!busy[k]) continue;
+    SrvGroup* g = sv->groups[k];
+    cnlos_status st = group_absorb(views[k], runs[k]);
+    if (st != CNLOS_OK) return st;
+    for (size_t j = 0; j < idx[k].size(); ++j) g->run[idx[k][j]] = runs[k][j];
+  }
+  ++sv->step_no;
+  // retire finished requests: copy the volume out, free the slot
+  int act = 0;
+  for (SrvGroup* g : sv->groups) {
+    for (int i = 0; i < g->K; ++i) {
+      cnlos_problem* m = g->slot[i];
+      if (!m) continue;
+      if (g->run[i].active) {
+        ++act;
+        continue;
+      }
+      cnlos_status st = g->run[i].status;
+      if (st == CNLOS_OK) st = cnlos_get_volume(m, g->req[i].r.out_dev);
+      if (hipStreamSynchronize(g->st) != hipSuccess && st == CNLOS_OK) st = fail(CNLOS_EHIP, "stream failed");
+      srv_complete(sv, g, i, st);
+    }
+  }
+  if (active) *active = act;
+  if (queued) *queued = (int32_t)sv->queue.size();
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_poll(cnlos_server* sv, cnlos_completion* out, int32_t cap, int32_t* n) {
+  if (!sv || !n || (cap > 0 && !out)) return fail(CNLOS_EINVAL, "NULL argument");
+  const int k = std::min<int>(cap, (int)sv->done.size());
+  for (int i = 0; i < k; ++i) out[i] = sv->done[i];
+  sv->done.erase(sv->done.begin(), sv->done.begin() + k);
+  *n = k;
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_usage(cnlos_server* sv, uint64_t* bytes_used, int32_t* groups) {
+  if (!sv) return fail(CNLOS_EINVAL, "server is NULL");
+  if (bytes_used) *bytes_used = sv->arena.used;
+  if (groups) *groups = (int32_t)sv->groups.size();
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_destroy(cnlos_server* sv) {
+  if (!sv) return CNLOS_OK;
+  for (SrvGroup* g : sv->groups) srv_group_free(sv, g);
+  delete sv;
   return CNLOS_OK;
 }
 

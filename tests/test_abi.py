@@ -23,7 +23,7 @@ def header_functions():
 def test_library_exports_every_declared_function():
     lib = C.load()
     names = header_functions()
-    assert len(names) == 27
+    assert len(names) == 33
     for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
@@ -178,3 +178,31 @@ def test_batch_members_may_differ_in_geometry_and_budget():
     empty = np.zeros((16, 16), np.uint8)
     assert _batch_create_status([a, b], [mask, empty]) == C.EINVAL
     assert "mask" in C.last_error()
+
+
+def test_server_submit_validates_without_a_device_call():
+    lib = C.load()
+    h = ctypes.c_void_p()
+    # a non-NULL, aligned fake arena: creating the server touches no device memory
+    assert lib.cnlos_server_create(ctypes.c_void_p(1 << 20), ctypes.c_uint64(1 << 30), 4, 4,
+                                   ctypes.byref(h)) == C.OK
+    mask = np.ones((16, 16), np.uint8)
+    req = C.Request()
+    req.cfg = C.default_config()
+    req.mask_host = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    req.tau0_dev = ctypes.c_void_p(256)
+    req.out_dev = ctypes.c_void_p(512)
+    req.cfg.nt = 100
+    assert lib.cnlos_server_submit(h, ctypes.byref(req)) == C.EUNSUPPORTED
+    req.cfg = C.default_config(model=C.MODEL_OPERATOR)
+    assert lib.cnlos_server_submit(h, ctypes.byref(req)) == C.EINVAL
+    req.cfg = C.default_config(nx=128, ny=128, nt=2048, model=C.MODEL_DUAL)
+    assert lib.cnlos_server_submit(h, ctypes.byref(req)) == C.ENOMEM     # never fits 1 GiB
+    req.cfg = C.default_config()
+    assert lib.cnlos_server_submit(h, ctypes.byref(req)) == C.OK
+    b, g = ctypes.c_uint64(), ctypes.c_int32()
+    assert lib.cnlos_server_usage(h, ctypes.byref(b), ctypes.byref(g)) == C.OK
+    assert b.value == 0 and g.value == 0
+    assert lib.cnlos_server_destroy(h) == C.OK
+    assert lib.cnlos_server_create(ctypes.c_void_p(1 << 20), ctypes.c_uint64(1 << 30), 0, 4,
+                                   ctypes.byref(h)) == C.EINVAL

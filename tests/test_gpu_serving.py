@@ -1,0 +1,105 @@
+"""Serving with continuous batching through the C ABI: requests of mixed
+shapes arrive while others run, are admitted into slot groups as slots and
+arena memory free up, and each result must equal the same request run alone
+bit for bit (one launch serves every slot of a group; reductions are in a
+fixed order per scene)."""
+import numpy as np
+import pytest
+
+from paper_2301_00406_amd import cnlos as C
+from paper_2301_00406_amd import scenes
+from tests.gpu_helpers import need_gpu, say, synth_measurement, to_dev
+
+pytestmark = pytest.mark.gpu
+
+OBJ = dict(a_u=5e-5, b_u=5e-5, mu=0.1)
+DUAL = dict(a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, warm_a=1.5e-4, warm_b=4e-5, mu=0.1,
+            lam=200.0)
+
+
+def _requests(torch):
+    """Uneven requests: three shapes, both models, per-request masks, noise
+    levels and iteration budgets."""
+    out = []
+    shapes = [(16, 128, "object"), (32, 256, "dual"), (16, 256, "object"), (32, 256, "dual"),
+              (16, 128, "object"), (16, 256, "object"), (32, 256, "dual"), (16, 128, "object")]
+    for i, (n, m, model) in enumerate(shapes):
+        sc = scenes.scene_custom(n, m, 3000 + i, wall=1.0, bin_ps=32.0 * 128 / m,
+                                 density=0.2 + 0.05 * i, peak=5.0 + 5 * i)
+        raw = synth_measurement(sc, 3100 + i)
+        if model == "dual":
+            cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=1.0, wall_h_m=1.0, bin_ps=sc.bin_ps,
+                                   model=C.MODEL_DUAL, init_iters=3 + i % 3, max_iters=6 + i,
+                                   **DUAL)
+        else:
+            cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=1.0, wall_h_m=1.0, bin_ps=sc.bin_ps,
+                                   model=C.MODEL_OBJECT, max_iters=12 + 2 * i, **OBJ)
+        out.append((cfg, sc.mask, to_dev(torch, raw)))
+    return out
+
+
+def _alone(torch, cfg, mask, raw):
+    P = C.Problem(cfg, mask)
+    P.set_measurement(raw)
+    P.run()
+    u = P.volume().cpu().numpy()
+    P.close()
+    return u
+
+
+def _serve(torch, reqs, arena_bytes, slots, rounds, arrivals):
+    """arrivals[i]: the step before which request i is submitted."""
+    S = C.Server(arena_bytes, slots=slots, rounds=rounds)
+    outs = [torch.zeros(tuple(r[2].shape), dtype=torch.float32, device="cuda") for r in reqs]
+    done = {}
+    step = 0
+    max_groups = 0
+    while len(done) < len(reqs):
+        for i, a in enumerate(arrivals):
+            if a == step:
+                cfg, mask, raw = reqs[i]
+                S.submit(cfg, mask, raw, outs[i], i)
+        S.step()
+        max_groups = max(max_groups, S.usage()[1])
+        for c in S.poll():
+            done[c["id"]] = c
+        step += 1
+        assert step < 2000, "serving loop did not drain"
+    S.close()
+    return outs, done, max_groups
+
+
+def test_served_results_equal_alone_runs_bitwise():
+    torch = need_gpu()
+    say("serving: 8 requests, 3 shapes, staggered arrivals, 2 slots per group")
+    reqs = _requests(torch)
+    arrivals = [0, 0, 1, 2, 2, 4, 6, 7]
+    outs, done, groups = _serve(torch, reqs, 4 << 30, slots=2, rounds=3, arrivals=arrivals)
+    assert groups >= 2
+    for i, (cfg, mask, raw) in enumerate(reqs):
+        c = done[i]
+        assert c["status"] == C.OK, (i, c)
+        planned = cfg.max_iters + (cfg.init_iters if cfg.model == C.MODEL_DUAL else 0)
+        assert c["iters"] == planned
+        ref = _alone(torch, cfg, mask, raw)
+        assert np.array_equal(outs[i].cpu().numpy(), ref), f"request {i} differs from its alone run"
+
+
+def test_admission_waits_for_arena_memory():
+    """An arena that holds one slot group of the largest shape and nothing
+    beside it: requests of other shapes wait in the queue until that group
+    drains, then run."""
+    torch = need_gpu()
+    say("serving: arena for one large group at a time")
+    r = _requests(torch)
+    reqs = [r[1], r[0], r[2]]            # 32x256 dual first, then 16x128 and 16x256 object
+    large = C.workspace_bytes(reqs[0][0])
+    arena = 2 * large + (1 << 20)        # two slots of the large shape, no room for another group
+    assert all(2 * C.workspace_bytes(q[0]) > (1 << 20) for q in reqs[1:])
+    outs, done, groups = _serve(torch, reqs, arena, slots=2, rounds=4, arrivals=[0, 0, 0])
+    for i, (cfg, mask, raw) in enumerate(reqs):
+        assert done[i]["status"] == C.OK
+        assert np.array_equal(outs[i].cpu().numpy(), _alone(torch, cfg, mask, raw))
+    # the small requests were admitted only once the large group had drained
+    for i in (1, 2):
+        assert done[i]["queued_steps"] >= done[0]["served_steps"]
