@@ -44,12 +44,16 @@ __device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
 // Spectrum planes are exchanged with global memory through an LDS staging
 // tile [kt][J], so every plane access is a 64-byte segment.
 // ---------------------------------------------------------------------------
+// Columns per block of a t pass of length 2^logf: 16 (128-byte plane
+// segments) while the staging tile fits LDS next to the tables, then fewer.
+constexpr int t_columns(int logf) { return logf <= 9 ? 16 : (logf == 10 ? 8 : 4); }
+
 template <int LOGF>
 struct TGeo {                                 // transform of length F = 2^LOGF
   static constexpr int F = 1 << LOGF;
   static constexpr int G = (F / 2) < 64 ? (F / 2) : 64;   // lanes per column
   static constexpr int E = F / G;                         // elements per lane (>= 2)
-  static constexpr int J = LOGF >= 11 ? 4 : 8;            // columns per block
+  static constexpr int J = t_columns(LOGF);               // columns per block
   static constexpr int NT = J * G;
 };
 
@@ -925,8 +929,8 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
 // launchers
 // ---------------------------------------------------------------------------
 // blocks of the t passes (their partial sums are indexed by block)
-int conv_blocks(int logn, int logm) { return (1 << (2 * logn)) / (logm >= 11 ? 4 : 8); }
-int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / (logm - 1 >= 11 ? 4 : 8); }
+int conv_blocks(int logn, int logm) { return (1 << (2 * logn)) / t_columns(logm); }
+int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / t_columns(logm - 1); }
 
 #define CNLOS_TIMED(prof, kind, st, launch)                 \
   do {                                                     \
