@@ -282,14 +282,13 @@ def algorithmic_bytes(kind, n, m, dual):
         return 2 * spec_s
     if kind == "t_inv_solve":      # the u solve also reads ubar
         return spec_s + f + (f / 2 if dual else f)
-    if kind == "vstep":            # dual: v, w and f steps in one kernel
-        return 20 * f + n * n if dual else 8 * f
-    if kind == "rhs_u":
-        return 9 * f
-    if kind == "rhs_tau":
-        return 10 * f
-    if kind == "post_u":           # dual: u side and tau side in one kernel
-        return 31 * f + n * n if dual else 13 * f
+    # the splitting variables v, w, f are recomputed where they are used
+    if kind == "rhs_u":            # ubar, grad f, Lambda (3), phi in; rhs out
+        return 7 * f
+    if kind == "rhs_tau":          # A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau in; rhs out
+        return 9 * f + n * n
+    if kind == "post_u":           # object: 7 volumes in, 5 out; dual adds the tau side (10 in, 6 out)
+        return 28 * f + n * n if dual else 12 * f
     return 0.0
 
 

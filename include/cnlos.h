@@ -110,7 +110,7 @@ typedef struct cnlos_config {
 typedef enum {
   CNLOS_FIELD_U = 0,        /* u^k                                          */
   CNLOS_FIELD_UBAR = 1,     /* extrapolated ubar^k                          */
-  CNLOS_FIELD_V = 2,        /* splitting variable v = grad u                */
+  CNLOS_FIELD_V = 2,        /* v of the next iteration (derived, read-only) */
   CNLOS_FIELD_LAM = 3,      /* multiplier Lambda (Lambda_1)                 */
   CNLOS_FIELD_PHI = 4,      /* curvature weight phi(kappa(u))               */
   CNLOS_FIELD_AU = 5,       /* A u^k (unmasked)                             */
@@ -118,9 +118,9 @@ typedef enum {
   CNLOS_FIELD_TAU0 = 7,     /* normalized measurement (read-only)           */
   CNLOS_FIELD_TAU = 8,      /* dual model: tau^k                            */
   CNLOS_FIELD_TAUBAR = 9,   /* dual model: extrapolated taubar^k            */
-  CNLOS_FIELD_W = 10,       /* dual model: w = grad tau                     */
+  CNLOS_FIELD_W = 10,       /* dual model: next w (derived, read-only)      */
   CNLOS_FIELD_LAM2 = 11,    /* dual model: Lambda_2                         */
-  CNLOS_FIELD_F = 12,       /* dual model: f = tau                          */
+  CNLOS_FIELD_F = 12,       /* dual model: next f (derived, read-only)      */
   CNLOS_FIELD_LAM3 = 13,    /* dual model: Lambda_3                         */
   CNLOS_FIELD_PHI_TAU = 14, /* dual model: phi(kappa(tau))                  */
   CNLOS_FIELD_COUNT = 15
@@ -219,9 +219,12 @@ cnlos_status cnlos_get_volume(cnlos_problem* p, float* u_dev);
 /* Dual model: copy the current signal estimate tau [nx][ny][nt].  Asynchronous. */
 cnlos_status cnlos_get_signal(cnlos_problem* p, float* tau_dev);
 
-/* Copy a state field out / in (checkpoint and resume).  Sizes per cnlos_field.
- * CNLOS_FIELD_TAU0 is read-only; dual-model fields need the dual model.
- * Asynchronous. */
+/* Copy a state field out / in (checkpoint and resume).  Sizes per cnlos_field
+ * (V, LAM, W and LAM2 hold 3 volumes).  The splitting variables v, w and f are
+ * not stored: reading them computes the values the next iteration will use
+ * from ubar, Lambda, phi (taubar, Lambda2, phi_tau; taubar, Lambda3, tau0),
+ * so they are read-only, like TAU0; restoring the other fields restores them.
+ * Dual-model fields need the dual model.  Asynchronous. */
 cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev);
 cnlos_status cnlos_set_field(cnlos_problem* p, int32_t field, const float* src_dev);
 

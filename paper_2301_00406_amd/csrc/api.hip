@@ -175,17 +175,14 @@ struct cnlos_problem {
   uint8_t* mask = nullptr;
   float* tau0 = nullptr;
   float* U[2] = {nullptr, nullptr};
-  float* ubar = nullptr;
-  float* v = nullptr;
+  float* UB[2] = {nullptr, nullptr};   // ubar^k and ubar^{k+1}
   float* lam = nullptr;
   float* phi = nullptr;
   float* AU[3] = {nullptr, nullptr, nullptr};
   float* gf = nullptr;
   float* T[2] = {nullptr, nullptr};
-  float* taubar = nullptr;
-  float* w = nullptr;
+  float* TB[2] = {nullptr, nullptr};   // taubar^k and taubar^{k+1}
   float* lam2 = nullptr;
-  float* f = nullptr;
   float* lam3 = nullptr;
   float* phi_tau = nullptr;
   Tables tb;
@@ -302,8 +299,8 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
   float* tau0 = cv.take<float>(V);
   float* U0 = cv.take<float>(V);
   float* U1 = cv.take<float>(V);
-  float* ubar = cv.take<float>(V);
-  float* v = cv.take<float>(3 * V);
+  float* UB0 = cv.take<float>(V);
+  float* UB1 = cv.take<float>(V);
   float* lam = cv.take<float>(3 * V);
   float* phi = cv.take<float>(V);
   float* A0 = cv.take<float>(V);
@@ -314,8 +311,8 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
     p->tau0 = tau0;
     p->U[0] = U0;
     p->U[1] = U1;
-    p->ubar = ubar;
-    p->v = v;
+    p->UB[0] = UB0;
+    p->UB[1] = UB1;
     p->lam = lam;
     p->phi = phi;
     p->AU[0] = A0;
@@ -326,19 +323,17 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
   if (c.model == CNLOS_MODEL_DUAL) {
     float* T0 = cv.take<float>(V);
     float* T1 = cv.take<float>(V);
-    float* taubar = cv.take<float>(V);
-    float* w = cv.take<float>(3 * V);
+    float* TB0 = cv.take<float>(V);
+    float* TB1 = cv.take<float>(V);
     float* lam2 = cv.take<float>(3 * V);
-    float* f = cv.take<float>(V);
     float* lam3 = cv.take<float>(V);
     float* phi_tau = cv.take<float>(V);
     if (p) {
       p->T[0] = T0;
       p->T[1] = T1;
-      p->taubar = taubar;
-      p->w = w;
+      p->TB[0] = TB0;
+      p->TB[1] = TB1;
       p->lam2 = lam2;
-      p->f = f;
       p->lam3 = lam3;
       p->phi_tau = phi_tau;
     }
@@ -488,15 +483,13 @@ cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
 
 cnlos_status reset_state(cnlos_problem* p) {
   const size_t V = p->V;
-  float* zero[] = {p->U[0], p->U[1], p->ubar, p->AU[0], p->AU[1], p->AU[2], p->gf};
+  float* zero[] = {p->U[0], p->U[1], p->UB[0], p->UB[1], p->AU[0], p->AU[1], p->AU[2], p->gf};
   for (float* z : zero) HIPCHK(launch_fill(z, V, 0.f, p->st));
-  HIPCHK(launch_fill(p->v, 3 * V, 0.f, p->st));
   HIPCHK(launch_fill(p->lam, 3 * V, 0.f, p->st));
   HIPCHK(launch_fill(p->phi, V, (float)phi_at_zero(phi_args(p, 1, false)), p->st));
   if (p->cfg.model == CNLOS_MODEL_DUAL) {
-    float* zd[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3};
+    float* zd[] = {p->T[0], p->T[1], p->TB[0], p->TB[1], p->lam3};
     for (float* z : zd) HIPCHK(launch_fill(z, V, 0.f, p->st));
-    HIPCHK(launch_fill(p->w, 3 * V, 0.f, p->st));
     HIPCHK(launch_fill(p->lam2, 3 * V, 0.f, p->st));
     HIPCHK(launch_fill(p->phi_tau, V, (float)phi_at_zero(phi_args(p, 2, true)), p->st));
   }
@@ -524,6 +517,10 @@ cnlos_status reset_state(cnlos_problem* p) {
   c.slot[R_AU_TR] = 1;
   c.slot[R_T_CUR] = 0;
   c.slot[R_T_TR] = 1;
+  c.slot[R_UB_CUR] = 0;
+  c.slot[R_UB_NEW] = 1;
+  c.slot[R_TB_CUR] = 0;
+  c.slot[R_TB_NEW] = 1;
   c.slot_pad = 0;
   p->iter_host = 0;
   return ctl_push(p);
@@ -556,6 +553,12 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     } else if (r == R_T_CUR || r == R_T_TR) {
       v.p[0] = p->T[0];
       v.p[1] = p->T[1];
+    } else if (r == R_UB_CUR || r == R_UB_NEW) {
+      v.p[0] = p->UB[0];
+      v.p[1] = p->UB[1];
+    } else if (r == R_TB_CUR || r == R_TB_NEW) {
+      v.p[0] = p->TB[0];
+      v.p[1] = p->TB[1];
     } else {
       v.p[0] = p->AU[0];
       v.p[1] = p->AU[1];
@@ -567,11 +570,10 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
   if (seqs & SEQ_S1) {
     const double mu = c.mu;
     const int G = G_STAGE1;
-    TIMED(KK_VSTEP, launch_vstep(ln, lm, p->ubar, p->lam, p->phi, p->v, mu, ctl, gated(G | G_FIRST), p->st));
     ConvSrc sa{};
     sa.a = role(R_AU_CUR);
     sa.b = role(R_AU_PREV);
-    sa.c = p->tau0;
+    sa.c = fixed(p->tau0);
     sa.w = p->wk;
     sa.mask = p->mask;
     sa.lincache = 1;
@@ -580,16 +582,18 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
     HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu, ctl, gated(G), p->st));
+    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, role(R_UB_CUR), p->gf, p->lam, p->phi, mu, ctl,
+                                 gated(G | G_FIRST), p->st));
     SolveEpi se{};
     se.out = role(R_U_TR);
-    se.ref = p->ubar;
+    se.ref = role(R_UB_CUR);
     se.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, gated(G), p->st,
                         &p->prof));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
+    sf.c = fixed(nullptr);
     ConvEpi ef{};
     ef.out = role(R_AU_TR);
     ef.w = p->wk;
@@ -601,8 +605,8 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_OBJ, ef, ctl, gated(G), p->st, &p->prof));
     TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
                                    gated(G), p->st));
-    const PostArgs pa{role(R_U_TR), role(R_U_CUR), p->v, p->lam, p->ubar, p->phi, (float)mu,
-                      phi_args(p, 1, false)};
+    const PostArgs pa{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
+                      (float)mu, phi_args(p, 1, false)};
     TIMED(KK_POST_U, launch_post(ln, lm, pa, p->partials, ctl, gated(G | G_AFTER_CHECK), p->st));
     // the data term of the energy comes from the forward pass (SL_DATA)
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu,
@@ -612,24 +616,20 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
 
   if (seqs & SEQ_TR) {
     const PhiArgs pu = phi_args(p, 2, false), pt = phi_args(p, 2, true);
-    float* zf[] = {p->T[0], p->T[1], p->taubar, p->f, p->lam3, p->w, p->lam2, p->lam};
-    size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V, 3 * V};
-    TIMED(KK_OTHER, launch_transition(ln, lm, ctl, role(R_U_CUR), p->ubar, p->phi, pu, p->phi_tau,
-                                      phi_at_zero(pt), zf,
-                                      zc, 8, bt, p->st));
+    float* zf[] = {p->T[0], p->T[1], p->TB[0], p->TB[1], p->lam3, p->lam2, p->lam};
+    size_t zc[] = {V, V, V, V, V, 3 * V, 3 * V};
+    TIMED(KK_OTHER, launch_transition(ln, lm, ctl, role(R_U_CUR), role(R_UB_CUR), p->phi, pu,
+                                      p->phi_tau, phi_at_zero(pt), zf, zc, 7, bt, p->st));
   }
 
   if (seqs & SEQ_S2) {
     // Algorithm 2
     const double mu1 = c.mu1, mu2 = c.mu2, mu3 = c.mu3, lam = c.lambda;
     const int G = G_STAGE2;
-    TIMED(KK_VSTEP, launch_pre_dual(ln, lm, p->ubar, p->lam, p->phi, p->v, mu1, p->taubar, p->lam2,
-                                    p->phi_tau, p->w, mu2, p->lam3, p->tau0, p->mask, p->f, lam, mu3,
-                                    ctl, gated(G | G_FIRST), p->st));
     ConvSrc sa{};
     sa.a = role(R_AU_CUR);
     sa.b = role(R_AU_PREV);
-    sa.c = p->taubar;
+    sa.c = role(R_TB_CUR);
     sa.w = p->wk;
     sa.lincache = 1;
     ConvEpi ea{};
@@ -637,16 +637,18 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
     HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, p->ubar, p->gf, p->v, p->lam, mu1, ctl, gated(G), p->st));
+    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, role(R_UB_CUR), p->gf, p->lam, p->phi, mu1, ctl,
+                                 gated(G | G_FIRST), p->st));
     SolveEpi se{};
     se.out = role(R_U_TR);
-    se.ref = p->ubar;
+    se.ref = role(R_UB_CUR);
     se.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, gated(G), p->st,
                         &p->prof));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
+    sf.c = fixed(nullptr);
     ConvEpi ef{};
     ef.out = role(R_AU_TR);
     ef.w = p->wk;
@@ -657,19 +659,20 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
                                    gated(G), p->st));
     const int GA = G | G_AFTER_CHECK;
-    TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, role(R_AU_TR), p->f, p->lam3, p->w, p->lam2, p->gf, mu2, mu3,
-                                     ctl, gated(GA), p->st));
+    TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, role(R_AU_TR), role(R_TB_CUR), p->lam3, p->tau0, p->mask,
+                                     p->lam2, p->phi_tau, p->gf, lam, mu2, mu3, ctl, gated(GA), p->st));
     SolveEpi st2{};
     st2.out = role(R_T_TR);
+    st2.ref = fixed(nullptr);
     st2.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, gated(GA),
                         p->st, &p->prof));
-    const PostArgs pu{role(R_U_TR), role(R_U_CUR), p->v, p->lam, p->ubar, p->phi, (float)mu1,
-                      phi_args(p, 2, false)};
-    const PostArgs pt{role(R_T_TR), role(R_T_CUR), p->w, p->lam2, p->taubar, p->phi_tau, (float)mu2,
-                      phi_args(p, 2, true)};
-    TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->f, p->lam3, mu3, role(R_AU_TR), p->tau0, p->mask,
-                                      p->partials, ctl, gated(GA), p->st));
+    const PostArgs pu{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
+                      (float)mu1, phi_args(p, 2, false)};
+    const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_TB_CUR), role(R_TB_NEW), p->lam2,
+                      p->phi_tau, (float)mu2, phi_args(p, 2, true)};
+    TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->lam3, mu3, lam, role(R_AU_TR), p->tau0,
+                                      p->mask, p->partials, ctl, gated(GA), p->st));
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1,
                                       gated(GA), p->st));
   }
@@ -683,8 +686,7 @@ float* field_ptr(cnlos_problem* p, int field, size_t* count) {
   *count = V;
   switch (field) {
     case CNLOS_FIELD_U: return p->U[h.slot[R_U_CUR]];
-    case CNLOS_FIELD_UBAR: return p->ubar;
-    case CNLOS_FIELD_V: *count = 3 * V; return p->v;
+    case CNLOS_FIELD_UBAR: return p->UB[h.slot[R_UB_CUR]];
     case CNLOS_FIELD_LAM: *count = 3 * V; return p->lam;
     case CNLOS_FIELD_PHI: return p->phi;
     case CNLOS_FIELD_AU: return p->AU[h.slot[R_AU_CUR]];
@@ -695,10 +697,8 @@ float* field_ptr(cnlos_problem* p, int field, size_t* count) {
   if (!dual) return nullptr;
   switch (field) {
     case CNLOS_FIELD_TAU: return p->T[h.slot[R_T_CUR]];
-    case CNLOS_FIELD_TAUBAR: return p->taubar;
-    case CNLOS_FIELD_W: *count = 3 * V; return p->w;
+    case CNLOS_FIELD_TAUBAR: return p->TB[h.slot[R_TB_CUR]];
     case CNLOS_FIELD_LAM2: *count = 3 * V; return p->lam2;
-    case CNLOS_FIELD_F: return p->f;
     case CNLOS_FIELD_LAM3: return p->lam3;
     case CNLOS_FIELD_PHI_TAU: return p->phi_tau;
     default: return nullptr;
@@ -1274,6 +1274,25 @@ cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev) {
   if (!dst_dev) return fail(CNLOS_EINVAL, "destination is NULL");
   cnlos_status s = ctl_pull(p);
   if (s != CNLOS_OK) return s;
+  const DevCtl& h = *p->ctl_host;
+  const bool dual = p->cfg.model == CNLOS_MODEL_DUAL;
+  const bool stage2 = dual && h.stage == 2;
+  // v, w and f are not stored: computed from the state the next iteration starts from
+  if (field == CNLOS_FIELD_V) {
+    HIPCHK(launch_vstep(p->logn, p->logm, p->UB[h.slot[R_UB_CUR]], p->lam, p->phi, dst_dev,
+                        stage2 ? p->cfg.mu1 : p->cfg.mu, p->st));
+    return CNLOS_OK;
+  }
+  if (dual && field == CNLOS_FIELD_W) {
+    HIPCHK(launch_vstep(p->logn, p->logm, p->TB[h.slot[R_TB_CUR]], p->lam2, p->phi_tau, dst_dev,
+                        p->cfg.mu2, p->st));
+    return CNLOS_OK;
+  }
+  if (dual && field == CNLOS_FIELD_F) {
+    HIPCHK(launch_fstep(p->logn, p->logm, p->TB[h.slot[R_TB_CUR]], p->lam3, p->tau0, p->mask,
+                        dst_dev, p->cfg.lambda, p->cfg.mu3, p->st));
+    return CNLOS_OK;
+  }
   size_t n = 0;
   float* src = field_ptr(p, field, &n);
   if (!src) return fail(CNLOS_EINVAL, "field not available for this model");
@@ -1286,6 +1305,8 @@ cnlos_status cnlos_set_field(cnlos_problem* p, int32_t field, const float* src_d
   CHECK_SOLVER(p);
   if (!src_dev) return fail(CNLOS_EINVAL, "source is NULL");
   if (field == CNLOS_FIELD_TAU0) return fail(CNLOS_EINVAL, "the measurement is set by cnlos_set_measurement");
+  if (field == CNLOS_FIELD_V || field == CNLOS_FIELD_W || field == CNLOS_FIELD_F)
+    return fail(CNLOS_EINVAL, "v, w and f are derived from the other fields and cannot be set");
   cnlos_status s = ctl_pull(p);
   if (s != CNLOS_OK) return s;
   size_t n = 0;

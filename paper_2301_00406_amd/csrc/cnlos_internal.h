@@ -71,7 +71,7 @@ constexpr int kLogCols = 6;
 enum HaltReason : int { HR_NONE = 0, HR_REJECT = 1, HR_STOP = 2, HR_BACKTRACK = 3, HR_NONFINITE = 4 };
 
 // Volumes whose role rotates with the accepted-iteration count.  Each role
-// draws from a small set of buffers (u: 2, A u: 3, tau: 2); the controller
+// draws from a small set of buffers (u, ubar, tau, taubar: 2; A u: 3); the controller
 // keeps which buffer currently plays each role (rotated by the finalize
 // kernel), so a kernel resolves it on the device and scenes at different
 // iteration counts can share one launch.
@@ -83,7 +83,11 @@ enum Role : int {
   R_AU_TR = 4,    // A u^{k+1} trial
   R_T_CUR = 5,    // tau^k
   R_T_TR = 6,     // tau^{k+1} trial
-  R_COUNT = 7
+  R_UB_CUR = 7,   // ubar^k (read by the iteration)
+  R_UB_NEW = 8,   // ubar^{k+1} (written by the post step)
+  R_TB_CUR = 9,   // taubar^k
+  R_TB_NEW = 10,  // taubar^{k+1}
+  R_COUNT = 11
 };
 
 // Phase gate of an iteration kernel (bits): which stage it belongs to and
@@ -141,8 +145,8 @@ __device__ __forceinline__ bool gated_off(const DevCtl* c, int gate) {
 // A volume operand: the fixed pointer p[0] (role < 0), or the buffer p[slot]
 // that the controller currently assigns to the role.
 struct Vol {
-  float* p[3];
-  int role;
+  float* p[3] = {nullptr, nullptr, nullptr};
+  int role = -1;
 };
 
 // Scenes of a batch live in equal workspaces at a fixed byte stride; a kernel
@@ -179,7 +183,7 @@ struct ResampleTables {
 struct ConvSrc {
   Vol a;
   Vol b;
-  const float* c;
+  Vol c;
   const float* w;
   const uint8_t* mask;
   const double* scale_div;   // divide by *scale_div (power iteration)
@@ -202,7 +206,7 @@ struct ConvEpi {
 // Epilogue of the t-axis inverse pass of a diagonal solve.
 struct SolveEpi {
   Vol out;
-  const float* ref;        // ||out - ref||^2 into SL_STEP when not null
+  Vol ref;                 // ||out - ref||^2 into SL_STEP when not null
   double* partials;
 };
 
@@ -245,34 +249,34 @@ struct PhiArgs {
   int kind;
   float eta;
 };
-hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
-                        float* v, double mu, const DevCtl* ctl, const Batch& bt, hipStream_t st);
+// derived fields: v (or w) and f from the current state, single problem
+hipError_t launch_vstep(int logn, int logm, const float* xbar, const float* lam, const float* phi,
+                        float* v, double mu, hipStream_t st);
+hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
+                        const float* tau0, const uint8_t* mask, float* f, double lambda,
+                        double mu3, hipStream_t st);
 // one side (u or tau) of the post-step update
 struct PostArgs {
   Vol xn;            // x+ (accepted)
   Vol xo;            // x^k
-  const float* v;    // v (u side) or w (tau side)
+  Vol xb;            // xbar^k (the iteration's v / w are recomputed from it)
+  Vol xbn;           // xbar^{k+1}, written
   float* lam;        // Lambda or Lambda2, updated in place
-  float* xbar;       // extrapolated point, written
-  float* phi;        // curvature weight, written
+  float* phi;        // curvature weight, updated in place
   float mu;
   PhiArgs pa;
 };
-hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* lam,
-                           const float* phi, float* v, double mu1, const float* taubar,
-                           const float* lam2, const float* phi_tau, float* w, double mu2,
-                           const float* lam3, const float* tau0, const uint8_t* mask, float* f,
-                           double lambda, double mu3, const DevCtl* ctl, const Batch& bt,
-                           hipStream_t st);
+
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
-                            const float* f, float* lam3, double mu3, Vol au,
-                            const float* tau0, const uint8_t* mask, double* partials,
-                            const DevCtl* ctl, const Batch& bt, hipStream_t st);
-hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
-                        const float* lam, double mu, const DevCtl* ctl, const Batch& bt,
+                            float* lam3, double mu3, double lambda, Vol au, const float* tau0,
+                            const uint8_t* mask, double* partials, const DevCtl* ctl,
+                            const Batch& bt, hipStream_t st);
+hipError_t launch_rhs_u(int logn, int logm, Vol ubar, float* gf_rhs, const float* lam,
+                        const float* phi, double mu, const DevCtl* ctl, const Batch& bt,
                         hipStream_t st);
-hipError_t launch_rhs_tau(int logn, int logm, Vol au, const float* f, const float* lam3,
-                          const float* w, const float* lam2, float* rhs, double mu2, double mu3,
+hipError_t launch_rhs_tau(int logn, int logm, Vol au, Vol taubar, const float* lam3,
+                          const float* tau0, const uint8_t* mask, const float* lam2,
+                          const float* phi_tau, float* rhs, double lambda, double mu2, double mu3,
                           const DevCtl* ctl, const Batch& bt, hipStream_t st);
 hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
                        const DevCtl* ctl, const Batch& bt, hipStream_t st);
@@ -282,7 +286,7 @@ hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb
 hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
                            int nb_sten, int dual, double lambda, double mu_res, const Batch& bt,
                            hipStream_t st);
-hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, float* ubar,
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, Vol ubar,
                              float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
                              float* const* zero_fields, const size_t* zero_counts, int nzero,
                              const Batch& bt, hipStream_t st);

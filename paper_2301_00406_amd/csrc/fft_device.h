@@ -70,13 +70,31 @@ __device__ __forceinline__ float2 lane_xor2(float2 v) {
 template <int D, int E>
 __device__ __forceinline__ void dif_xstage(float2 (&x)[E], int s, const float2* __restrict__ twc) {
   const bool upper = (s & D) != 0;
-  const float2 tw_ = twc[D + (s & (D - 1))];
-  const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
   const float sg = upper ? -1.f : 1.f;
+  if constexpr (D == 1) {
+    // span 1: the twiddle is 1
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const float2 o = lane_xor2<D>(x[r]);
-    x[r] = cmul(make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y), w);
+    for (int r = 0; r < E; ++r) {
+      const float2 o = lane_xor2<D>(x[r]);
+      x[r] = make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y);
+    }
+  } else if constexpr (D == 2) {
+    // span 2: the twiddles are 1 and -i
+    const bool rot = upper && (s & 1);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const float2 o = lane_xor2<D>(x[r]);
+      const float2 y = make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y);
+      x[r] = rot ? make_float2(y.y, -y.x) : y;
+    }
+  } else {
+    const float2 tw_ = twc[D + (s & (D - 1))];
+    const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const float2 o = lane_xor2<D>(x[r]);
+      x[r] = cmul(make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y), w);
+    }
   }
 }
 
@@ -84,17 +102,34 @@ __device__ __forceinline__ void dif_xstage(float2 (&x)[E], int s, const float2* 
 // lane: a - b conj(w).  The upper lane scales its own value by conj(w) before
 // the exchange (the lower lane by 1), so both results are o + sgn t with t
 // the lane's scaled value and o the partner's: no selects per element.
+// Spans 1 and 2 have the twiddles 1 and (1, i after conjugation).
 template <int D, int E>
 __device__ __forceinline__ void dit_xstage(float2 (&x)[E], int s, const float2* __restrict__ twc) {
   const bool upper = (s & D) != 0;
-  const float2 tw_ = twc[D + (s & (D - 1))];
-  const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
   const float sg = upper ? -1.f : 1.f;
+  if constexpr (D == 1) {
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const float2 t = cmulc(x[r], w);
-    const float2 o = lane_xor2<D>(t);
-    x[r] = make_float2(o.x + sg * t.x, o.y + sg * t.y);
+    for (int r = 0; r < E; ++r) {
+      const float2 o = lane_xor2<D>(x[r]);
+      x[r] = make_float2(o.x + sg * x[r].x, o.y + sg * x[r].y);
+    }
+  } else if constexpr (D == 2) {
+    const bool rot = upper && (s & 1);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const float2 t = rot ? make_float2(-x[r].y, x[r].x) : x[r];   // times conj(-i) = i
+      const float2 o = lane_xor2<D>(t);
+      x[r] = make_float2(o.x + sg * t.x, o.y + sg * t.y);
+    }
+  } else {
+    const float2 tw_ = twc[D + (s & (D - 1))];
+    const float2 w = upper ? tw_ : make_float2(1.f, 0.f);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const float2 t = cmulc(x[r], w);
+      const float2 o = lane_xor2<D>(t);
+      x[r] = make_float2(o.x + sg * t.x, o.y + sg * t.y);
+    }
   }
 }
 
@@ -184,19 +219,31 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
   }
 }
 
-// Sums of K partial arrays partials[slot[k]][0..nb[k]) by one block, all K
-// loaded and reduced together, each in a fixed order; results valid in thread 0.
+// Sums of K partial arrays partials[slot[k]][0..nb[k]) by one block of 1024
+// threads (nb[k] <= 4096), all K loaded and reduced together, each in a fixed
+// order; results valid in thread 0.
 template <int K>
 __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ partials,
                                                      const int (&slot)[K], const int (&nb)[K],
                                                      int max_blocks, double (&out)[K]) {
   __shared__ double red[K][16];
   double acc[K];
+  // every load is issued before the first add (fixed trip counts, unrolled):
+  // one memory round trip instead of K
+  constexpr int kPer = 4;   // covers 4 x blockDim >= max_blocks partials (1024 threads)
+  double vals[K][kPer];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int i = threadIdx.x + j * (int)blockDim.x;
+      vals[k][j] = i < nb[k] ? partials[(size_t)slot[k] * max_blocks + i] : 0.0;
+    }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     acc[k] = 0.0;
-    for (int i = threadIdx.x; i < nb[k]; i += blockDim.x)
-      acc[k] += partials[(size_t)slot[k] * max_blocks + i];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) acc[k] += vals[k][j];
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

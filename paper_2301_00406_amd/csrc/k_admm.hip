@@ -79,24 +79,6 @@ __device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_
   return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
 }
 
-// v = shrink(grad xbar - Lambda/mu, phi/mu) at voxel g, isotropic over the
-// three components (eq. (7); the w-step of Algorithm 2 is the same on taubar)
-__device__ __forceinline__ void vstep_at(const float* __restrict__ xb, const float* __restrict__ lam,
-                                         const float* __restrict__ phi, float* __restrict__ v,
-                                         float inv_mu, size_t g, size_t V, const Nbr& nb) {
-  float gx, gy, gt;
-  grad_at(xb, g, nb.xp, nb.yp, nb.tp, gx, gy, gt);
-  const float ax = gx - lam[g] * inv_mu;
-  const float ay = gy - lam[V + g] * inv_mu;
-  const float at = gt - lam[2 * V + g] * inv_mu;
-  const float nrm = sqrtf(ax * ax + ay * ay + at * at);
-  const float thr = phi[g] * inv_mu;
-  const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
-  v[g] = ax * s;
-  v[V + g] = ay * s;
-  v[2 * V + g] = at * s;
-}
-
 // Common head of the iteration kernels: shift the controller to this launch's
 // scene, apply the phase gate, and (first kernel of an iteration slot) clear
 // the previous slot's rejection.
@@ -110,136 +92,210 @@ __device__ __forceinline__ float* vol_at(const Vol& v, const DevCtl* c, size_t z
   return vol_resolve(v, c, zo);
 }
 
-__global__ void __launch_bounds__(kStencilThreads)
-k_vstep(const float* __restrict__ ub, const float* __restrict__ lam, const float* __restrict__ phi,
-        float* __restrict__ v, float inv_mu, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
-  const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  ub = zsh(ub, zo);
-  lam = zsh(lam, zo);
-  phi = zsh(phi, zo);
-  v = zsh(v, zo);
-  const size_t V = (size_t)1 << (2 * logn + logm);
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x)
-    vstep_at(ub, lam, phi, v, inv_mu, g, V, neighbours(g, logn, logm));
+// v = shrink(grad xbar - Lambda/mu, phi/mu) at voxel q, isotropic over the
+// three components (eq. (7); the w-step of Algorithm 2 is the same on taubar).
+// The splitting variables are never stored: every kernel that needs v (or w)
+// recomputes it from xbar, Lambda and phi, which are unchanged between the
+// v-step and its last use in the same iteration.
+__device__ __forceinline__ void v_at(const float* __restrict__ xb, const float* __restrict__ lam,
+                                     const float* __restrict__ phi, float inv_mu, size_t q,
+                                     size_t V, int logn, int logm, float& vx, float& vy,
+                                     float& vt) {
+  const Nbr nb = neighbours(q, logn, logm);
+  float gx, gy, gt;
+  grad_at(xb, q, nb.xp, nb.yp, nb.tp, gx, gy, gt);
+  const float ax = gx - lam[q] * inv_mu;
+  const float ay = gy - lam[V + q] * inv_mu;
+  const float at = gt - lam[2 * V + q] * inv_mu;
+  const float nrm = sqrtf(ax * ax + ay * ay + at * at);
+  const float thr = phi[q] * inv_mu;
+  const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
+  vx = ax * s;
+  vy = ay * s;
+  vt = at * s;
 }
 
-// Algorithm 2's pointwise steps before the u update, in one pass: v on ubar,
-// w on taubar, and f, the pointwise minimizer of lambda/2 |f - tau0|^2 on kept
-// points + <Lambda3, f - taubar> + mu3/2 |f - taubar|^2.
+// f: pointwise minimizer of lambda/2 |f - tau0|^2 on kept points
+//    + <Lambda3, f - taubar> + mu3/2 |f - taubar|^2 (never stored, as v)
+// (inv_kept = 1 / (lambda + mu3), inv_mu3 = 1 / mu3)
+__device__ __forceinline__ float f_at(float tb, float l3, float t0, bool kept, float lambda,
+                                      float mu3, float inv_kept, float inv_mu3) {
+  return kept ? (lambda * t0 + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
+}
+
+// nabla^*(mu v + Lambda) at voxel g: minus the backward-difference divergence
+__device__ __forceinline__ float adj_mu_v_lam(const float* __restrict__ xb,
+                                              const float* __restrict__ lam,
+                                              const float* __restrict__ phi, float mu,
+                                              float inv_mu, size_t g, size_t V, const Nbr& nb,
+                                              int logn, int logm) {
+  float vx, vy, vt, ux, uy, ut;
+  v_at(xb, lam, phi, inv_mu, g, V, logn, logm, vx, vy, vt);
+  const float px0 = mu * vx + lam[g], py0 = mu * vy + lam[V + g], pt0 = mu * vt + lam[2 * V + g];
+  v_at(xb, lam, phi, inv_mu, nb.xm, V, logn, logm, vx, uy, ut);
+  const float pxm = mu * vx + lam[nb.xm];
+  v_at(xb, lam, phi, inv_mu, nb.ym, V, logn, logm, ux, vy, ut);
+  const float pym = mu * vy + lam[V + nb.ym];
+  v_at(xb, lam, phi, inv_mu, nb.tm, V, logn, logm, ux, uy, vt);
+  const float ptm = mu * vt + lam[2 * V + nb.tm];
+  return -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
+}
+
+// derived fields on request: v (or w) and f from the current state
 __global__ void __launch_bounds__(kStencilThreads)
-k_pre_dual(const float* __restrict__ ub, const float* __restrict__ lam,
-           const float* __restrict__ phi, float* __restrict__ v, float inv_mu1,
-           const float* __restrict__ taubar, const float* __restrict__ lam2,
-           const float* __restrict__ phi_tau, float* __restrict__ w, float inv_mu2,
-           const float* __restrict__ lam3, const float* __restrict__ tau0,
-           const uint8_t* __restrict__ mask, float* __restrict__ f, float lambda, float mu3,
-           int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
-  const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  ub = zsh(ub, zo);
-  lam = zsh(lam, zo);
-  phi = zsh(phi, zo);
-  v = zsh(v, zo);
-  taubar = zsh(taubar, zo);
-  lam2 = zsh(lam2, zo);
-  phi_tau = zsh(phi_tau, zo);
-  w = zsh(w, zo);
-  lam3 = zsh(lam3, zo);
-  tau0 = zsh(tau0, zo);
-  mask = zsh(mask, zo);
-  f = zsh(f, zo);
+k_vstep(const float* __restrict__ xb, const float* __restrict__ lam, const float* __restrict__ phi,
+        float* __restrict__ v, float inv_mu, int logn, int logm) {
+  const size_t V = (size_t)1 << (2 * logn + logm);
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
+       g += (size_t)gridDim.x * blockDim.x) {
+    float vx, vy, vt;
+    v_at(xb, lam, phi, inv_mu, g, V, logn, logm, vx, vy, vt);
+    v[g] = vx;
+    v[V + g] = vy;
+    v[2 * V + g] = vt;
+  }
+}
+
+__global__ void __launch_bounds__(kStencilThreads)
+k_fstep(const float* __restrict__ taubar, const float* __restrict__ lam3,
+        const float* __restrict__ tau0, const uint8_t* __restrict__ mask, float* __restrict__ f,
+        float lambda, float mu3, int logn, int logm) {
   const size_t V = (size_t)1 << (2 * logn + logm);
   const float inv_kept = 1.f / (lambda + mu3), inv_mu3 = 1.f / mu3;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    vstep_at(ub, lam, phi, v, inv_mu1, g, V, nb);
-    vstep_at(taubar, lam2, phi_tau, w, inv_mu2, g, V, nb);
-    const float tb = taubar[g], l3 = lam3[g];
-    f[g] = mask[g >> logm] ? (lambda * tau0[g] + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
-  }
+       g += (size_t)gridDim.x * blockDim.x)
+    f[g] = f_at(taubar[g], lam3[g], tau0[g], mask[g >> logm] != 0, lambda, mu3, inv_kept, inv_mu3);
 }
 
-// rhs = L ubar - grad f + nabla^*(mu v + Lambda)   (eq. (10)/(11) right-hand side), in place
+// Right-hand sides of the two diagonal solves, tiled so that each v (or w)
+// is computed about twice instead of four times: a block of 256 threads owns
+// a tile of Tx x Ty scan columns x Tt bins (Tt = min(m, 64), Ty = 2), computes
+// v on its voxels and on the backward halo faces into LDS, then forms
+//   u side:   rhs = L ubar - grad f + nabla^*(mu v + Lambda)            (eqs. (10), (11))
+//   tau side: rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem)
+// in place over grad f (u side) or into rhs (tau side).
+struct RhsTile {
+  int Tt, Ty, Tx;
+};
+inline RhsTile rhs_tile(int logn, int logm) {
+  RhsTile t;
+  t.Tt = logm >= 6 ? 64 : (1 << logm);
+  t.Ty = 2;
+  t.Tx = kStencilThreads / (t.Tt * t.Ty);
+  (void)logn;
+  return t;
+}
+constexpr int kRhsHalo = 3 * 9 * 3 * 65;   // 3 components x (Tx+1)(Ty+1)(Tt+1), upper bound
+
+template <bool TAU>
 __global__ void __launch_bounds__(kStencilThreads)
-k_rhs_u(const float* __restrict__ ub, float* __restrict__ gf_rhs, const float* __restrict__ v,
-        const float* __restrict__ lam, float mu, int logn, int logm, DevCtl* ctl, size_t zs,
-        int gate) {
+k_rhs(Vol xb_v, const float* __restrict__ lam, const float* __restrict__ phi, float mu,
+      float* __restrict__ gf_rhs, Vol au_v, const float* __restrict__ lam3,
+      const float* __restrict__ tau0, const uint8_t* __restrict__ mask, float lambda, float mu3,
+      int Tt, int Ty, int Tx, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
+  __shared__ float vb[kRhsHalo];
   const size_t zo = (size_t)blockIdx.z * zs;
   if (!iter_head(ctl, zo, gate)) return;
-  ub = zsh(ub, zo);
-  gf_rhs = zsh(gf_rhs, zo);
-  v = zsh(v, zo);
+  const float* __restrict__ xb = vol_at(xb_v, ctl, zo);
   lam = zsh(lam, zo);
-  const size_t V = (size_t)1 << (2 * logn + logm);
-  const float L = (float)ctl->L;
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    const float px0 = mu * v[g] + lam[g], pxm = mu * v[nb.xm] + lam[nb.xm];
-    const float py0 = mu * v[V + g] + lam[V + g], pym = mu * v[V + nb.ym] + lam[V + nb.ym];
-    const float pt0 = mu * v[2 * V + g] + lam[2 * V + g],
-                ptm = mu * v[2 * V + nb.tm] + lam[2 * V + nb.tm];
-    const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
-    gf_rhs[g] = L * ub[g] - gf_rhs[g] + adj;
-  }
-}
-
-// rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem of Algorithm 2)
-__global__ void __launch_bounds__(kStencilThreads)
-k_rhs_tau(Vol au_v, const float* __restrict__ f, const float* __restrict__ lam3,
-          const float* __restrict__ w, const float* __restrict__ lam2, float* __restrict__ rhs,
-          float mu2, float mu3, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
-  const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  const float* __restrict__ au = vol_at(au_v, ctl, zo);
-  f = zsh(f, zo);
+  phi = zsh(phi, zo);
+  gf_rhs = zsh(gf_rhs, zo);
+  const float* __restrict__ au = TAU ? vol_at(au_v, ctl, zo) : nullptr;
   lam3 = zsh(lam3, zo);
-  w = zsh(w, zo);
-  lam2 = zsh(lam2, zo);
-  rhs = zsh(rhs, zo);
+  tau0 = zsh(tau0, zo);
+  mask = zsh(mask, zo);
+  const int N = 1 << logn, M = 1 << logm;
   const size_t V = (size_t)1 << (2 * logn + logm);
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    const float px0 = mu2 * w[g] + lam2[g], pxm = mu2 * w[nb.xm] + lam2[nb.xm];
-    const float py0 = mu2 * w[V + g] + lam2[V + g], pym = mu2 * w[V + nb.ym] + lam2[V + nb.ym];
-    const float pt0 = mu2 * w[2 * V + g] + lam2[2 * V + g],
-                ptm = mu2 * w[2 * V + nb.tm] + lam2[2 * V + nb.tm];
-    const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
-    rhs[g] = au[g] + mu3 * f[g] + lam3[g] + adj;
+  const float inv_mu = 1.f / mu;
+  // tile origin
+  const int ntt = M / Tt, nty = N / Ty;
+  int b = blockIdx.x;
+  const int k0 = (b % ntt) * Tt;
+  b /= ntt;
+  const int j0 = (b % nty) * Ty;
+  const int i0 = (b / nty) * Tx;
+  const int SX = (Ty + 1) * (Tt + 1), SY = Tt + 1, SC = (Tx + 1) * SX;
+  auto vidx = [&](int c, int lx, int ly, int lt) { return c * SC + (lx + 1) * SX + (ly + 1) * SY + lt + 1; };
+  auto vox = [&](int i, int j, int k) {
+    i &= N - 1;
+    j &= N - 1;
+    k &= M - 1;
+    return ((size_t)i * N + j) * M + k;
+  };
+  const int tid = threadIdx.x;
+  const int lt = tid % Tt, ly = (tid / Tt) % Ty, lx = tid / (Tt * Ty);
+  const size_t g = vox(i0 + lx, j0 + ly, k0 + lt);
+  float vx, vy, vt;
+  v_at(xb, lam, phi, inv_mu, g, V, logn, logm, vx, vy, vt);
+  vb[vidx(0, lx, ly, lt)] = vx;
+  vb[vidx(1, lx, ly, lt)] = vy;
+  vb[vidx(2, lx, ly, lt)] = vt;
+  // backward halo: the x face (only its x component is used), the y face, the t line
+  const int hx = Ty * Tt, hy = Tx * Tt, ht = Tx * Ty;
+  for (int h = tid; h < hx + hy + ht; h += kStencilThreads) {
+    int ax, ay, at, c;
+    if (h < hx) {
+      ax = -1, ay = h / Tt, at = h % Tt, c = 0;
+    } else if (h < hx + hy) {
+      const int q = h - hx;
+      ax = q / Tt, ay = -1, at = q % Tt, c = 1;
+    } else {
+      const int q = h - hx - hy;
+      ax = q / Ty, ay = q % Ty, at = -1, c = 2;
+    }
+    float w[3];
+    v_at(xb, lam, phi, inv_mu, vox(i0 + ax, j0 + ay, k0 + at), V, logn, logm, w[0], w[1], w[2]);
+    vb[vidx(c, ax, ay, at)] = w[c];
+  }
+  __syncthreads();
+  const size_t gxm = vox(i0 + lx - 1, j0 + ly, k0 + lt);
+  const size_t gym = vox(i0 + lx, j0 + ly - 1, k0 + lt);
+  const size_t gtm = vox(i0 + lx, j0 + ly, k0 + lt - 1);
+  const float px0 = mu * vx + lam[g], py0 = mu * vy + lam[V + g], pt0 = mu * vt + lam[2 * V + g];
+  const float pxm = mu * vb[vidx(0, lx - 1, ly, lt)] + lam[gxm];
+  const float pym = mu * vb[vidx(1, lx, ly - 1, lt)] + lam[V + gym];
+  const float ptm = mu * vb[vidx(2, lx, ly, lt - 1)] + lam[2 * V + gtm];
+  const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
+  if (!TAU) {
+    gf_rhs[g] = (float)ctl->L * xb[g] - gf_rhs[g] + adj;
+  } else {
+    const float l3 = lam3[g];
+    const float f = f_at(xb[g], l3, tau0[g], mask[g >> logm] != 0, lambda, mu3,
+                         1.f / (lambda + mu3), 1.f / mu3);
+    gf_rhs[g] = au[g] + mu3 * f + l3 + adj;
   }
 }
 
 // After the accepted step: multiplier ascent (eq. (12)), FISTA extrapolation,
 // curvature weight refresh, and the FP64 energy/residual partials.
-// u mode : Lambda += mu (v - grad x+), xbar, phi_u; partials TV_U, PRIMAL, DUAL.
-// tau mode: Lambda2 += mu2 (w - grad tau+), Lambda3 += mu3 (f - tau+), taubar,
+// u mode : Lambda += mu (v - grad x+), xbar', phi_u; partials TV_U, PRIMAL, DUAL.
+// tau mode: Lambda2 += mu2 (w - grad tau+), Lambda3 += mu3 (f - tau+), taubar',
 //           phi_tau; partials TV_TAU, FIT (|A u+ - tau+|^2), FID (|D(tau+ - tau0)|^2).
+// v (w) and f are those of this iteration: recomputed from the xbar, Lambda and
+// phi the iteration started from, read here before they are overwritten.
 template <bool TAU>
 __device__ __forceinline__ void post_at(const float* __restrict__ xn, const float* __restrict__ xo,
-                                        const float* __restrict__ v, float* __restrict__ lam,
-                                        float* __restrict__ xbar, float* __restrict__ phi,
+                                        const float* __restrict__ xb, float* __restrict__ lam,
+                                        float* __restrict__ xbn, float* __restrict__ phi,
                                         float mu, const PhiArgs& pa, float eta2, float beta,
-                                        const float* __restrict__ f, float* __restrict__ lam3,
-                                        float mu3, const float* __restrict__ au,
+                                        float* __restrict__ lam3, float mu3, float lambda,
+                                        const float* __restrict__ au,
                                         const float* __restrict__ tau0,
                                         const uint8_t* __restrict__ mask, size_t g, size_t V,
                                         const Nbr& nb, int logn, int logm, double& s_tv,
                                         double& s_a, double& s_b) {
+  float vx, vy, vt;
+  v_at(xb, lam, phi, 1.f / mu, g, V, logn, logm, vx, vy, vt);
   float gx, gy, gt;
   const float kappa = curvature_at(xn, g, nb, logn, logm, eta2, gx, gy, gt);
   const float ph = phi_eval(kappa, pa);
   phi[g] = ph;
-  const float vx = v[g], vy = v[V + g], vt = v[2 * V + g];
   lam[g] += mu * (vx - gx);
   lam[V + g] += mu * (vy - gy);
   lam[2 * V + g] += mu * (vt - gt);
   const float x0 = xn[g];
   const float d0 = x0 - xo[g];
-  xbar[g] = x0 + beta * d0;
+  xbn[g] = x0 + beta * d0;
   const float gn = sqrtf(gx * gx + gy * gy + gt * gt);
   s_tv += (double)ph * (double)gn;
   if (!TAU) {
@@ -250,10 +306,13 @@ __device__ __forceinline__ void post_at(const float* __restrict__ xn, const floa
     const float dt = (xn[nb.tp] - xo[nb.tp]) - d0;
     s_b += (double)dx * dx + (double)dy * dy + (double)dt * dt;
   } else {
-    lam3[g] += mu3 * (f[g] - x0);
+    const bool kept = mask[g >> logm] != 0;
+    const float l3 = lam3[g];
+    const float f = f_at(xb[g], l3, tau0[g], kept, lambda, mu3, 1.f / (lambda + mu3), 1.f / mu3);
+    lam3[g] = l3 + mu3 * (f - x0);
     const float r = au[g] - x0;
     s_a += (double)r * r;
-    if (mask[g >> logm]) {
+    if (kept) {
       const float e = x0 - tau0[g];
       s_b += (double)e * e;
     }
@@ -268,9 +327,9 @@ k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* c
   if (!iter_head(ctl, zo, gate)) return;
   const float* xn = vol_at(pu.xn, ctl, zo);
   const float* xo = vol_at(pu.xo, ctl, zo);
-  pu.v = zsh(pu.v, zo);
+  const float* xb = vol_at(pu.xb, ctl, zo);
+  float* xbn = vol_at(pu.xbn, ctl, zo);
   pu.lam = zsh(pu.lam, zo);
-  pu.xbar = zsh(pu.xbar, zo);
   pu.phi = zsh(pu.phi, zo);
   partials = zsh(partials, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
@@ -281,9 +340,9 @@ k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* c
   double s_tv = 0.0, s_a = 0.0, s_b = 0.0;
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x)
-    post_at<false>(xn, xo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eta2, beta, nullptr,
-                   nullptr, 0.f, nullptr, nullptr, nullptr, g, V, neighbours(g, logn, logm), logn,
-                   logm, s_tv, s_a, s_b);
+    post_at<false>(xn, xo, xb, pu.lam, xbn, pu.phi, pu.mu, pu.pa, eta2, beta, nullptr, 0.f, 0.f,
+                   nullptr, nullptr, nullptr, g, V, neighbours(g, logn, logm), logn, logm, s_tv,
+                   s_a, s_b);
   double vals[3] = {s_tv, s_a, s_b};
   const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
   block_sum_store<3>(vals, partials, slots, kMaxBlocks);
@@ -291,26 +350,24 @@ k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* c
 
 // Algorithm 2's updates after the accepted step, u side and tau side in one pass.
 __global__ void __launch_bounds__(kStencilThreads)
-k_post_dual(PostArgs pu, PostArgs pt, const float* __restrict__ f, float* __restrict__ lam3,
-            float mu3, Vol au_v, const float* __restrict__ tau0,
-            const uint8_t* __restrict__ mask, double* __restrict__ partials, int logn, int logm,
-            DevCtl* ctl, size_t zs, int gate) {
+k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float lambda,
+            Vol au_v, const float* __restrict__ tau0, const uint8_t* __restrict__ mask,
+            double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
   if (!iter_head(ctl, zo, gate)) return;
   const float* uxn = vol_at(pu.xn, ctl, zo);
   const float* uxo = vol_at(pu.xo, ctl, zo);
+  const float* uxb = vol_at(pu.xb, ctl, zo);
+  float* uxbn = vol_at(pu.xbn, ctl, zo);
   const float* txn = vol_at(pt.xn, ctl, zo);
   const float* txo = vol_at(pt.xo, ctl, zo);
+  const float* txb = vol_at(pt.xb, ctl, zo);
+  float* txbn = vol_at(pt.xbn, ctl, zo);
   const float* au = vol_at(au_v, ctl, zo);
-  pu.v = zsh(pu.v, zo);
   pu.lam = zsh(pu.lam, zo);
-  pu.xbar = zsh(pu.xbar, zo);
   pu.phi = zsh(pu.phi, zo);
-  pt.v = zsh(pt.v, zo);
   pt.lam = zsh(pt.lam, zo);
-  pt.xbar = zsh(pt.xbar, zo);
   pt.phi = zsh(pt.phi, zo);
-  f = zsh(f, zo);
   lam3 = zsh(lam3, zo);
   tau0 = zsh(tau0, zo);
   mask = zsh(mask, zo);
@@ -324,10 +381,10 @@ k_post_dual(PostArgs pu, PostArgs pt, const float* __restrict__ f, float* __rest
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x) {
     const Nbr nb = neighbours(g, logn, logm);
-    post_at<false>(uxn, uxo, pu.v, pu.lam, pu.xbar, pu.phi, pu.mu, pu.pa, eu, beta, nullptr,
-                   nullptr, 0.f, nullptr, nullptr, nullptr, g, V, nb, logn, logm, s[0], s[1], s[2]);
-    post_at<true>(txn, txo, pt.v, pt.lam, pt.xbar, pt.phi, pt.mu, pt.pa, et, beta, f, lam3,
-                  mu3, au, tau0, mask, g, V, nb, logn, logm, s[3], s[4], s[5]);
+    post_at<false>(uxn, uxo, uxb, pu.lam, uxbn, pu.phi, pu.mu, pu.pa, eu, beta, nullptr, 0.f, 0.f,
+                   nullptr, nullptr, nullptr, g, V, nb, logn, logm, s[0], s[1], s[2]);
+    post_at<true>(txn, txo, txb, pt.lam, txbn, pt.phi, pt.mu, pt.pa, et, beta, lam3, mu3, lambda,
+                  au, tau0, mask, g, V, nb, logn, logm, s[3], s[4], s[5]);
   }
   const int slots[6] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_TV_TAU, SL_FIT, SL_FID};
   block_sum_store<6>(s, partials, slots, kMaxBlocks);
@@ -440,6 +497,12 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
     r = ctl->slot[R_T_CUR];
     ctl->slot[R_T_CUR] = ctl->slot[R_T_TR];
     ctl->slot[R_T_TR] = r;
+    r = ctl->slot[R_UB_CUR];
+    ctl->slot[R_UB_CUR] = ctl->slot[R_UB_NEW];
+    ctl->slot[R_UB_NEW] = r;
+    r = ctl->slot[R_TB_CUR];
+    ctl->slot[R_TB_CUR] = ctl->slot[R_TB_NEW];
+    ctl->slot[R_TB_NEW] = r;
     ctl->energy_prev = E;
     ctl->last_energy = E;
     ctl->last_primal = primal;
@@ -461,14 +524,14 @@ __device__ __forceinline__ bool transition_due(const DevCtl* c) {
 // ubar = u, phi_u = phi(kappa(u)), phi_tau = phi(0); tau, taubar, w, f and the
 // multipliers are zeroed by k_zero_if_stage1.
 __global__ void __launch_bounds__(kStencilThreads)
-k_transition_fields(const DevCtl* ctl, Vol u_v, float* __restrict__ ubar,
+k_transition_fields(const DevCtl* ctl, Vol u_v, Vol ubar_v,
                     float* __restrict__ phi_u, PhiArgs pa, float* __restrict__ phi_tau,
                     float phi_tau0, int logn, int logm, size_t zs) {
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
   if (!transition_due(ctl)) return;
   const float* __restrict__ u = vol_resolve(u_v, ctl, zo);
-  ubar = zsh(ubar, zo);
+  float* __restrict__ ubar = vol_resolve(ubar_v, ctl, zo);
   phi_u = zsh(phi_u, zo);
   phi_tau = zsh(phi_tau, zo);
   const size_t V = (size_t)1 << (2 * logn + logm);
@@ -598,50 +661,55 @@ static dim3 sgrid_z(int logn, int logm, const Batch& bt) {
   return dim3(stencil_blocks(logn, logm), 1, bt.nz);
 }
 
-hipError_t launch_vstep(int logn, int logm, const float* ubar, const float* lam, const float* phi,
-                        float* v, double mu, const DevCtl* ctl, const Batch& bt, hipStream_t st) {
-  hipLaunchKernelGGL(k_vstep, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, lam, phi,
-                     v, (float)(1.0 / mu), logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
+hipError_t launch_vstep(int logn, int logm, const float* xbar, const float* lam, const float* phi,
+                        float* v, double mu, hipStream_t st) {
+  hipLaunchKernelGGL(k_vstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, xbar, lam, phi, v,
+                     (float)(1.0 / mu), logn, logm);
   return hipGetLastError();
 }
 
-hipError_t launch_pre_dual(int logn, int logm, const float* ubar, const float* lam,
-                           const float* phi, float* v, double mu1, const float* taubar,
-                           const float* lam2, const float* phi_tau, float* w, double mu2,
-                           const float* lam3, const float* tau0, const uint8_t* mask, float* f,
-                           double lambda, double mu3, const DevCtl* ctl, const Batch& bt,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_pre_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, lam,
-                     phi, v, (float)(1.0 / mu1), taubar, lam2, phi_tau, w, (float)(1.0 / mu2), lam3,
-                     tau0, mask, f, (float)lambda, (float)mu3, logn, logm,
-                     const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
+hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* lam3,
+                        const float* tau0, const uint8_t* mask, float* f, double lambda,
+                        double mu3, hipStream_t st) {
+  hipLaunchKernelGGL(k_fstep, sgrid(logn, logm), dim3(kStencilThreads), 0, st, taubar, lam3, tau0,
+                     mask, f, (float)lambda, (float)mu3, logn, logm);
   return hipGetLastError();
 }
 
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
-                            const float* f, float* lam3, double mu3, Vol au,
-                            const float* tau0, const uint8_t* mask, double* partials,
-                            const DevCtl* ctl, const Batch& bt, hipStream_t st) {
-  hipLaunchKernelGGL(k_post_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pu, pt, f,
-                     lam3, (float)mu3, au, tau0, mask, partials, logn, logm,
+                            float* lam3, double mu3, double lambda, Vol au, const float* tau0,
+                            const uint8_t* mask, double* partials, const DevCtl* ctl,
+                            const Batch& bt, hipStream_t st) {
+  hipLaunchKernelGGL(k_post_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pu, pt,
+                     lam3, (float)mu3, (float)lambda, au, tau0, mask, partials, logn, logm,
                      const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_u(int logn, int logm, const float* ubar, float* gf_rhs, const float* v,
-                        const float* lam, double mu, const DevCtl* ctl, const Batch& bt,
+static dim3 rhs_grid(int logn, int logm, const RhsTile& t, const Batch& bt) {
+  const int tiles = ((1 << logm) / t.Tt) * ((1 << logn) / t.Ty) * ((1 << logn) / t.Tx);
+  return dim3(tiles, 1, bt.nz);
+}
+
+hipError_t launch_rhs_u(int logn, int logm, Vol ubar, float* gf_rhs, const float* lam,
+                        const float* phi, double mu, const DevCtl* ctl, const Batch& bt,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_u, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, ubar, gf_rhs,
-                     v, lam, (float)mu, logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
+  const RhsTile t = rhs_tile(logn, logm);
+  hipLaunchKernelGGL(k_rhs<false>, rhs_grid(logn, logm, t, bt), dim3(kStencilThreads), 0, st, ubar,
+                     lam, phi, (float)mu, gf_rhs, Vol{}, nullptr, nullptr, nullptr, 0.f, 0.f, t.Tt,
+                     t.Ty, t.Tx, logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_tau(int logn, int logm, Vol au, const float* f, const float* lam3,
-                          const float* w, const float* lam2, float* rhs, double mu2, double mu3,
+hipError_t launch_rhs_tau(int logn, int logm, Vol au, Vol taubar, const float* lam3,
+                          const float* tau0, const uint8_t* mask, const float* lam2,
+                          const float* phi_tau, float* rhs, double lambda, double mu2, double mu3,
                           const DevCtl* ctl, const Batch& bt, hipStream_t st) {
-  hipLaunchKernelGGL(k_rhs_tau, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, au, f, lam3,
-                     w, lam2, rhs, (float)mu2, (float)mu3, logn, logm, const_cast<DevCtl*>(ctl),
-                     bt.zs, bt.gate);
+  const RhsTile t = rhs_tile(logn, logm);
+  hipLaunchKernelGGL(k_rhs<true>, rhs_grid(logn, logm, t, bt), dim3(kStencilThreads), 0, st, taubar,
+                     lam2, phi_tau, (float)mu2, rhs, au, lam3, tau0, mask, (float)lambda,
+                     (float)mu3, t.Tt, t.Ty, t.Tx, logn, logm, const_cast<DevCtl*>(ctl), bt.zs,
+                     bt.gate);
   return hipGetLastError();
 }
 
@@ -667,7 +735,7 @@ hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int
   return hipGetLastError();
 }
 
-hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, float* ubar,
+hipError_t launch_transition(int logn, int logm, DevCtl* ctl, Vol u, Vol ubar,
                              float* phi_u, const PhiArgs& pa_u, float* phi_tau, double phi_tau0,
                              float* const* zero_fields, const size_t* zero_counts, int nzero,
                              const Batch& bt, hipStream_t st) {

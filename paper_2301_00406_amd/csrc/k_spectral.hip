@@ -99,7 +99,7 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   spec = zsh(spec, zo);
   const float* sa = vol_in(src.a, ctl, zo);
   const float* sb = vol_in(src.b, ctl, zo);
-  src.c = zsh(src.c, zo);
+  const float* sc_ = vol_in(src.c, ctl, zo);
   src.w = zsh(src.w, zo);
   src.mask = zsh(src.mask, zo);
   src.scale_div = zsh(src.scale_div, zo);
@@ -131,7 +131,7 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
     const size_t g = (size_t)col * M + k;
     float x = ca * sa[g];
     if (sb) x += cb * sb[g];
-    if (src.c) x -= src.c[g];
+    if (sc_) x -= sc_[g];
     if (src.w) x *= src.w[k];
     xf[k] = x * sc * mk;
   }
@@ -826,7 +826,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   float* eout = vol_out(ep.out, ctl, zo);
-  ep.ref = zsh(ep.ref, zo);
+  const float* eref = vol_in(ep.ref, ctl, zo);
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = blockIdx.x * J, col = col0 + b;
@@ -856,7 +856,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   dit_inlane<G, E, E / 2>(x, s, twc);
   double acc = 0.0;
   float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
-  const float2* ref2 = ep.ref ? reinterpret_cast<const float2*>(ep.ref) + (size_t)col * H : nullptr;
+  const float2* ref2 = eref ? reinterpret_cast<const float2*>(eref) + (size_t)col * H : nullptr;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = G * r + s;
@@ -868,7 +868,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
       acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
     }
   }
-  if (ep.ref) {
+  if (eref) {
     double v[1] = {acc};
     const int slots[1] = {SL_STEP};
     block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);

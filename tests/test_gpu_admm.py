@@ -87,7 +87,10 @@ def test_algorithm1_fields_after_a_few_iterations():
                   sc.mask)
     P.set_measurement(to_dev(torch, raw))
     P.run()
-    checks = {C.FIELD_U: st.u, C.FIELD_UBAR: st.ubar, C.FIELD_V: st.v, C.FIELD_LAM: st.Lam,
+    # v is not stored on the GPU: reading it gives the v-step of the next
+    # iteration (eq. (7)) from the current ubar, Lambda and phi
+    v_next = O.shrink(O.grad(st.ubar) - st.Lam / p.mu, st.phi / p.mu)
+    checks = {C.FIELD_U: st.u, C.FIELD_UBAR: st.ubar, C.FIELD_V: v_next, C.FIELD_LAM: st.Lam,
               C.FIELD_PHI: st.phi, C.FIELD_AU: O.apply_A(st.u, op)}
     for fld, ref in checks.items():
         err = rel_l2(to_host(P.get_field(fld)), ref)
@@ -176,7 +179,9 @@ def test_checkpoint_restores_into_a_fresh_handle():
     P.set_measurement(to_dev(torch, raw))
     P.run(7)
     info = P.info()
-    fields = {f: P.get_field(f).clone() for f in range(15) if f != C.FIELD_TAU0}
+    derived = (C.FIELD_V, C.FIELD_W, C.FIELD_F)
+    fields = {f: P.get_field(f).clone() for f in range(15) if f not in (C.FIELD_TAU0,) + derived}
+    der = {f: P.get_field(f).clone() for f in derived}
     P.run()
     ref = to_host(P.volume())
     Q = C.Problem(cfg, sc.mask)
@@ -184,6 +189,10 @@ def test_checkpoint_restores_into_a_fresh_handle():
     Q.set_info(info)
     for f, t in fields.items():
         Q.set_field(f, t)
+    for f, t in der.items():                 # derived fields follow from the restored ones
+        assert torch.equal(Q.get_field(f), t), f
+        with pytest.raises(C.CnlosError):
+            Q.set_field(f, t)
     Q.run()
     np.testing.assert_array_equal(to_host(Q.volume()), ref)
 
