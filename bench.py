@@ -276,17 +276,15 @@ def algorithmic_bytes(kind, n, m, dual):
         return spec_c + (3 * f + f) / 2
     if kind == "t_inv_conv":       # forward launch also reads A u^k, A u^{k-1}
         return spec_c + f + (2 * f) / 2
-    if kind == "t_fwd_solve":
-        return f + spec_s
+    if kind == "t_fwd_solve":      # right-hand side formed in the t pass from its inputs:
+        u_in = 6 * f               # u solve: ubar, grad f, Lambda (3), phi
+        tau_in = 8 * f + n * n     # tau solve: A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau
+        return spec_s + ((u_in + tau_in) / 2 if dual else u_in)
     if kind == "plane_solve":
         return 2 * spec_s
     if kind == "t_inv_solve":      # the u solve also reads ubar
         return spec_s + f + (f / 2 if dual else f)
     # the splitting variables v, w, f are recomputed where they are used
-    if kind == "rhs_u":            # ubar, grad f, Lambda (3), phi in; rhs out
-        return 7 * f
-    if kind == "rhs_tau":          # A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau in; rhs out
-        return 9 * f + n * n
     if kind == "post_u":           # object: 7 volumes in, 5 out; dual adds the tau side (10 in, 6 out)
         return 28 * f + n * n if dual else 12 * f
     return 0.0
@@ -294,7 +292,8 @@ def algorithmic_bytes(kind, n, m, dual):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("k_spectral.hip", "k_admm.hip", "fft_device.h", "cnlos_internal.h"):
+    for name in ("k_spectral.hip", "k_admm.hip", "fft_device.h", "cnlos_internal.h",
+                 "stencil_device.h"):
         with open(os.path.join(ROOT, "paper_2301_00406_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -245,14 +245,13 @@ typedef enum {
   CNLOS_KK_T_FWD_CONV = 0,   /* convolution: resample + R2C along t           */
   CNLOS_KK_PLANE_CONV = 1,   /* convolution: padded (x, y) transform with H^  */
   CNLOS_KK_T_INV_CONV = 2,   /* convolution: C2R along t + R_t^{-1} + epilogue */
-  CNLOS_KK_T_FWD_SOLVE = 3,  /* diagonal solve: R2C along t                   */
+  CNLOS_KK_T_FWD_SOLVE = 3,  /* diagonal solve: right-hand side + R2C along t */
   CNLOS_KK_PLANE_SOLVE = 4,  /* diagonal solve: (x, y) transform and divide    */
   CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t                   */
-  CNLOS_KK_VSTEP = 6,        /* steps before the u solve: v (object model);
-                                v, w and f in one kernel (dual model)          */
-  CNLOS_KK_FSTEP = 7,        /* reserved (the f step runs inside VSTEP)        */
-  CNLOS_KK_RHS_U = 8,        /* right-hand side of the u solve                 */
-  CNLOS_KK_RHS_TAU = 9,      /* right-hand side of the tau solve               */
+  CNLOS_KK_VSTEP = 6,        /* reserved (v, w, f are recomputed where used)   */
+  CNLOS_KK_FSTEP = 7,        /* reserved                                       */
+  CNLOS_KK_RHS_U = 8,        /* reserved (formed inside T_FWD_SOLVE)           */
+  CNLOS_KK_RHS_TAU = 9,      /* reserved (formed inside T_FWD_SOLVE)           */
   CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature: u (object
                                 model); u and tau in one kernel (dual model)   */
   CNLOS_KK_POST_TAU = 11,    /* reserved (the tau side runs inside POST_U)     */

@@ -435,6 +435,30 @@ bool same_shared(const cnlos_config& b, const cnlos_config& a) {
          b.eta_curv == a.eta_curv && b.backtracking == a.backtracking;
 }
 
+// the rotating-role operand r of problem p (its candidate buffers and role)
+Vol role_of(const cnlos_problem* p, int r) {
+  Vol v;
+  v.role = r;
+  if (r == R_U_CUR || r == R_U_TR) {
+    v.p[0] = p->U[0];
+    v.p[1] = p->U[1];
+  } else if (r == R_T_CUR || r == R_T_TR) {
+    v.p[0] = p->T[0];
+    v.p[1] = p->T[1];
+  } else if (r == R_UB_CUR || r == R_UB_NEW) {
+    v.p[0] = p->UB[0];
+    v.p[1] = p->UB[1];
+  } else if (r == R_TB_CUR || r == R_TB_NEW) {
+    v.p[0] = p->TB[0];
+    v.p[1] = p->TB[1];
+  } else {
+    v.p[0] = p->AU[0];
+    v.p[1] = p->AU[1];
+    v.p[2] = p->AU[2];
+  }
+  return v;
+}
+
 inline Vol fixed(const float* q) { return Vol{{const_cast<float*>(q), nullptr, nullptr}, -1}; }
 
 // One padded convolution of the problem (forward or adjoint).
@@ -545,27 +569,19 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     b.gate = g;
     return b;
   };
-  auto role = [&](int r) {
-    Vol v{{nullptr, nullptr, nullptr}, r};
-    if (r == R_U_CUR || r == R_U_TR) {
-      v.p[0] = p->U[0];
-      v.p[1] = p->U[1];
-    } else if (r == R_T_CUR || r == R_T_TR) {
-      v.p[0] = p->T[0];
-      v.p[1] = p->T[1];
-    } else if (r == R_UB_CUR || r == R_UB_NEW) {
-      v.p[0] = p->UB[0];
-      v.p[1] = p->UB[1];
-    } else if (r == R_TB_CUR || r == R_TB_NEW) {
-      v.p[0] = p->TB[0];
-      v.p[1] = p->TB[1];
-    } else {
-      v.p[0] = p->AU[0];
-      v.p[1] = p->AU[1];
-      v.p[2] = p->AU[2];
-    }
-    return v;
+  // right-hand side of the u solve, computed in the solve's t pass
+  auto rhs_u = [&](double mu) {
+    RhsSrc r;
+    r.mode = RHS_U;
+    r.xb = role_of(p, R_UB_CUR);
+    r.gf = p->gf;
+    r.lam = p->lam;
+    r.phi = p->phi;
+    r.mu = (float)mu;
+    r.logn = ln;
+    return r;
   };
+  auto role = [&](int r) { return role_of(p, r); };
 
   if (seqs & SEQ_S1) {
     const double mu = c.mu;
@@ -582,14 +598,12 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
     HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, role(R_UB_CUR), p->gf, p->lam, p->phi, mu, ctl,
-                                 gated(G | G_FIRST), p->st));
     SolveEpi se{};
     se.out = role(R_U_TR);
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu, se, ctl, gated(G), p->st,
-                        &p->prof));
+    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu), p->spec, &ctl->L, 0.0, mu, se, ctl,
+                        gated(G | G_FIRST), p->st, &p->prof));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
@@ -637,14 +651,12 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
     HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_RHS_U, launch_rhs_u(ln, lm, role(R_UB_CUR), p->gf, p->lam, p->phi, mu1, ctl,
-                                 gated(G | G_FIRST), p->st));
     SolveEpi se{};
     se.out = role(R_U_TR);
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, &ctl->L, 0.0, mu1, se, ctl, gated(G), p->st,
-                        &p->prof));
+    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu1), p->spec, &ctl->L, 0.0, mu1, se, ctl,
+                        gated(G | G_FIRST), p->st, &p->prof));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
@@ -659,14 +671,25 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
                                    gated(G), p->st));
     const int GA = G | G_AFTER_CHECK;
-    TIMED(KK_RHS_TAU, launch_rhs_tau(ln, lm, role(R_AU_TR), role(R_TB_CUR), p->lam3, p->tau0, p->mask,
-                                     p->lam2, p->phi_tau, p->gf, lam, mu2, mu3, ctl, gated(GA), p->st));
+    RhsSrc rt;
+    rt.mode = RHS_TAU;
+    rt.xb = role(R_TB_CUR);
+    rt.au = role(R_AU_TR);
+    rt.lam = p->lam2;
+    rt.phi = p->phi_tau;
+    rt.lam3 = p->lam3;
+    rt.tau0 = p->tau0;
+    rt.mask = p->mask;
+    rt.mu = (float)mu2;
+    rt.lambda = (float)lam;
+    rt.mu3 = (float)mu3;
+    rt.logn = ln;
     SolveEpi st2{};
     st2.out = role(R_T_TR);
     st2.ref = fixed(nullptr);
     st2.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, p->gf, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl, gated(GA),
-                        p->st, &p->prof));
+    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rt, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl,
+                        gated(GA), p->st, &p->prof));
     const PostArgs pu{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu1, phi_args(p, 2, false)};
     const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_TB_CUR), role(R_TB_NEW), p->lam2,

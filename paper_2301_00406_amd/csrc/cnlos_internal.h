@@ -203,6 +203,26 @@ struct ConvEpi {
   double* partials;
 };
 
+// Right-hand side of a diagonal solve computed where the solve's t pass reads
+// it, instead of being stored:
+//   RHS_U   : L ubar - grad f + nabla^*(mu v + Lambda)          (eqs. (10), (11))
+//   RHS_TAU : A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2) (tau-subproblem)
+// with v (w) and f recomputed from xbar, Lambda, phi (and Lambda3, tau0).
+enum RhsMode : int { RHS_LOAD = 0, RHS_U = 1, RHS_TAU = 2 };
+struct RhsSrc {
+  int mode = RHS_LOAD;
+  Vol xb;                    // ubar / taubar
+  Vol au;                    // A u+ (RHS_TAU)
+  const float* gf = nullptr;     // grad f (RHS_U)
+  const float* lam = nullptr;    // Lambda / Lambda2
+  const float* phi = nullptr;    // phi / phi_tau
+  const float* lam3 = nullptr;   // RHS_TAU
+  const float* tau0 = nullptr;
+  const uint8_t* mask = nullptr;
+  float mu = 1.f, lambda = 0.f, mu3 = 0.f;
+  int logn = 0;
+};
+
 // Epilogue of the t-axis inverse pass of a diagonal solve.
 struct SolveEpi {
   Vol out;
@@ -235,9 +255,10 @@ constexpr Batch kSingle{1, 0, G_NONE};
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
                        const Batch& bt, hipStream_t st, Prof* prof);
-hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
-                        const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof);
+hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, const RhsSrc& rs,
+                        float2* spec, const double* c_dev, double c_val, double mu,
+                        const SolveEpi& ep, const DevCtl* ctl, const Batch& bt, hipStream_t st,
+                        Prof* prof);
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
                            const double* cosn, double invZ, hipStream_t st);
 int conv_blocks(int logn, int logm);          // blocks of the convolution t passes
@@ -271,13 +292,6 @@ hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostAr
                             float* lam3, double mu3, double lambda, Vol au, const float* tau0,
                             const uint8_t* mask, double* partials, const DevCtl* ctl,
                             const Batch& bt, hipStream_t st);
-hipError_t launch_rhs_u(int logn, int logm, Vol ubar, float* gf_rhs, const float* lam,
-                        const float* phi, double mu, const DevCtl* ctl, const Batch& bt,
-                        hipStream_t st);
-hipError_t launch_rhs_tau(int logn, int logm, Vol au, Vol taubar, const float* lam3,
-                          const float* tau0, const uint8_t* mask, const float* lam2,
-                          const float* phi_tau, float* rhs, double lambda, double mu2, double mu3,
-                          const DevCtl* ctl, const Batch& bt, hipStream_t st);
 hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
                        const DevCtl* ctl, const Batch& bt, hipStream_t st);
 int stencil_blocks(int logn, int logm);

@@ -9,6 +9,7 @@
 
 #include "cnlos_internal.h"
 #include "fft_device.h"
+#include "stencil_device.h"
 
 namespace cnlos {
 
@@ -23,62 +24,6 @@ int stencil_blocks(int logn, int logm) {
   return (int)nb;
 }
 
-// periodic neighbour offsets of voxel g
-struct Nbr {
-  size_t xp, xm, yp, ym, tp, tm;
-};
-
-__device__ __forceinline__ Nbr neighbours(size_t g, int logn, int logm) {
-  const size_t M = (size_t)1 << logm, N = (size_t)1 << logn;
-  const size_t sx = N * M, sy = M;
-  const size_t k = g & (M - 1);
-  const size_t j = (g >> logm) & (N - 1);
-  const size_t i = g >> (logm + logn);
-  Nbr r;
-  r.xp = (i == N - 1) ? g - (N - 1) * sx : g + sx;
-  r.xm = (i == 0) ? g + (N - 1) * sx : g - sx;
-  r.yp = (j == N - 1) ? g - (N - 1) * sy : g + sy;
-  r.ym = (j == 0) ? g + (N - 1) * sy : g - sy;
-  r.tp = (k == M - 1) ? g - (M - 1) : g + 1;
-  r.tm = (k == 0) ? g + (M - 1) : g - 1;
-  return r;
-}
-
-__device__ __forceinline__ float phi_eval(float kappa, const PhiArgs& pa) {
-  const float a = (float)pa.a, b = (float)pa.b;
-  if (pa.kind == 1) return a + b * fabsf(kappa);
-  if (pa.kind == 2) return sqrtf(a + b * kappa * kappa);
-  return a + b * kappa * kappa;
-}
-
-// forward-difference gradient of x at voxel g (neighbours given)
-__device__ __forceinline__ void grad_at(const float* __restrict__ x, size_t g, size_t xp, size_t yp,
-                                        size_t tp, float& gx, float& gy, float& gt) {
-  const float x0 = x[g];
-  gx = x[xp] - x0;
-  gy = x[yp] - x0;
-  gt = x[tp] - x0;
-}
-
-// kappa = div^-( grad x / sqrt(|grad x|^2 + eta^2) ) at voxel g, plus grad x(g)
-__device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_t g, const Nbr& nb,
-                                              int logn, int logm, float eta2, float& gx0,
-                                              float& gy0, float& gt0) {
-  grad_at(x, g, nb.xp, nb.yp, nb.tp, gx0, gy0, gt0);
-  const float i0 = rsqrtf(gx0 * gx0 + gy0 * gy0 + gt0 * gt0 + eta2);
-  float ax, ay, at;
-  const Nbr bx = neighbours(nb.xm, logn, logm);
-  grad_at(x, nb.xm, bx.xp, bx.yp, bx.tp, ax, ay, at);
-  const float nxm = ax * rsqrtf(ax * ax + ay * ay + at * at + eta2);
-  const Nbr by = neighbours(nb.ym, logn, logm);
-  grad_at(x, nb.ym, by.xp, by.yp, by.tp, ax, ay, at);
-  const float nym = ay * rsqrtf(ax * ax + ay * ay + at * at + eta2);
-  const Nbr bt = neighbours(nb.tm, logn, logm);
-  grad_at(x, nb.tm, bt.xp, bt.yp, bt.tp, ax, ay, at);
-  const float ntm = at * rsqrtf(ax * ax + ay * ay + at * at + eta2);
-  return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
-}
-
 // Common head of the iteration kernels: shift the controller to this launch's
 // scene, apply the phase gate, and (first kernel of an iteration slot) clear
 // the previous slot's rejection.
@@ -90,55 +35,6 @@ __device__ __forceinline__ bool iter_head(DevCtl*& ctl, size_t zo, int gate) {
 }
 __device__ __forceinline__ float* vol_at(const Vol& v, const DevCtl* c, size_t zo) {
   return vol_resolve(v, c, zo);
-}
-
-// v = shrink(grad xbar - Lambda/mu, phi/mu) at voxel q, isotropic over the
-// three components (eq. (7); the w-step of Algorithm 2 is the same on taubar).
-// The splitting variables are never stored: every kernel that needs v (or w)
-// recomputes it from xbar, Lambda and phi, which are unchanged between the
-// v-step and its last use in the same iteration.
-__device__ __forceinline__ void v_at(const float* __restrict__ xb, const float* __restrict__ lam,
-                                     const float* __restrict__ phi, float inv_mu, size_t q,
-                                     size_t V, int logn, int logm, float& vx, float& vy,
-                                     float& vt) {
-  const Nbr nb = neighbours(q, logn, logm);
-  float gx, gy, gt;
-  grad_at(xb, q, nb.xp, nb.yp, nb.tp, gx, gy, gt);
-  const float ax = gx - lam[q] * inv_mu;
-  const float ay = gy - lam[V + q] * inv_mu;
-  const float at = gt - lam[2 * V + q] * inv_mu;
-  const float nrm = sqrtf(ax * ax + ay * ay + at * at);
-  const float thr = phi[q] * inv_mu;
-  const float s = nrm > thr ? (nrm - thr) / nrm : 0.f;
-  vx = ax * s;
-  vy = ay * s;
-  vt = at * s;
-}
-
-// f: pointwise minimizer of lambda/2 |f - tau0|^2 on kept points
-//    + <Lambda3, f - taubar> + mu3/2 |f - taubar|^2 (never stored, as v)
-// (inv_kept = 1 / (lambda + mu3), inv_mu3 = 1 / mu3)
-__device__ __forceinline__ float f_at(float tb, float l3, float t0, bool kept, float lambda,
-                                      float mu3, float inv_kept, float inv_mu3) {
-  return kept ? (lambda * t0 + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
-}
-
-// nabla^*(mu v + Lambda) at voxel g: minus the backward-difference divergence
-__device__ __forceinline__ float adj_mu_v_lam(const float* __restrict__ xb,
-                                              const float* __restrict__ lam,
-                                              const float* __restrict__ phi, float mu,
-                                              float inv_mu, size_t g, size_t V, const Nbr& nb,
-                                              int logn, int logm) {
-  float vx, vy, vt, ux, uy, ut;
-  v_at(xb, lam, phi, inv_mu, g, V, logn, logm, vx, vy, vt);
-  const float px0 = mu * vx + lam[g], py0 = mu * vy + lam[V + g], pt0 = mu * vt + lam[2 * V + g];
-  v_at(xb, lam, phi, inv_mu, nb.xm, V, logn, logm, vx, uy, ut);
-  const float pxm = mu * vx + lam[nb.xm];
-  v_at(xb, lam, phi, inv_mu, nb.ym, V, logn, logm, ux, vy, ut);
-  const float pym = mu * vy + lam[V + nb.ym];
-  v_at(xb, lam, phi, inv_mu, nb.tm, V, logn, logm, ux, uy, vt);
-  const float ptm = mu * vt + lam[2 * V + nb.tm];
-  return -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
 }
 
 // derived fields on request: v (or w) and f from the current state
@@ -165,105 +61,6 @@ k_fstep(const float* __restrict__ taubar, const float* __restrict__ lam3,
   for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
        g += (size_t)gridDim.x * blockDim.x)
     f[g] = f_at(taubar[g], lam3[g], tau0[g], mask[g >> logm] != 0, lambda, mu3, inv_kept, inv_mu3);
-}
-
-// Right-hand sides of the two diagonal solves, tiled so that each v (or w)
-// is computed about twice instead of four times: a block of 256 threads owns
-// a tile of Tx x Ty scan columns x Tt bins (Tt = min(m, 64), Ty = 2), computes
-// v on its voxels and on the backward halo faces into LDS, then forms
-//   u side:   rhs = L ubar - grad f + nabla^*(mu v + Lambda)            (eqs. (10), (11))
-//   tau side: rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem)
-// in place over grad f (u side) or into rhs (tau side).
-struct RhsTile {
-  int Tt, Ty, Tx;
-};
-inline RhsTile rhs_tile(int logn, int logm) {
-  RhsTile t;
-  t.Tt = logm >= 6 ? 64 : (1 << logm);
-  t.Ty = 2;
-  t.Tx = kStencilThreads / (t.Tt * t.Ty);
-  (void)logn;
-  return t;
-}
-constexpr int kRhsHalo = 3 * 9 * 3 * 65;   // 3 components x (Tx+1)(Ty+1)(Tt+1), upper bound
-
-template <bool TAU>
-__global__ void __launch_bounds__(kStencilThreads)
-k_rhs(Vol xb_v, const float* __restrict__ lam, const float* __restrict__ phi, float mu,
-      float* __restrict__ gf_rhs, Vol au_v, const float* __restrict__ lam3,
-      const float* __restrict__ tau0, const uint8_t* __restrict__ mask, float lambda, float mu3,
-      int Tt, int Ty, int Tx, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
-  __shared__ float vb[kRhsHalo];
-  const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  const float* __restrict__ xb = vol_at(xb_v, ctl, zo);
-  lam = zsh(lam, zo);
-  phi = zsh(phi, zo);
-  gf_rhs = zsh(gf_rhs, zo);
-  const float* __restrict__ au = TAU ? vol_at(au_v, ctl, zo) : nullptr;
-  lam3 = zsh(lam3, zo);
-  tau0 = zsh(tau0, zo);
-  mask = zsh(mask, zo);
-  const int N = 1 << logn, M = 1 << logm;
-  const size_t V = (size_t)1 << (2 * logn + logm);
-  const float inv_mu = 1.f / mu;
-  // tile origin
-  const int ntt = M / Tt, nty = N / Ty;
-  int b = blockIdx.x;
-  const int k0 = (b % ntt) * Tt;
-  b /= ntt;
-  const int j0 = (b % nty) * Ty;
-  const int i0 = (b / nty) * Tx;
-  const int SX = (Ty + 1) * (Tt + 1), SY = Tt + 1, SC = (Tx + 1) * SX;
-  auto vidx = [&](int c, int lx, int ly, int lt) { return c * SC + (lx + 1) * SX + (ly + 1) * SY + lt + 1; };
-  auto vox = [&](int i, int j, int k) {
-    i &= N - 1;
-    j &= N - 1;
-    k &= M - 1;
-    return ((size_t)i * N + j) * M + k;
-  };
-  const int tid = threadIdx.x;
-  const int lt = tid % Tt, ly = (tid / Tt) % Ty, lx = tid / (Tt * Ty);
-  const size_t g = vox(i0 + lx, j0 + ly, k0 + lt);
-  float vx, vy, vt;
-  v_at(xb, lam, phi, inv_mu, g, V, logn, logm, vx, vy, vt);
-  vb[vidx(0, lx, ly, lt)] = vx;
-  vb[vidx(1, lx, ly, lt)] = vy;
-  vb[vidx(2, lx, ly, lt)] = vt;
-  // backward halo: the x face (only its x component is used), the y face, the t line
-  const int hx = Ty * Tt, hy = Tx * Tt, ht = Tx * Ty;
-  for (int h = tid; h < hx + hy + ht; h += kStencilThreads) {
-    int ax, ay, at, c;
-    if (h < hx) {
-      ax = -1, ay = h / Tt, at = h % Tt, c = 0;
-    } else if (h < hx + hy) {
-      const int q = h - hx;
-      ax = q / Tt, ay = -1, at = q % Tt, c = 1;
-    } else {
-      const int q = h - hx - hy;
-      ax = q / Ty, ay = q % Ty, at = -1, c = 2;
-    }
-    float w[3];
-    v_at(xb, lam, phi, inv_mu, vox(i0 + ax, j0 + ay, k0 + at), V, logn, logm, w[0], w[1], w[2]);
-    vb[vidx(c, ax, ay, at)] = w[c];
-  }
-  __syncthreads();
-  const size_t gxm = vox(i0 + lx - 1, j0 + ly, k0 + lt);
-  const size_t gym = vox(i0 + lx, j0 + ly - 1, k0 + lt);
-  const size_t gtm = vox(i0 + lx, j0 + ly, k0 + lt - 1);
-  const float px0 = mu * vx + lam[g], py0 = mu * vy + lam[V + g], pt0 = mu * vt + lam[2 * V + g];
-  const float pxm = mu * vb[vidx(0, lx - 1, ly, lt)] + lam[gxm];
-  const float pym = mu * vb[vidx(1, lx, ly - 1, lt)] + lam[V + gym];
-  const float ptm = mu * vb[vidx(2, lx, ly, lt - 1)] + lam[2 * V + gtm];
-  const float adj = -((px0 - pxm) + (py0 - pym) + (pt0 - ptm));
-  if (!TAU) {
-    gf_rhs[g] = (float)ctl->L * xb[g] - gf_rhs[g] + adj;
-  } else {
-    const float l3 = lam3[g];
-    const float f = f_at(xb[g], l3, tau0[g], mask[g >> logm] != 0, lambda, mu3,
-                         1.f / (lambda + mu3), 1.f / mu3);
-    gf_rhs[g] = au[g] + mu3 * f + l3 + adj;
-  }
 }
 
 // After the accepted step: multiplier ascent (eq. (12)), FISTA extrapolation,
@@ -686,32 +483,6 @@ hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostAr
   return hipGetLastError();
 }
 
-static dim3 rhs_grid(int logn, int logm, const RhsTile& t, const Batch& bt) {
-  const int tiles = ((1 << logm) / t.Tt) * ((1 << logn) / t.Ty) * ((1 << logn) / t.Tx);
-  return dim3(tiles, 1, bt.nz);
-}
-
-hipError_t launch_rhs_u(int logn, int logm, Vol ubar, float* gf_rhs, const float* lam,
-                        const float* phi, double mu, const DevCtl* ctl, const Batch& bt,
-                        hipStream_t st) {
-  const RhsTile t = rhs_tile(logn, logm);
-  hipLaunchKernelGGL(k_rhs<false>, rhs_grid(logn, logm, t, bt), dim3(kStencilThreads), 0, st, ubar,
-                     lam, phi, (float)mu, gf_rhs, Vol{}, nullptr, nullptr, nullptr, 0.f, 0.f, t.Tt,
-                     t.Ty, t.Tx, logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
-  return hipGetLastError();
-}
-
-hipError_t launch_rhs_tau(int logn, int logm, Vol au, Vol taubar, const float* lam3,
-                          const float* tau0, const uint8_t* mask, const float* lam2,
-                          const float* phi_tau, float* rhs, double lambda, double mu2, double mu3,
-                          const DevCtl* ctl, const Batch& bt, hipStream_t st) {
-  const RhsTile t = rhs_tile(logn, logm);
-  hipLaunchKernelGGL(k_rhs<true>, rhs_grid(logn, logm, t, bt), dim3(kStencilThreads), 0, st, taubar,
-                     lam2, phi_tau, (float)mu2, rhs, au, lam3, tau0, mask, (float)lambda,
-                     (float)mu3, t.Tt, t.Ty, t.Tx, logn, logm, const_cast<DevCtl*>(ctl), bt.zs,
-                     bt.gate);
-  return hipGetLastError();
-}
 
 hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
                        const DevCtl* ctl, const Batch& bt, hipStream_t st) {

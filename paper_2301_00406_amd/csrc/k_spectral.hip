@@ -17,6 +17,7 @@
 // by ky parity to fit LDS).
 #include "cnlos_internal.h"
 #include "fft_device.h"
+#include "stencil_device.h"
 
 namespace cnlos {
 
@@ -746,10 +747,142 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
 // t pass, forward, diagonal solve: real length m -> complex length m/2 of the
 // packed pairs -> untangle -> planes kt = 0 .. m/2 - 1, the two real bins
 // kt = 0 and kt = m/2 sharing plane 0 as X_0 + i X_{m/2}.
-template <int LOGM>
+//
+// With SRC != RHS_LOAD the source is the solve's right-hand side, computed
+// here per bin (RhsSrc) instead of being read from a stored volume; the u
+// solve's instance is the first rejection-aware kernel of an iteration slot
+// and clears the previous slot's rejection (G_FIRST).
+// p = mu v + Lambda at the two bins k, k + 1 (k even) of one scan column,
+// v = shrink(grad xbar - Lambda/mu, phi/mu) as in the v-step (eq. (7)).
+// c, cxp, cyp: offsets of the column and of its x + 1 and y + 1 neighbours;
+// kn = (k + 2) mod m.  Offsets are per scene and below 2^31.
+struct PPair {
+  float2 xb;                 // xbar at the two bins
+  float px[2], py[2], pt[2];
+};
+
+// element o of q, o a 32-bit element offset (a 32-bit byte offset from the
+// uniform base, so the load takes the scalar-base addressing form)
+__device__ __forceinline__ float2 ld2(const float* __restrict__ q, uint32_t o) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(q) + (o << 2));
+}
+__device__ __forceinline__ float ld1(const float* __restrict__ q, uint32_t o) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(q) + (o << 2));
+}
+
+__device__ __forceinline__ PPair p_pair(const float* __restrict__ xb, const float* __restrict__ lam,
+                                        const float* __restrict__ phi, float mu, float inv_mu,
+                                        uint32_t V, uint32_t c, uint32_t cxp, uint32_t cyp,
+                                        uint32_t k, uint32_t kn) {
+  PPair r;
+  const float2 a = ld2(xb, c + k), ax = ld2(xb, cxp + k), ay = ld2(xb, cyp + k);
+  const float an = ld1(xb, c + kn);
+  const float2 l0 = ld2(lam, c + k), l1 = ld2(lam, V + c + k), l2 = ld2(lam, 2 * V + c + k);
+  const float2 ph = ld2(phi, c + k);
+  r.xb = a;
+  const float gx[2] = {ax.x - a.x, ax.y - a.y};
+  const float gy[2] = {ay.x - a.x, ay.y - a.y};
+  const float gt[2] = {a.y - a.x, an - a.y};
+  const float lx[2] = {l0.x, l0.y}, ly[2] = {l1.x, l1.y}, lt[2] = {l2.x, l2.y};
+  const float pv[2] = {ph.x, ph.y};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float bx = gx[h] - lx[h] * inv_mu;
+    const float by = gy[h] - ly[h] * inv_mu;
+    const float bt = gt[h] - lt[h] * inv_mu;
+    const float sh = shrink_factor(bx * bx + by * by + bt * bt, pv[h] * inv_mu);
+    r.px[h] = mu * (bx * sh) + lx[h];
+    r.py[h] = mu * (by * sh) + ly[h];
+    r.pt[h] = mu * (bt * sh) + lt[h];
+  }
+  return r;
+}
+
+// Right-hand side of a diagonal solve at the bin pairs (2p, 2p + 1),
+// p = G r + s, of the block's J scan columns, into x[r] as (rhs_2p, rhs_2p+1):
+//   u side:   rhs = L ubar - grad f + nabla^*(mu v + Lambda)             (eqs. (10), (11))
+//   tau side: rhs = A u+ + mu3 f + Lambda3 + nabla^*(mu2 w + Lambda2)   (tau-subproblem)
+// with nabla^* q = -(backward-difference divergence of q).  Each p = mu v +
+// Lambda is formed at the lane's own voxels and at their x - 1 neighbours; the
+// y - 1 neighbour's p_y comes from the neighbouring column through LDS (a
+// halo column when that column is in another block) and the t - 1
+// neighbour's p_t from the previous lane.
+template <int SRC, int G, int E, int J, int M, int NT>
+__device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, const DevCtl* ctl,
+                                          const float* __restrict__ xb,
+                                          const float* __restrict__ au, int col0, int b, int s,
+                                          int tid, int nn, float* pyl) {
+  const int logn = rs.logn;
+  const uint32_t N = 1u << logn, V = (uint32_t)nn * M;
+  const float mu = rs.mu, inv_mu = 1.f / mu;
+  auto cof = [&](uint32_t i, uint32_t j) { return (((i & (N - 1)) << logn) | (j & (N - 1))) * (uint32_t)M; };
+  const uint32_t col = col0 + b, i = col >> logn, j = col & (N - 1);
+  const uint32_t c = cof(i, j), cxp = cof(i + 1, j), cyp = cof(i, j + 1);
+  const uint32_t cxm = cof(i - 1, j), cxmyp = cof(i - 1, j + 1);
+  // p_y of the column before the block's first one (y - 1 of column col0)
+  if (J < (int)N) {
+    const uint32_t i0 = (uint32_t)col0 >> logn, j0 = col0 & (N - 1);
+    const uint32_t ch = cof(i0, j0 - 1), chxp = cof(i0 + 1, j0 - 1), chyp = cof(i0, j0);
+    for (int h = tid; h < M / 2; h += NT) {
+      const PPair q = p_pair(xb, rs.lam, rs.phi, mu, inv_mu, V, ch, chxp, chyp, 2 * h,
+                             (2 * h + 2) & (M - 1));
+      pyl[2 * h] = q.py[0];
+      pyl[2 * h + 1] = q.py[1];
+    }
+  }
+  // x gets everything but the two neighbour terms that other lanes supply
+  float t1[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const uint32_t k = 2 * (G * r + s), kn = (k + 2) & (M - 1);
+    const PPair q = p_pair(xb, rs.lam, rs.phi, mu, inv_mu, V, c, cxp, cyp, k, kn);
+    const PPair qm = p_pair(xb, rs.lam, rs.phi, mu, inv_mu, V, cxm, c, cxmyp, k, kn);
+    pyl[(b + 1) * M + k] = q.py[0];
+    pyl[(b + 1) * M + k + 1] = q.py[1];
+    float b0, b1;
+    if constexpr (SRC == RHS_U) {
+      const float L = (float)ctl->L;
+      const float2 g = ld2(rs.gf, c + k);
+      b0 = L * q.xb.x - g.x;
+      b1 = L * q.xb.y - g.y;
+    } else {
+      const float2 a = ld2(au, c + k), l3 = ld2(rs.lam3, c + k), t0 = ld2(rs.tau0, c + k);
+      const bool kept = rs.mask[col] != 0;
+      const float ik = 1.f / (rs.lambda + rs.mu3), im = 1.f / rs.mu3;
+      const float f0 = f_at(q.xb.x, l3.x, t0.x, kept, rs.lambda, rs.mu3, ik, im);
+      const float f1 = f_at(q.xb.y, l3.y, t0.y, kept, rs.lambda, rs.mu3, ik, im);
+      b0 = a.x + rs.mu3 * f0 + l3.x;
+      b1 = a.y + rs.mu3 * f1 + l3.y;
+    }
+    x[r].x = b0 - ((q.px[0] - qm.px[0]) + q.py[0] + q.pt[0]);
+    x[r].y = b1 - ((q.px[1] - qm.px[1]) + q.py[1] + (q.pt[1] - q.pt[0]));
+    t1[r] = q.pt[1];
+    // finish this pair here (no sinking of its arithmetic past the loop), one
+    // pair's loads in flight at a time: no spills
+    asm volatile("" : "+v"(x[r].x), "+v"(x[r].y), "+v"(t1[r]));
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // p_t at bin k - 1: the second bin of the previous lane's pair (lane G - 1
+  // of the previous r for s = 0; bin m - 1 for k = 0)
+  float up[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) up[r] = __shfl(t1[r], (s + G - 1) & (G - 1), G);
+  __syncthreads();
+  // slot of the y - 1 neighbour column: previous column, the same row's last
+  // column when the block holds whole rows, else the halo
+  const int ym = j > 0 ? b : (J >= (int)N ? b + (int)N : 0);
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = 2 * (G * r + s);
+    x[r].x += pyl[ym * M + k] + (s > 0 ? up[r] : up[(r + E - 1) % E]);
+    x[r].y += pyl[ym * M + k + 1];
+  }
+}
+
+template <int LOGM, int SRC>
 __global__ void __launch_bounds__(TGeo<LOGM - 1>::NT)
-k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
-             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl,
+k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict__ tw,
+             const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, DevCtl* ctl,
              size_t zs, int gate) {
   using T = TGeo<LOGM - 1>;
   constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
@@ -761,7 +894,7 @@ k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
   if (gated_off(ctl, gate)) return;
-  src = zsh(src, zo);
+  if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   spec = zsh(spec, zo);
@@ -769,10 +902,26 @@ k_tfwd_solve(const float* __restrict__ src, const float2* __restrict__ tw,
   const int col0 = blockIdx.x * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
   for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
-  const float2* src2 = reinterpret_cast<const float2*>(src) + (size_t)col * H;
   float2 x[E];
+  if constexpr (SRC == RHS_LOAD) {
+    src = zsh(src, zo);
+    const float2* src2 = reinterpret_cast<const float2*>(src) + (size_t)col * H;
 #pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = src2[G * r + s];
+    for (int r = 0; r < E; ++r) x[r] = src2[G * r + s];
+  } else {
+    const float* xb = vol_resolve(rs.xb, ctl, zo);
+    const float* au = SRC == RHS_TAU ? vol_resolve(rs.au, ctl, zo) : nullptr;
+    rs.gf = zsh(rs.gf, zo);
+    rs.lam = zsh(rs.lam, zo);
+    rs.phi = zsh(rs.phi, zo);
+    rs.lam3 = zsh(rs.lam3, zo);
+    rs.tau0 = zsh(rs.tau0, zo);
+    rs.mask = zsh(rs.mask, zo);
+    // p_y of the halo column and of the block's columns: [J + 1][m] floats
+    static_assert((J + 1) * M <= 2 * LDS2, "p_y staging does not fit the transform's LDS");
+    rhs_pairs<SRC, G, E, J, M, NT>(x, rs, ctl, xb, au, col0, b, s, tid, nn,
+                                   reinterpret_cast<float*>(lds));
+  }
   __syncthreads();
   dif_inlane<G, E, E / 2>(x, s, twc);
   dif_xlane<G, E>(x, s, twc);
@@ -994,17 +1143,32 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
 }
 
 template <int LOGN, int LOGM>
-static hipError_t solve_impl(const Tables& tb, const float* rhs, float2* spec, const double* c_dev,
-                             double c_val, double mu, const SolveEpi& ep, const DevCtl* ctl,
-                             const Batch& bt, hipStream_t st, Prof* prof) {
+static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& rs, float2* spec,
+                             const double* c_dev, double c_val, double mu, const SolveEpi& ep,
+                             const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   using TG = TGeo<LOGM - 1>;
   const int nb = NN / TG::J;
   const int nz = bt.nz, g = bt.gate;
   const size_t zs = bt.zs;
-  CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
-              hipLaunchKernelGGL(k_tfwd_solve<LOGM>, dim3(nb, 1, nz), dim3(TG::NT), 0, st, rhs,
-                                 tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
+  DevCtl* c = const_cast<DevCtl*>(ctl);
+  switch (rs.mode) {
+    case RHS_U:
+      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_U>), dim3(nb, 1, nz), dim3(TG::NT), 0,
+                                     st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+      break;
+    case RHS_TAU:
+      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_TAU>), dim3(nb, 1, nz), dim3(TG::NT), 0,
+                                     st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+      break;
+    default:
+      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_LOAD>), dim3(nb, 1, nz), dim3(TG::NT),
+                                     0, st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+      break;
+  }
   CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
               hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2, 1, nz),
                                  dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
@@ -1045,10 +1209,11 @@ hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src,
   CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof)
 }
 
-hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, float2* spec,
-                        const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                        const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof) {
-  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof)
+hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, const RhsSrc& rs,
+                        float2* spec, const double* c_dev, double c_val, double mu,
+                        const SolveEpi& ep, const DevCtl* ctl, const Batch& bt, hipStream_t st,
+                        Prof* prof) {
+  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, rs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof)
 }
 
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,

@@ -1,0 +1,106 @@
+// Device helpers of the difference operators and the splitting steps
+// (Sections 3.1 and 4.1), shared by the stencil kernels and the kernels that
+// fold a right-hand side into a transform.  Volumes are [n][n][m], t fastest,
+// periodic, unit spacing.
+#pragma once
+#include <math.h>
+
+#include "cnlos_internal.h"
+
+namespace cnlos {
+
+// periodic neighbour offsets of voxel g
+struct Nbr {
+  size_t xp, xm, yp, ym, tp, tm;
+};
+
+__device__ __forceinline__ Nbr neighbours(size_t g, int logn, int logm) {
+  const size_t M = (size_t)1 << logm, N = (size_t)1 << logn;
+  const size_t sx = N * M, sy = M;
+  const size_t k = g & (M - 1);
+  const size_t j = (g >> logm) & (N - 1);
+  const size_t i = g >> (logm + logn);
+  Nbr r;
+  r.xp = (i == N - 1) ? g - (N - 1) * sx : g + sx;
+  r.xm = (i == 0) ? g + (N - 1) * sx : g - sx;
+  r.yp = (j == N - 1) ? g - (N - 1) * sy : g + sy;
+  r.ym = (j == 0) ? g + (N - 1) * sy : g - sy;
+  r.tp = (k == M - 1) ? g - (M - 1) : g + 1;
+  r.tm = (k == 0) ? g + (M - 1) : g - 1;
+  return r;
+}
+
+__device__ __forceinline__ float phi_eval(float kappa, const PhiArgs& pa) {
+  const float a = (float)pa.a, b = (float)pa.b;
+  if (pa.kind == 1) return a + b * fabsf(kappa);
+  if (pa.kind == 2) return sqrtf(a + b * kappa * kappa);
+  return a + b * kappa * kappa;
+}
+
+// forward-difference gradient of x at voxel g (neighbours given)
+__device__ __forceinline__ void grad_at(const float* __restrict__ x, size_t g, size_t xp, size_t yp,
+                                        size_t tp, float& gx, float& gy, float& gt) {
+  const float x0 = x[g];
+  gx = x[xp] - x0;
+  gy = x[yp] - x0;
+  gt = x[tp] - x0;
+}
+
+// kappa = div^-( grad x / sqrt(|grad x|^2 + eta^2) ) at voxel g, plus grad x(g)
+__device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_t g, const Nbr& nb,
+                                              int logn, int logm, float eta2, float& gx0,
+                                              float& gy0, float& gt0) {
+  grad_at(x, g, nb.xp, nb.yp, nb.tp, gx0, gy0, gt0);
+  const float i0 = rsqrtf(gx0 * gx0 + gy0 * gy0 + gt0 * gt0 + eta2);
+  float ax, ay, at;
+  const Nbr bx = neighbours(nb.xm, logn, logm);
+  grad_at(x, nb.xm, bx.xp, bx.yp, bx.tp, ax, ay, at);
+  const float nxm = ax * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const Nbr by = neighbours(nb.ym, logn, logm);
+  grad_at(x, nb.ym, by.xp, by.yp, by.tp, ax, ay, at);
+  const float nym = ay * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const Nbr bt = neighbours(nb.tm, logn, logm);
+  grad_at(x, nb.tm, bt.xp, bt.yp, bt.tp, ax, ay, at);
+  const float ntm = at * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
+}
+
+// factor s of the isotropic shrinkage shrink(a, thr) = s a for |a|^2 = n2:
+// max(1 - thr / |a|, 0), branch-free through the hardware reciprocal square
+// root; |a| <= 1e-15 is taken as a = 0 (the shrunk vector is then below
+// 1e-15 in every case).
+__device__ __forceinline__ float shrink_factor(float n2, float thr) {
+  const float inv = n2 > 1e-30f ? __builtin_amdgcn_rsqf(n2) : 0.f;
+  return fmaxf(1.f - thr * inv, 0.f);
+}
+
+// v = shrink(grad xbar - Lambda/mu, phi/mu) at voxel q, isotropic over the
+// three components (eq. (7); the w-step of Algorithm 2 is the same on taubar).
+// The splitting variables are never stored: every kernel that needs v (or w)
+// recomputes it from xbar, Lambda and phi, which are unchanged between the
+// v-step and its last use in the same iteration.
+__device__ __forceinline__ void v_at(const float* __restrict__ xb, const float* __restrict__ lam,
+                                     const float* __restrict__ phi, float inv_mu, size_t q,
+                                     size_t V, int logn, int logm, float& vx, float& vy,
+                                     float& vt) {
+  const Nbr nb = neighbours(q, logn, logm);
+  float gx, gy, gt;
+  grad_at(xb, q, nb.xp, nb.yp, nb.tp, gx, gy, gt);
+  const float ax = gx - lam[q] * inv_mu;
+  const float ay = gy - lam[V + q] * inv_mu;
+  const float at = gt - lam[2 * V + q] * inv_mu;
+  const float s = shrink_factor(ax * ax + ay * ay + at * at, phi[q] * inv_mu);
+  vx = ax * s;
+  vy = ay * s;
+  vt = at * s;
+}
+
+// f: pointwise minimizer of lambda/2 |f - tau0|^2 on kept points
+//    + <Lambda3, f - taubar> + mu3/2 |f - taubar|^2 (never stored, as v)
+// (inv_kept = 1 / (lambda + mu3), inv_mu3 = 1 / mu3)
+__device__ __forceinline__ float f_at(float tb, float l3, float t0, bool kept, float lambda,
+                                      float mu3, float inv_kept, float inv_mu3) {
+  return kept ? (lambda * t0 + mu3 * tb - l3) * inv_kept : tb - l3 * inv_mu3;
+}
+
+}  // namespace cnlos
