@@ -245,6 +245,14 @@ struct Tables {
 // All launchers return hipGetLastError() of their launch.
 // Launch geometry of a batch: nz scenes at a workspace stride of zs bytes
 // (nz = 1, zs = 0 for a single problem), and the phase gate of the launch.
+// XCD-aware block order.  Workgroups are dealt round-robin over the 8 XCDs,
+// each with its own L2; logical block xcd_block(b, nb) places nb / 8
+// consecutive logical blocks on one XCD, so blocks that read each other's
+// neighbour columns share an L2 (identity when nb is not a multiple of 8).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  return (nb & 7) ? b : (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 struct Batch {
   int nz;
   size_t zs;

@@ -63,55 +63,131 @@ k_fstep(const float* __restrict__ taubar, const float* __restrict__ lam3,
     f[g] = f_at(taubar[g], lam3[g], tau0[g], mask[g >> logm] != 0, lambda, mu3, inv_kept, inv_mu3);
 }
 
+// Contiguous range of bin pairs of this block: XCD-aware order, so that the
+// blocks of one XCD cover one contiguous part of the volume and the x / y
+// neighbour columns a pair reads are mostly in that XCD's L2.
+struct PairRange {
+  uint32_t q0, q1;
+};
+__device__ __forceinline__ PairRange pair_range(uint32_t P) {
+  const uint32_t nb = gridDim.x, L = xcd_block(blockIdx.x, nb);
+  const uint32_t chunk = ((P + nb - 1) / nb + blockDim.x - 1) / blockDim.x * blockDim.x;
+  PairRange r;
+  r.q0 = min(P, L * chunk);
+  r.q1 = min(P, r.q0 + chunk);
+  return r;
+}
+
 // After the accepted step: multiplier ascent (eq. (12)), FISTA extrapolation,
-// curvature weight refresh, and the FP64 energy/residual partials.
+// curvature weight refresh, and the FP64 energy/residual partials, on the bin
+// pair (k, k + 1) of one scan column.
 // u mode : Lambda += mu (v - grad x+), xbar', phi_u; partials TV_U, PRIMAL, DUAL.
 // tau mode: Lambda2 += mu2 (w - grad tau+), Lambda3 += mu3 (f - tau+), taubar',
 //           phi_tau; partials TV_TAU, FIT (|A u+ - tau+|^2), FID (|D(tau+ - tau0)|^2).
 // v (w) and f are those of this iteration: recomputed from the xbar, Lambda and
 // phi the iteration started from, read here before they are overwritten.
+// The curvature kappa = div^-( grad x+ / sqrt(|grad x+|^2 + eta^2) ) needs the
+// gradient at the voxel and at its x - 1, y - 1 and t - 1 neighbours; for bin
+// k + 1 the t - 1 neighbour is bin k.
 template <bool TAU>
-__device__ __forceinline__ void post_at(const float* __restrict__ xn, const float* __restrict__ xo,
-                                        const float* __restrict__ xb, float* __restrict__ lam,
-                                        float* __restrict__ xbn, float* __restrict__ phi,
-                                        float mu, const PhiArgs& pa, float eta2, float beta,
-                                        float* __restrict__ lam3, float mu3, float lambda,
-                                        const float* __restrict__ au,
-                                        const float* __restrict__ tau0,
-                                        const uint8_t* __restrict__ mask, size_t g, size_t V,
-                                        const Nbr& nb, int logn, int logm, double& s_tv,
-                                        double& s_a, double& s_b) {
-  float vx, vy, vt;
-  v_at(xb, lam, phi, 1.f / mu, g, V, logn, logm, vx, vy, vt);
-  float gx, gy, gt;
-  const float kappa = curvature_at(xn, g, nb, logn, logm, eta2, gx, gy, gt);
-  const float ph = phi_eval(kappa, pa);
-  phi[g] = ph;
-  lam[g] += mu * (vx - gx);
-  lam[V + g] += mu * (vy - gy);
-  lam[2 * V + g] += mu * (vt - gt);
-  const float x0 = xn[g];
-  const float d0 = x0 - xo[g];
-  xbn[g] = x0 + beta * d0;
-  const float gn = sqrtf(gx * gx + gy * gy + gt * gt);
-  s_tv += (double)ph * (double)gn;
+__device__ __forceinline__ void post_pair(const float* __restrict__ xn,
+                                          const float* __restrict__ xo,
+                                          const float* __restrict__ xb, float* __restrict__ lam,
+                                          float* __restrict__ xbn, float* __restrict__ phi,
+                                          float mu, const PhiArgs& pa, float eta2, float beta,
+                                          float* __restrict__ lam3, float mu3, float lambda,
+                                          const float* __restrict__ au,
+                                          const float* __restrict__ tau0,
+                                          const uint8_t* __restrict__ mask, uint32_t V,
+                                          const PairOff& o, double& s_tv, double& s_a,
+                                          double& s_b) {
+  const uint32_t ck = o.c + o.k;
+  // v = shrink(grad xbar - Lambda/mu, phi/mu) at both bins (eq. (7))
+  const float inv_mu = 1.f / mu;
+  const float2 b0 = ld2(xb, ck), bx = ld2(xb, o.cxp + o.k), by = ld2(xb, o.cyp + o.k);
+  const float bn = ld1(xb, o.c + o.kn);
+  const float2 l0 = ld2(lam, ck), l1 = ld2(lam, V + ck), l2 = ld2(lam, 2 * V + ck);
+  const float2 p0 = ld2(phi, ck);
+  const float gb[2][3] = {{bx.x - b0.x, by.x - b0.x, b0.y - b0.x},
+                          {bx.y - b0.y, by.y - b0.y, bn - b0.y}};
+  const float lm[2][3] = {{l0.x, l1.x, l2.x}, {l0.y, l1.y, l2.y}};
+  const float pold[2] = {p0.x, p0.y};
+  float v[2][3];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float ax = gb[h][0] - lm[h][0] * inv_mu;
+    const float ay = gb[h][1] - lm[h][1] * inv_mu;
+    const float at = gb[h][2] - lm[h][2] * inv_mu;
+    const float sh = shrink_factor(ax * ax + ay * ay + at * at, pold[h] * inv_mu);
+    v[h][0] = ax * sh;
+    v[h][1] = ay * sh;
+    v[h][2] = at * sh;
+  }
+  // gradients of x+ at the pair and at the neighbours the curvature reaches
+  const float2 a = ld2(xn, ck), ax = ld2(xn, o.cxp + o.k), ay = ld2(xn, o.cyp + o.k);
+  const float an = ld1(xn, o.c + o.kn);
+  const float2 mx = ld2(xn, o.cxm + o.k), mxy = ld2(xn, o.cxmyp + o.k);
+  const float mxn = ld1(xn, o.cxm + o.kn);
+  const float2 my = ld2(xn, o.cym + o.k), myx = ld2(xn, o.cymxp + o.k);
+  const float myn = ld1(xn, o.cym + o.kn);
+  const float tm = ld1(xn, o.c + o.km), tmx = ld1(xn, o.cxp + o.km), tmy = ld1(xn, o.cyp + o.km);
+  const float x0[2] = {a.x, a.y};
+  const float g[2][3] = {{ax.x - a.x, ay.x - a.x, a.y - a.x}, {ax.y - a.y, ay.y - a.y, an - a.y}};
+  const float gxm[2][3] = {{a.x - mx.x, mxy.x - mx.x, mx.y - mx.x},
+                           {a.y - mx.y, mxy.y - mx.y, mxn - mx.y}};
+  const float gym[2][3] = {{myx.x - my.x, a.x - my.x, my.y - my.x},
+                           {myx.y - my.y, a.y - my.y, myn - my.y}};
+  const float gtm[3] = {tmx - tm, tmy - tm, a.x - tm};
+  auto n2 = [](const float (&q)[3]) { return q[0] * q[0] + q[1] * q[1] + q[2] * q[2]; };
+  float i0[2], ph[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) i0[h] = rsq(n2(g[h]) + eta2);
+  const float ntm[2] = {gtm[2] * rsq(n2(gtm) + eta2), g[0][2] * i0[0]};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float nxm = gxm[h][0] * rsq(n2(gxm[h]) + eta2);
+    const float nym = gym[h][1] * rsq(n2(gym[h]) + eta2);
+    const float kappa = (g[h][0] * i0[h] - nxm) + (g[h][1] * i0[h] - nym) + (g[h][2] * i0[h] - ntm[h]);
+    ph[h] = phi_eval(kappa, pa);
+  }
+  st2(phi, ck, make_float2(ph[0], ph[1]));
+  st2(lam, ck, make_float2(l0.x + mu * (v[0][0] - g[0][0]), l0.y + mu * (v[1][0] - g[1][0])));
+  st2(lam, V + ck, make_float2(l1.x + mu * (v[0][1] - g[0][1]), l1.y + mu * (v[1][1] - g[1][1])));
+  st2(lam, 2 * V + ck,
+      make_float2(l2.x + mu * (v[0][2] - g[0][2]), l2.y + mu * (v[1][2] - g[1][2])));
+  const float2 q0 = ld2(xo, ck);
+  const float d[2] = {a.x - q0.x, a.y - q0.y};
+  st2(xbn, ck, make_float2(a.x + beta * d[0], a.y + beta * d[1]));
+#pragma unroll
+  for (int h = 0; h < 2; ++h) s_tv += (double)ph[h] * (double)__builtin_amdgcn_sqrtf(n2(g[h]));
   if (!TAU) {
-    const float rx = vx - gx, ry = vy - gy, rt = vt - gt;
-    s_a += (double)rx * rx + (double)ry * ry + (double)rt * rt;
-    const float dx = (xn[nb.xp] - xo[nb.xp]) - d0;
-    const float dy = (xn[nb.yp] - xo[nb.yp]) - d0;
-    const float dt = (xn[nb.tp] - xo[nb.tp]) - d0;
-    s_b += (double)dx * dx + (double)dy * dy + (double)dt * dt;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float rx = v[h][0] - g[h][0], ry = v[h][1] - g[h][1], rt = v[h][2] - g[h][2];
+      s_a += (double)rx * rx + (double)ry * ry + (double)rt * rt;
+    }
+    const float2 qx = ld2(xo, o.cxp + o.k), qy = ld2(xo, o.cyp + o.k);
+    const float qn = ld1(xo, o.c + o.kn);
+    const float dn[2][3] = {{(ax.x - qx.x) - d[0], (ay.x - qy.x) - d[0], d[1] - d[0]},
+                            {(ax.y - qx.y) - d[1], (ay.y - qy.y) - d[1], (an - qn) - d[1]}};
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      s_b += (double)dn[h][0] * dn[h][0] + (double)dn[h][1] * dn[h][1] +
+             (double)dn[h][2] * dn[h][2];
   } else {
-    const bool kept = mask[g >> logm] != 0;
-    const float l3 = lam3[g];
-    const float f = f_at(xb[g], l3, tau0[g], kept, lambda, mu3, 1.f / (lambda + mu3), 1.f / mu3);
-    lam3[g] = l3 + mu3 * (f - x0);
-    const float r = au[g] - x0;
-    s_a += (double)r * r;
+    const bool kept = mask[o.col] != 0;
+    const float2 l3 = ld2(lam3, ck), t0 = ld2(tau0, ck), av = ld2(au, ck);
+    const float ik = 1.f / (lambda + mu3), im = 1.f / mu3;
+    const float f0 = f_at(b0.x, l3.x, t0.x, kept, lambda, mu3, ik, im);
+    const float f1 = f_at(b0.y, l3.y, t0.y, kept, lambda, mu3, ik, im);
+    st2(lam3, ck, make_float2(l3.x + mu3 * (f0 - x0[0]), l3.y + mu3 * (f1 - x0[1])));
+    const float r0 = av.x - x0[0], r1 = av.y - x0[1];
+    s_a += (double)r0 * r0;
+    s_a += (double)r1 * r1;
     if (kept) {
-      const float e = x0 - tau0[g];
-      s_b += (double)e * e;
+      const float e0 = x0[0] - t0.x, e1 = x0[1] - t0.y;
+      s_b += (double)e0 * e0;
+      s_b += (double)e1 * e1;
     }
   }
 }
@@ -129,17 +205,17 @@ k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* c
   pu.lam = zsh(pu.lam, zo);
   pu.phi = zsh(pu.phi, zo);
   partials = zsh(partials, zo);
-  const size_t V = (size_t)1 << (2 * logn + logm);
+  const uint32_t V = 1u << (2 * logn + logm), P = V / 2;
   const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)((t - 1.0) / tn);
   const float eta2 = pu.pa.eta * pu.pa.eta;
   double s_tv = 0.0, s_a = 0.0, s_b = 0.0;
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x)
-    post_at<false>(xn, xo, xb, pu.lam, xbn, pu.phi, pu.mu, pu.pa, eta2, beta, nullptr, 0.f, 0.f,
-                   nullptr, nullptr, nullptr, g, V, neighbours(g, logn, logm), logn, logm, s_tv,
-                   s_a, s_b);
+  const PairRange pr = pair_range(P);
+  for (uint32_t q = pr.q0 + threadIdx.x; q < pr.q1; q += blockDim.x)
+    post_pair<false>(xn, xo, xb, pu.lam, xbn, pu.phi, pu.mu, pu.pa, eta2, beta, nullptr, 0.f,
+                     0.f, nullptr, nullptr, nullptr, V, pair_offsets(q, logn, logm), s_tv, s_a,
+                     s_b);
   double vals[3] = {s_tv, s_a, s_b};
   const int slots[3] = {SL_TV_U, SL_PRIMAL, SL_DUAL};
   block_sum_store<3>(vals, partials, slots, kMaxBlocks);
@@ -169,19 +245,19 @@ k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float
   tau0 = zsh(tau0, zo);
   mask = zsh(mask, zo);
   partials = zsh(partials, zo);
-  const size_t V = (size_t)1 << (2 * logn + logm);
+  const uint32_t V = 1u << (2 * logn + logm), P = V / 2;
   const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)((t - 1.0) / tn);
   const float eu = pu.pa.eta * pu.pa.eta, et = pt.pa.eta * pt.pa.eta;
   double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < V;
-       g += (size_t)gridDim.x * blockDim.x) {
-    const Nbr nb = neighbours(g, logn, logm);
-    post_at<false>(uxn, uxo, uxb, pu.lam, uxbn, pu.phi, pu.mu, pu.pa, eu, beta, nullptr, 0.f, 0.f,
-                   nullptr, nullptr, nullptr, g, V, nb, logn, logm, s[0], s[1], s[2]);
-    post_at<true>(txn, txo, txb, pt.lam, txbn, pt.phi, pt.mu, pt.pa, et, beta, lam3, mu3, lambda,
-                  au, tau0, mask, g, V, nb, logn, logm, s[3], s[4], s[5]);
+  const PairRange pr = pair_range(P);
+  for (uint32_t q = pr.q0 + threadIdx.x; q < pr.q1; q += blockDim.x) {
+    const PairOff o = pair_offsets(q, logn, logm);
+    post_pair<false>(uxn, uxo, uxb, pu.lam, uxbn, pu.phi, pu.mu, pu.pa, eu, beta, nullptr, 0.f,
+                     0.f, nullptr, nullptr, nullptr, V, o, s[0], s[1], s[2]);
+    post_pair<true>(txn, txo, txb, pt.lam, txbn, pt.phi, pt.mu, pt.pa, et, beta, lam3, mu3,
+                    lambda, au, tau0, mask, V, o, s[3], s[4], s[5]);
   }
   const int slots[6] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_TV_TAU, SL_FIT, SL_FID};
   block_sum_store<6>(s, partials, slots, kMaxBlocks);

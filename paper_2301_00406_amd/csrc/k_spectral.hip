@@ -105,7 +105,7 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   src.mask = zsh(src.mask, zo);
   src.scale_div = zsh(src.scale_div, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
-  const int col0 = blockIdx.x * J, col = col0 + b;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) {
     tws[i] = tw[i];
     twc[i] = twcg[i];
@@ -223,7 +223,7 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   ep.tau0 = zsh(ep.tau0, zo);
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
-  const int col0 = blockIdx.x * J, col = col0 + b;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) {
     tws[i] = tw[i];
     twc[i] = twcg[i];
@@ -761,15 +761,6 @@ struct PPair {
   float px[2], py[2], pt[2];
 };
 
-// element o of q, o a 32-bit element offset (a 32-bit byte offset from the
-// uniform base, so the load takes the scalar-base addressing form)
-__device__ __forceinline__ float2 ld2(const float* __restrict__ q, uint32_t o) {
-  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(q) + (o << 2));
-}
-__device__ __forceinline__ float ld1(const float* __restrict__ q, uint32_t o) {
-  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(q) + (o << 2));
-}
-
 __device__ __forceinline__ PPair p_pair(const float* __restrict__ xb, const float* __restrict__ lam,
                                         const float* __restrict__ phi, float mu, float inv_mu,
                                         uint32_t V, uint32_t c, uint32_t cxp, uint32_t cyp,
@@ -899,7 +890,7 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
   twcg = zsh(twcg, zo);
   spec = zsh(spec, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
-  const int col0 = blockIdx.x * J, col = col0 + b;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
   for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
   float2 x[E];
@@ -978,7 +969,7 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   const float* eref = vol_in(ep.ref, ctl, zo);
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
-  const int col0 = blockIdx.x * J, col = col0 + b;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) tws[i] = tw[i];
   for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
   for (int it = tid; it < H * J; it += NT) {

@@ -9,6 +9,54 @@
 
 namespace cnlos {
 
+// element o of q for a 32-bit element offset o (a 32-bit byte offset from
+// the uniform base, so the access takes the scalar-base addressing form);
+// offsets are per scene, below 2^30 elements
+__device__ __forceinline__ float2 ld2(const float* __restrict__ q, uint32_t o) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(q) + (o << 2));
+}
+__device__ __forceinline__ float ld1(const float* __restrict__ q, uint32_t o) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(q) + (o << 2));
+}
+__device__ __forceinline__ void st2(float* __restrict__ q, uint32_t o, float2 v) {
+  *reinterpret_cast<float2*>(reinterpret_cast<char*>(q) + (o << 2)) = v;
+}
+
+// reciprocal square root of an argument that is never zero or denormal
+// (|g|^2 + eta^2 with eta > 0)
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Offsets of a bin pair (k, k + 1), k even, of one scan column and of the
+// neighbour columns the difference operators reach (periodic in x, y, t).
+struct PairOff {
+  uint32_t col;                            // scan column i n + j
+  uint32_t c, cxp, cyp, cxm, cym;          // column offsets (times m): own, x+1, y+1, x-1, y-1
+  uint32_t cxmyp, cymxp;                   // (x-1, y+1), (x+1, y-1)
+  uint32_t k, kn, km;                      // k, (k + 2) mod m, (k - 1) mod m
+};
+
+__device__ __forceinline__ PairOff pair_offsets(uint32_t q, int logn, int logm) {
+  const uint32_t N = 1u << logn, M = 1u << logm;
+  const uint32_t col = q >> (logm - 1), k = 2 * (q & (M / 2 - 1));
+  const uint32_t i = col >> logn, j = col & (N - 1);
+  auto cof = [&](uint32_t a, uint32_t b) {
+    return (((a & (N - 1)) << logn) | (b & (N - 1))) << logm;
+  };
+  PairOff o;
+  o.col = col;
+  o.c = col << logm;
+  o.cxp = cof(i + 1, j);
+  o.cyp = cof(i, j + 1);
+  o.cxm = cof(i - 1, j);
+  o.cym = cof(i, j - 1);
+  o.cxmyp = cof(i - 1, j + 1);
+  o.cymxp = cof(i + 1, j - 1);
+  o.k = k;
+  o.kn = (k + 2) & (M - 1);
+  o.km = (k - 1) & (M - 1);
+  return o;
+}
+
 // periodic neighbour offsets of voxel g
 struct Nbr {
   size_t xp, xm, yp, ym, tp, tm;
@@ -51,17 +99,17 @@ __device__ __forceinline__ float curvature_at(const float* __restrict__ x, size_
                                               int logn, int logm, float eta2, float& gx0,
                                               float& gy0, float& gt0) {
   grad_at(x, g, nb.xp, nb.yp, nb.tp, gx0, gy0, gt0);
-  const float i0 = rsqrtf(gx0 * gx0 + gy0 * gy0 + gt0 * gt0 + eta2);
+  const float i0 = rsq(gx0 * gx0 + gy0 * gy0 + gt0 * gt0 + eta2);
   float ax, ay, at;
   const Nbr bx = neighbours(nb.xm, logn, logm);
   grad_at(x, nb.xm, bx.xp, bx.yp, bx.tp, ax, ay, at);
-  const float nxm = ax * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const float nxm = ax * rsq(ax * ax + ay * ay + at * at + eta2);
   const Nbr by = neighbours(nb.ym, logn, logm);
   grad_at(x, nb.ym, by.xp, by.yp, by.tp, ax, ay, at);
-  const float nym = ay * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const float nym = ay * rsq(ax * ax + ay * ay + at * at + eta2);
   const Nbr bt = neighbours(nb.tm, logn, logm);
   grad_at(x, nb.tm, bt.xp, bt.yp, bt.tp, ax, ay, at);
-  const float ntm = at * rsqrtf(ax * ax + ay * ay + at * at + eta2);
+  const float ntm = at * rsq(ax * ax + ay * ay + at * at + eta2);
   return (gx0 * i0 - nxm) + (gy0 * i0 - nym) + (gt0 * i0 - ntm);
 }
 
