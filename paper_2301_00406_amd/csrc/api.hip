@@ -1077,7 +1077,18 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
   }
   std::vector<int4> srows(m), scols(m);
   std::vector<float> srv, scv;
+  // the t pass computes rows of more than 3 taps from prefix sums of the first
+  // resample_scan_rows lane-rows of the column and takes their interior
+  // weights as 1: check both
+  const int lanes = m / 2 < 64 ? m / 2 : 64;
+  const int scan_end = resample_scan_rows(m, lanes) * lanes;
   for (int q = 0; q < m; ++q) {
+    if (rows[q].size() > 3) {
+      if (rows[q].back().first + 1 > scan_end)
+        return fail(CNLOS_EINVAL, "long resampling row beyond the prefix-summed range");
+      for (size_t t = 1; t + 1 < rows[q].size(); ++t)
+        if ((float)rows[q][t].second != 1.f) return fail(CNLOS_EINVAL, "resampling interior weight is not 1");
+    }
     srows[q] = make_int4(rows[q].empty() ? 0 : rows[q][0].first, (int)rows[q].size(), (int)srv.size(), 0);
     for (size_t t = 0; t < rows[q].size(); ++t) {
       if (rows[q][t].first != rows[q][0].first + (int)t) return fail(CNLOS_EINVAL, "resampling row not contiguous");
@@ -1085,6 +1096,7 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
     }
   }
   for (int k = 0; k < m; ++k) {
+    if (cols[k].size() > 3) return fail(CNLOS_EINVAL, "resampling column of more than 3 taps");
     scols[k] = make_int4(cols[k].empty() ? 0 : cols[k][0].first, (int)cols[k].size(), (int)scv.size(), 0);
     for (size_t t = 0; t < cols[k].size(); ++t) {
       if (cols[k][t].first != cols[k][0].first + (int)t) return fail(CNLOS_EINVAL, "resampling column not contiguous");

@@ -245,6 +245,14 @@ struct Tables {
 // All launchers return hipGetLastError() of their launch.
 // Launch geometry of a batch: nz scenes at a workspace stride of zs bytes
 // (nz = 1, zs = 0 for a single problem), and the phase gate of the launch.
+// Lane-rows of a t-pass column (G lanes, m / G rows) whose prefix sums the
+// R_z rows of more than 3 taps use: those rows end below m/4 + 8 (the table
+// builder checks it).
+constexpr int resample_scan_rows(int M, int G) {
+  const int r = (M / 4 + 8 + G - 1) / G;
+  return r < M / G ? r : M / G;
+}
+
 // XCD-aware block order.  Workgroups are dealt round-robin over the 8 XCDs,
 // each with its own L2; logical block xcd_block(b, nb) places nb / 8
 // consecutive logical blocks on one XCD, so blocks that read each other's

@@ -126,6 +126,8 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   const float sc = src.scale_div ? (float)(1.0 / *src.scale_div) : 1.f;
   const float mk = src.mask ? (float)src.mask[col] : 1.f;
   float* xf = reinterpret_cast<float*>(lds + b * ZS);     // this column's real input
+  float* pf = xf + M;                                      // its prefix sums (below)
+  float xv[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = G * r + s;
@@ -134,7 +136,27 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
     if (sb) x += cb * sb[g];
     if (sc_) x -= sc_[g];
     if (src.w) x *= src.w[k];
-    xf[k] = x * sc * mk;
+    xv[r] = x * sc * mk;
+    xf[k] = xv[r];
+  }
+  // R_z rows of more than 3 taps (small q, where a z bin spans many t bins)
+  // have interior weights exactly 1, so they are computed as w x[k0] +
+  // (P[k1] - P[k0 + 1]) + w' x[k1] from exclusive prefix sums P of the first
+  // RS G inputs (those rows end below m/4 + 8, checked when the tables are
+  // built); rows of at most 3 taps are summed directly.  No row loops, so no
+  // lane waits for the longest row of its wave.
+  constexpr int RS = resample_scan_rows(M, G);
+  float carry = 0.f;
+#pragma unroll
+  for (int r = 0; r < RS; ++r) {
+    float inc = xv[r];
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const float y = __shfl_up(inc, d, G);
+      if (s >= d) inc += y;
+    }
+    pf[G * r + s] = carry + (inc - xv[r]);
+    carry += __shfl(inc, G - 1, G);
   }
   __syncthreads();
   // R_z rows 2p, 2p+1 packed as one complex value, lower half of the transform
@@ -146,8 +168,20 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int4 ri = srow[2 * p + h];
+      const int k0 = ri.x, cnt = ri.y, off = ri.z;
       float acc = 0.f;
-      for (int t = 0; t < ri.y; ++t) acc += sval[ri.z + t] * xf[ri.x + t];
+      if (cnt > 0) {
+        const int t1 = cnt - 1;
+        const float wa = sval[off], wb = sval[off + t1];
+        const float xa = xf[k0], xb = xf[k0 + t1];
+        if (cnt > 3) {
+          acc = wa * xa + (pf[k0 + t1] - pf[k0 + 1]) + wb * xb;
+        } else {
+          acc = wa * xa;
+          if (cnt == 3) acc += sval[off + 1] * xf[k0 + 1];
+          if (cnt >= 2) acc += wb * xb;
+        }
+      }
       v[h] = acc;
     }
     x[r] = make_float2(v[0], v[1]);
@@ -279,9 +313,11 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = G * r + s;
-    const int4 ci = scol[k];
+    const int4 ci = scol[k];               // at most 3 taps (checked on the host)
     float tk = 0.f;
-    for (int t = 0; t < ci.y; ++t) tk += sval[ci.z + t] * g[ci.x + t];
+    if (ci.y > 0) tk += sval[ci.z] * g[ci.x];
+    if (ci.y > 1) tk += sval[ci.z + 1] * g[ci.x + 1];
+    if (ci.y > 2) tk += sval[ci.z + 2] * g[ci.x + 2];
     if (ep.w) tk *= ep.w[k];
     const size_t gi = (size_t)col * M + k;
     if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
