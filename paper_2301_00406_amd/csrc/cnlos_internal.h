@@ -1,5 +1,6 @@
 // Internal interfaces between the host driver and the kernel translation units.
 #pragma once
+#include <cstddef>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -100,6 +101,16 @@ enum Gate : int { G_NONE = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_AFTER_CHECK = 4, G_F
 // trial only sets `reject`, which makes the rest of its iteration slot a no-op,
 // and the next slot retries the iteration with the larger L.
 struct DevCtl {
+  // the fields every kernel's phase gate reads, in one 32-byte block at the
+  // start (one scalar load at kernel start)
+  int32_t halt;
+  int32_t iter;        // accepted iterations
+  int32_t stage;       // 1 = Algorithm 1, 2 = Algorithm 2
+  int32_t target;      // iteration kernels return once iter >= target
+  int32_t reject;      // the current slot's trial was rejected
+  int32_t stage1_end;  // dual model: iterations of the warm start; object: a large value
+  int32_t reason;
+  int32_t trials;      // rejections in the current iteration
   int32_t slot[R_COUNT];   // buffer index per role
   int32_t slot_pad;
   double L;            // current step constant
@@ -111,35 +122,27 @@ struct DevCtl {
   double pow_est;
   double last_energy, last_primal, last_dual;
   double reserved_d;
-  int32_t halt;
-  int32_t reason;
-  int32_t iter;        // accepted iterations
-  int32_t trials;      // rejections in the current iteration
   int32_t bt_rejects;  // rejections since create/reset
-  int32_t stage;       // 1 = Algorithm 1, 2 = Algorithm 2
   int32_t log_count;   // rows written to the log ring
   int32_t bt_max_trials;
   double bt_factor;
   double eps_stop;
   double mu_dual;      // mu (object) or mu1 (dual) for the dual residual
   double lambda;
-  int32_t target;      // iteration kernels return once iter >= target
-  int32_t reject;      // the current slot's trial was rejected
-  int32_t stage1_end;  // dual model: iterations of the warm start; object: a large value
-  int32_t reserved_i;
 };
+static_assert(offsetof(DevCtl, slot) == 32, "the gate fields fill the first 32 bytes");
 
 // true when a kernel with phase gate `gate` has nothing to do for this scene
+// (every field is loaded before the first decision, so the test costs one
+// memory round trip at kernel start instead of a chain of dependent ones)
 __device__ __forceinline__ bool gated_off(const DevCtl* c, int gate) {
   if (c == nullptr) return false;
-  if (c->halt) return true;
-  if (gate == G_NONE) return false;
-  if (c->iter >= c->target) return true;
-  const int stage = c->stage;
-  if ((gate & G_STAGE1) && (stage != 1 || c->iter >= c->stage1_end)) return true;
-  if ((gate & G_STAGE2) && stage != 2) return true;
-  if ((gate & G_AFTER_CHECK) && c->reject) return true;
-  return false;
+  const int halt = c->halt, iter = c->iter, target = c->target, stage = c->stage;
+  const int s1end = c->stage1_end, rej = c->reject;
+  const bool s1 = (gate & G_STAGE1) != 0, s2 = (gate & G_STAGE2) != 0;
+  const bool ac = (gate & G_AFTER_CHECK) != 0;
+  return (halt != 0) | ((gate != G_NONE) & (iter >= target)) |
+         (s1 & ((stage != 1) | (iter >= s1end))) | (s2 & (stage != 2)) | (ac & (rej != 0));
 }
 
 // A volume operand: the fixed pointer p[0] (role < 0), or the buffer p[slot]
