@@ -132,6 +132,36 @@ struct DevCtl {
 };
 static_assert(offsetof(DevCtl, slot) == 32, "the gate fields fill the first 32 bytes");
 
+// The controller's head (gate fields and buffer slots), read once at kernel
+// start: one memory round trip for the phase gate and every role operand.
+struct CtlHead {
+  int32_t halt, iter, stage, target, reject, stage1_end, reason, trials;
+  int32_t slot[R_COUNT];
+  bool valid;                // false: no controller (plain operator launches)
+};
+__device__ __forceinline__ CtlHead ctl_head(const DevCtl* c) {
+  CtlHead h{};
+  h.valid = c != nullptr;
+  if (c) {
+    h.halt = c->halt;
+    h.iter = c->iter;
+    h.stage = c->stage;
+    h.target = c->target;
+    h.reject = c->reject;
+    h.stage1_end = c->stage1_end;
+#pragma unroll
+    for (int r = 0; r < R_COUNT; ++r) h.slot[r] = c->slot[r];
+  }
+  return h;
+}
+__device__ __forceinline__ bool gated_off(const CtlHead& h, int gate) {
+  const bool s1 = (gate & G_STAGE1) != 0, s2 = (gate & G_STAGE2) != 0;
+  const bool ac = (gate & G_AFTER_CHECK) != 0;
+  return h.valid & ((h.halt != 0) | ((gate != G_NONE) & (h.iter >= h.target)) |
+                    (s1 & ((h.stage != 1) | (h.iter >= h.stage1_end))) | (s2 & (h.stage != 2)) |
+                    (ac & (h.reject != 0)));
+}
+
 // true when a kernel with phase gate `gate` has nothing to do for this scene
 // (every field is loaded before the first decision, so the test costs one
 // memory round trip at kernel start instead of a chain of dependent ones)
@@ -166,6 +196,14 @@ __device__ __forceinline__ T* zsh(T* p, size_t off) {
 __device__ __forceinline__ float* vol_resolve(const Vol& v, const DevCtl* c, size_t zo) {
   if (v.role < 0) return zsh(v.p[0], zo);
   const int k = c->slot[v.role];
+  float* q = k == 0 ? v.p[0] : (k == 1 ? v.p[1] : v.p[2]);
+  return zsh(q, zo);
+}
+__device__ __forceinline__ float* vol_resolve(const Vol& v, const CtlHead& h, size_t zo) {
+  // select chain over the roles (a runtime index would put the head in scratch)
+  int k = 0;
+#pragma unroll
+  for (int r = 0; r < R_COUNT; ++r) k = v.role == r ? h.slot[r] : k;
   float* q = k == 0 ? v.p[0] : (k == 1 ? v.p[1] : v.p[2]);
   return zsh(q, zo);
 }

@@ -27,11 +27,14 @@ int stencil_blocks(int logn, int logm) {
 // Common head of the iteration kernels: shift the controller to this launch's
 // scene, apply the phase gate, and (first kernel of an iteration slot) clear
 // the previous slot's rejection.
-__device__ __forceinline__ bool iter_head(DevCtl*& ctl, size_t zo, int gate) {
-  ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return false;
+__device__ __forceinline__ bool iter_gate(DevCtl* ctl, const CtlHead& hd, int gate) {
+  if (gated_off(hd, gate)) return false;
   if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
   return true;
+}
+__device__ __forceinline__ bool iter_head(DevCtl*& ctl, size_t zo, int gate) {
+  ctl = zsh(ctl, zo);
+  return iter_gate(ctl, ctl_head(ctl), gate);
 }
 __device__ __forceinline__ float* vol_at(const Vol& v, const DevCtl* c, size_t zo) {
   return vol_resolve(v, c, zo);
@@ -197,11 +200,13 @@ __global__ void __launch_bounds__(kStencilThreads)
 k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs,
        int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  const float* xn = vol_at(pu.xn, ctl, zo);
-  const float* xo = vol_at(pu.xo, ctl, zo);
-  const float* xb = vol_at(pu.xb, ctl, zo);
-  float* xbn = vol_at(pu.xbn, ctl, zo);
+  ctl = zsh(ctl, zo);
+  const CtlHead hd = ctl_head(ctl);
+  const float* xn = vol_resolve(pu.xn, hd, zo);
+  const float* xo = vol_resolve(pu.xo, hd, zo);
+  const float* xb = vol_resolve(pu.xb, hd, zo);
+  float* xbn = vol_resolve(pu.xbn, hd, zo);
+  if (!iter_gate(ctl, hd, gate)) return;
   pu.lam = zsh(pu.lam, zo);
   pu.phi = zsh(pu.phi, zo);
   partials = zsh(partials, zo);
@@ -227,16 +232,18 @@ k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float
             Vol au_v, const float* __restrict__ tau0, const uint8_t* __restrict__ mask,
             double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
-  const float* uxn = vol_at(pu.xn, ctl, zo);
-  const float* uxo = vol_at(pu.xo, ctl, zo);
-  const float* uxb = vol_at(pu.xb, ctl, zo);
-  float* uxbn = vol_at(pu.xbn, ctl, zo);
-  const float* txn = vol_at(pt.xn, ctl, zo);
-  const float* txo = vol_at(pt.xo, ctl, zo);
-  const float* txb = vol_at(pt.xb, ctl, zo);
-  float* txbn = vol_at(pt.xbn, ctl, zo);
-  const float* au = vol_at(au_v, ctl, zo);
+  ctl = zsh(ctl, zo);
+  const CtlHead hd = ctl_head(ctl);
+  const float* uxn = vol_resolve(pu.xn, hd, zo);
+  const float* uxo = vol_resolve(pu.xo, hd, zo);
+  const float* uxb = vol_resolve(pu.xb, hd, zo);
+  float* uxbn = vol_resolve(pu.xbn, hd, zo);
+  const float* txn = vol_resolve(pt.xn, hd, zo);
+  const float* txo = vol_resolve(pt.xo, hd, zo);
+  const float* txb = vol_resolve(pt.xb, hd, zo);
+  float* txbn = vol_resolve(pt.xbn, hd, zo);
+  const float* au = vol_resolve(au_v, hd, zo);
+  if (!iter_gate(ctl, hd, gate)) return;
   pu.lam = zsh(pu.lam, zo);
   pu.phi = zsh(pu.phi, zo);
   pt.lam = zsh(pt.lam, zo);

@@ -22,11 +22,11 @@
 namespace cnlos {
 
 // the volume behind v for this launch's scene (zo: the scene's byte offset)
-__device__ __forceinline__ const float* vol_in(const Vol& v, const DevCtl* c, size_t zo) {
-  return vol_resolve(v, c, zo);
+__device__ __forceinline__ const float* vol_in(const Vol& v, const CtlHead& h, size_t zo) {
+  return vol_resolve(v, h, zo);
 }
-__device__ __forceinline__ float* vol_out(const Vol& v, const DevCtl* c, size_t zo) {
-  return vol_resolve(v, c, zo);
+__device__ __forceinline__ float* vol_out(const Vol& v, const CtlHead& h, size_t zo) {
+  return vol_resolve(v, h, zo);
 }
 __device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
   S.rows = zsh(S.rows, zo);
@@ -93,14 +93,15 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   __shared__ float sval_l[NNZ];
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return;
+  const CtlHead hd = ctl_head(ctl);
+  const float* sa = vol_in(src.a, hd, zo);
+  const float* sb = vol_in(src.b, hd, zo);
+  const float* sc_ = vol_in(src.c, hd, zo);
+  if (gated_off(hd, gate)) return;
   zsh_tables(S, zo);
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   spec = zsh(spec, zo);
-  const float* sa = vol_in(src.a, ctl, zo);
-  const float* sb = vol_in(src.b, ctl, zo);
-  const float* sc_ = vol_in(src.c, ctl, zo);
   src.w = zsh(src.w, zo);
   src.mask = zsh(src.mask, zo);
   src.scale_div = zsh(src.scale_div, zo);
@@ -243,15 +244,16 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   __shared__ float sval_l[NNZ];
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return;
+  const CtlHead hd = ctl_head(ctl);
+  float* eout = vol_out(ep.out, hd, zo);
+  const float* eau = (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au, hd, zo) : nullptr;
+  const float* eaup =
+      (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au_prev, hd, zo) : nullptr;
+  if (gated_off(hd, gate)) return;
   zsh_tables(S, zo);
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   spec = zsh(spec, zo);
-  float* eout = vol_out(ep.out, ctl, zo);
-  const float* eau = (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au, ctl, zo) : nullptr;
-  const float* eaup =
-      (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) ? vol_in(ep.au_prev, ctl, zo) : nullptr;
   ep.w = zsh(ep.w, zo);
   ep.mask = zsh(ep.mask, zo);
   ep.tau0 = zsh(ep.tau0, zo);
@@ -920,7 +922,10 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
   __shared__ float2 twc[H];
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return;
+  const CtlHead hd = ctl_head(ctl);
+  const float* xb = SRC != RHS_LOAD ? vol_resolve(rs.xb, hd, zo) : nullptr;
+  const float* au = SRC == RHS_TAU ? vol_resolve(rs.au, hd, zo) : nullptr;
+  if (gated_off(hd, gate)) return;
   if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
@@ -936,8 +941,6 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
 #pragma unroll
     for (int r = 0; r < E; ++r) x[r] = src2[G * r + s];
   } else {
-    const float* xb = vol_resolve(rs.xb, ctl, zo);
-    const float* au = SRC == RHS_TAU ? vol_resolve(rs.au, ctl, zo) : nullptr;
     rs.gf = zsh(rs.gf, zo);
     rs.lam = zsh(rs.lam, zo);
     rs.phi = zsh(rs.phi, zo);
@@ -997,12 +1000,13 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   __shared__ float2 twc[H];
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
-  if (gated_off(ctl, gate)) return;
+  const CtlHead hd = ctl_head(ctl);
+  float* eout = vol_out(ep.out, hd, zo);
+  const float* eref = vol_in(ep.ref, hd, zo);
+  if (gated_off(hd, gate)) return;
   spec = zsh(spec, zo);
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
-  float* eout = vol_out(ep.out, ctl, zo);
-  const float* eref = vol_in(ep.ref, ctl, zo);
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
