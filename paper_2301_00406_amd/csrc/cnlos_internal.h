@@ -149,6 +149,8 @@ __device__ __forceinline__ CtlHead ctl_head(const DevCtl* c) {
     h.target = c->target;
     h.reject = c->reject;
     h.stage1_end = c->stage1_end;
+    h.reason = c->reason;
+    h.trials = c->trials;
 #pragma unroll
     for (int r = 0; r < R_COUNT; ++r) h.slot[r] = c->slot[r];
   }

@@ -292,8 +292,14 @@ __global__ void __launch_bounds__(kCtlThreads)
 k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on,
         size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
+  ctl = zsh(ctl, zo);
   partials = zsh(partials, zo);
+  // every controller field the decision needs is read up front, with the
+  // gate fields (not after the reduction's barriers)
+  const CtlHead hd = ctl_head(ctl);
+  const double L = ctl->L, bt_factor = ctl->bt_factor;
+  const int bt_rejects = ctl->bt_rejects, bt_max = ctl->bt_max_trials;
+  if (!iter_gate(ctl, hd, gate)) return;
   const int slots[2] = {SL_CHECK, SL_STEP}, nbs[2] = {nb_conv, nb_step};
   double sums[2];
   block_sum_partials_k<2>(partials, slots, nbs, kMaxBlocks, sums);
@@ -302,16 +308,17 @@ k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_st
     if (!isfinite(s_chk) || !isfinite(s_step)) {
       ctl->halt = 1;
       ctl->reason = HR_NONFINITE;
-    } else if (bt_on && !(s_chk <= ctl->L * s_step)) {
-      ctl->trials += 1;
-      ctl->bt_rejects += 1;
-      if (ctl->trials > ctl->bt_max_trials) {
+    } else if (bt_on && !(s_chk <= L * s_step)) {
+      const int trials = hd.trials + 1;
+      ctl->trials = trials;
+      ctl->bt_rejects = bt_rejects + 1;
+      if (trials > bt_max) {
         ctl->halt = 1;
         ctl->reason = HR_BACKTRACK;
       } else {
         // the rest of this slot is skipped; the next slot redoes the iteration
         ctl->reject = 1;
-        ctl->L *= ctl->bt_factor;
+        ctl->L = L * bt_factor;
       }
     }
   }
@@ -322,9 +329,15 @@ __global__ void __launch_bounds__(kCtlThreads)
 k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
            int nb_conv, int nb_sten, int dual, double lambda, double mu_res, size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
-  if (!iter_head(ctl, zo, gate)) return;
+  ctl = zsh(ctl, zo);
   logbuf = zsh(logbuf, zo);
   partials = zsh(partials, zo);
+  // every controller field thread 0 needs is read up front, with the gate
+  // fields (not after the reduction's barriers)
+  const CtlHead hd = ctl_head(ctl);
+  const double Ep = ctl->energy_prev, L = ctl->L, t = ctl->t, eps_stop = ctl->eps_stop;
+  const int log_count = ctl->log_count;
+  if (!iter_gate(ctl, hd, gate)) return;
   double E, prim, dres;
   if (!dual) {
     const int slots[4] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_DATA};
@@ -349,45 +362,38 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
       ctl->reason = HR_NONFINITE;
       return;
     }
-    const double Ep = ctl->energy_prev;
     const double rel = (isfinite(Ep) && E != 0.0) ? fabs(Ep - E) / fabs(E) : INFINITY;
     const double primal = sqrt(prim), dualr = mu_res * sqrt(dres);
-    double* row = logbuf + (size_t)(ctl->log_count % kLogRows) * kLogCols;
+    double* row = logbuf + (size_t)(log_count % kLogRows) * kLogCols;
     row[0] = E;
     row[1] = primal;
     row[2] = dualr;
-    row[3] = ctl->L;
-    row[4] = (double)ctl->trials;
+    row[3] = L;
+    row[4] = (double)hd.trials;
     row[5] = rel;
-    ctl->log_count += 1;
-    const double t = ctl->t;
+    ctl->log_count = log_count + 1;
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
     ctl->beta = (t - 1.0) / tn;
     ctl->t = tn;
-    ctl->iter += 1;
+    ctl->iter = hd.iter + 1;
     ctl->trials = 0;
-    // the trial becomes the current iterate
-    int r = ctl->slot[R_U_CUR];
-    ctl->slot[R_U_CUR] = ctl->slot[R_U_TR];
-    ctl->slot[R_U_TR] = r;
-    r = ctl->slot[R_AU_PREV];
-    ctl->slot[R_AU_PREV] = ctl->slot[R_AU_CUR];
-    ctl->slot[R_AU_CUR] = ctl->slot[R_AU_TR];
-    ctl->slot[R_AU_TR] = r;
-    r = ctl->slot[R_T_CUR];
-    ctl->slot[R_T_CUR] = ctl->slot[R_T_TR];
-    ctl->slot[R_T_TR] = r;
-    r = ctl->slot[R_UB_CUR];
-    ctl->slot[R_UB_CUR] = ctl->slot[R_UB_NEW];
-    ctl->slot[R_UB_NEW] = r;
-    r = ctl->slot[R_TB_CUR];
-    ctl->slot[R_TB_CUR] = ctl->slot[R_TB_NEW];
-    ctl->slot[R_TB_NEW] = r;
+    // the trial becomes the current iterate (buffer roles rotate)
+    ctl->slot[R_U_CUR] = hd.slot[R_U_TR];
+    ctl->slot[R_U_TR] = hd.slot[R_U_CUR];
+    ctl->slot[R_AU_PREV] = hd.slot[R_AU_CUR];
+    ctl->slot[R_AU_CUR] = hd.slot[R_AU_TR];
+    ctl->slot[R_AU_TR] = hd.slot[R_AU_PREV];
+    ctl->slot[R_T_CUR] = hd.slot[R_T_TR];
+    ctl->slot[R_T_TR] = hd.slot[R_T_CUR];
+    ctl->slot[R_UB_CUR] = hd.slot[R_UB_NEW];
+    ctl->slot[R_UB_NEW] = hd.slot[R_UB_CUR];
+    ctl->slot[R_TB_CUR] = hd.slot[R_TB_NEW];
+    ctl->slot[R_TB_NEW] = hd.slot[R_TB_CUR];
     ctl->energy_prev = E;
     ctl->last_energy = E;
     ctl->last_primal = primal;
     ctl->last_dual = dualr;
-    if (ctl->eps_stop > 0.0 && rel <= ctl->eps_stop) {
+    if (eps_stop > 0.0 && rel <= eps_stop) {
       ctl->halt = 1;
       ctl->reason = HR_STOP;
     }
