@@ -278,8 +278,8 @@ def algorithmic_bytes(kind, n, m, dual):
     f = 4 * V
     if kind == "plane_conv":
         return 2 * spec_c + hq
-    if kind == "t_fwd_conv":       # adjoint launch reads 3 volumes, forward launch 1
-        return spec_c + (3 * f + f) / 2
+    if kind == "t_fwd_conv":       # the adjoint's first pass reads 3 volumes (the forward
+        return spec_c + 3 * f      # operator's runs inside the u solve's last pass)
     if kind == "t_inv_conv":       # forward launch also reads A u^k, A u^{k-1}
         return spec_c + f + (2 * f) / 2
     if kind == "t_fwd_solve":      # right-hand side formed in the t pass from its inputs:
@@ -288,8 +288,9 @@ def algorithmic_bytes(kind, n, m, dual):
         return spec_s + ((u_in + tau_in) / 2 if dual else u_in)
     if kind == "plane_solve":
         return 2 * spec_s
-    if kind == "t_inv_solve":      # the u solve also reads ubar
-        return spec_s + f + (f / 2 if dual else f)
+    if kind == "t_inv_solve":      # u solve: reads ubar, writes u+ and A u+'s first planes;
+        u = spec_s + 2 * f + spec_c  # tau solve (dual): writes tau+
+        return (u + spec_s + f) / 2 if dual else u
     # the splitting variables v, w, f are recomputed where they are used
     if kind == "post_u":           # object: 7 volumes in, 5 out; dual adds the tau side (10 in, 6 out)
         return 28 * f + n * n if dual else 12 * f

@@ -187,6 +187,7 @@ struct cnlos_problem {
   float* phi_tau = nullptr;
   Tables tb;
   int nb_conv = 0, nb_solve = 0, nb_sten = 0;
+  int nb_step = 0;          // blocks writing the u solve's step partials (fused pass)
   Prof prof;
 };
 
@@ -602,8 +603,9 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     se.out = role(R_U_TR);
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
+    // the solve's last pass also starts A u+ (forward t pass of the convolution)
     HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu), p->spec, &ctl->L, 0.0, mu, se, ctl,
-                        gated(G | G_FIRST), p->st, &p->prof));
+                        gated(G | G_FIRST), p->st, &p->prof, true));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
@@ -616,8 +618,9 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ef.au_prev = role(R_AU_PREV);
     ef.tau0 = p->tau0;
     ef.partials = p->partials;
-    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_OBJ, ef, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
+    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_OBJ, ef, ctl, gated(G), p->st,
+                       &p->prof, true));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
                                    gated(G), p->st));
     const PostArgs pa{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu, phi_args(p, 1, false)};
@@ -656,7 +659,7 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu1), p->spec, &ctl->L, 0.0, mu1, se, ctl,
-                        gated(G | G_FIRST), p->st, &p->prof));
+                        gated(G | G_FIRST), p->st, &p->prof, true));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
@@ -667,8 +670,9 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ef.au = role(R_AU_CUR);
     ef.au_prev = role(R_AU_PREV);
     ef.partials = p->partials;
-    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st, &p->prof));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_solve, c.backtracking ? 1 : 0,
+    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st,
+                       &p->prof, true));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
                                    gated(G), p->st));
     const int GA = G | G_AFTER_CHECK;
     RhsSrc rt;
@@ -1027,6 +1031,7 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
   p->carve_bytes = carve(p, *cfg, p->ws);
   p->nb_conv = conv_blocks(p->logn, p->logm);
   p->nb_solve = solve_blocks(p->logn, p->logm);
+  p->nb_step = fused_solve_blocks(p->logn, p->logm);
   p->nb_sten = stencil_blocks(p->logn, p->logm);
   *out = p;   // from here on errors leave a handle the caller must destroy
 
@@ -1590,6 +1595,7 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
   p->carve_bytes = carve(p, cfg, ws);
   p->nb_conv = conv_blocks(p->logn, p->logm);
   p->nb_solve = solve_blocks(p->logn, p->logm);
+  p->nb_step = fused_solve_blocks(p->logn, p->logm);
   p->nb_sten = stencil_blocks(p->logn, p->logm);
   p->tb.tw_t = p->tw_t;
   p->tb.tw_xy = p->tw_xy;

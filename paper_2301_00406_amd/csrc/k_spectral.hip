@@ -74,72 +74,21 @@ __device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
 // pairs (x[2p], x[2p+1]); its upper half is zero, so the first DIF stage is a
 // twist.  With PK the two real bins kt = 0 and kt = m share plane 0 as
 // X_0 + i X_m, so the transform fills exactly m planes.
+// Forward t pass of the convolution from a column whose real input is in
+// LDS (xf, with xv[r] = xf[G r + s] in registers): R_z, packed real-to-complex
+// transform of length 2m, untangle, staged coalesced plane writes.
 template <int LOGM, bool PK>
-__global__ void __launch_bounds__(TGeo<LOGM>::NT)
-k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
-            const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl,
-            size_t zs, int gate) {
+__device__ __forceinline__ void tfwd_conv_from_lds(float2* lds, const float2* tws,
+                                                   const float2* twc, const int4* srow,
+                                                   const float* sval, float (&xv)[TGeo<LOGM>::E],
+                                                   int tid, int col0, float2* __restrict__ spec,
+                                                   int nn) {
   using T = TGeo<LOGM>;
   constexpr int M = 1 << LOGM, G = T::G, E = T::E, J = T::J, NT = T::NT;
-  constexpr int ZS = M + M / 8 + 4;               // per-column LDS stride (float2)
-  constexpr int LDS2 = (J * ZS > stg_size<J>(M + 1)) ? J * ZS : stg_size<J>(M + 1);
-  // the resampling table (<= 3m + 64 values) is staged in LDS up to m = 1024
-  constexpr bool STAGE = M <= 1024;
-  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
-  __shared__ float2 lds[LDS2];
-  __shared__ float2 tws[M];
-  __shared__ float2 twc[M];
-  __shared__ int4 srow_l[STAGE ? M : 1];
-  __shared__ float sval_l[NNZ];
-  const size_t zo = (size_t)blockIdx.z * zs;
-  ctl = zsh(ctl, zo);
-  const CtlHead hd = ctl_head(ctl);
-  const float* sa = vol_in(src.a, hd, zo);
-  const float* sb = vol_in(src.b, hd, zo);
-  const float* sc_ = vol_in(src.c, hd, zo);
-  if (gated_off(hd, gate)) return;
-  zsh_tables(S, zo);
-  tw = zsh(tw, zo);
-  twcg = zsh(twcg, zo);
-  spec = zsh(spec, zo);
-  src.w = zsh(src.w, zo);
-  src.mask = zsh(src.mask, zo);
-  src.scale_div = zsh(src.scale_div, zo);
-  const int tid = threadIdx.x, b = tid / G, s = tid % G;
-  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) {
-    tws[i] = tw[i];
-    twc[i] = twcg[i];
-  }
-  if constexpr (STAGE) {
-    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
-    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
-  }
-  const int4* srow = STAGE ? srow_l : S.rows;
-  const float* sval = STAGE ? sval_l : S.rvals;
-
-  float ca = 1.f, cb = 0.f;
-  if (src.lincache) {
-    const double beta = ctl->beta;
-    ca = (float)(1.0 + beta);
-    cb = (float)(-beta);
-  }
-  const float sc = src.scale_div ? (float)(1.0 / *src.scale_div) : 1.f;
-  const float mk = src.mask ? (float)src.mask[col] : 1.f;
-  float* xf = reinterpret_cast<float*>(lds + b * ZS);     // this column's real input
-  float* pf = xf + M;                                      // its prefix sums (below)
-  float xv[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int k = G * r + s;
-    const size_t g = (size_t)col * M + k;
-    float x = ca * sa[g];
-    if (sb) x += cb * sb[g];
-    if (sc_) x -= sc_[g];
-    if (src.w) x *= src.w[k];
-    xv[r] = x * sc * mk;
-    xf[k] = xv[r];
-  }
+  constexpr int ZS = M + M / 8 + 4;
+  const int b = tid / G, s = tid % G;
+  float* xf = reinterpret_cast<float*>(lds + b * ZS);
+  float* pf = xf + M;
   // R_z rows of more than 3 taps (small q, where a z bin spans many t bins)
   // have interior weights exactly 1, so they are computed as w x[k0] +
   // (P[k1] - P[k0 + 1]) + w' x[k1] from exclusive prefix sums P of the first
@@ -223,7 +172,74 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   for (int it = tid; it < NP * J; it += NT) {
     const int bb = it % J, k = it / J;
     spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
+  }}
+
+template <int LOGM, bool PK>
+__global__ void __launch_bounds__(TGeo<LOGM>::NT)
+k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
+            const float2* __restrict__ twcg, float2* __restrict__ spec, int nn, const DevCtl* ctl,
+            size_t zs, int gate) {
+  using T = TGeo<LOGM>;
+  constexpr int M = 1 << LOGM, G = T::G, E = T::E, J = T::J, NT = T::NT;
+  constexpr int ZS = M + M / 8 + 4;               // per-column LDS stride (float2)
+  constexpr int LDS2 = (J * ZS > stg_size<J>(M + 1)) ? J * ZS : stg_size<J>(M + 1);
+  // the resampling table (<= 3m + 64 values) is staged in LDS up to m = 1024
+  constexpr bool STAGE = M <= 1024;
+  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
+  __shared__ float2 lds[LDS2];
+  __shared__ float2 tws[M];
+  __shared__ float2 twc[M];
+  __shared__ int4 srow_l[STAGE ? M : 1];
+  __shared__ float sval_l[NNZ];
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  const CtlHead hd = ctl_head(ctl);
+  const float* sa = vol_in(src.a, hd, zo);
+  const float* sb = vol_in(src.b, hd, zo);
+  const float* sc_ = vol_in(src.c, hd, zo);
+  if (gated_off(hd, gate)) return;
+  zsh_tables(S, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  spec = zsh(spec, zo);
+  src.w = zsh(src.w, zo);
+  src.mask = zsh(src.mask, zo);
+  src.scale_div = zsh(src.scale_div, zo);
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) {
+    tws[i] = tw[i];
+    twc[i] = twcg[i];
   }
+  if constexpr (STAGE) {
+    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
+    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
+  }
+  const int4* srow = STAGE ? srow_l : S.rows;
+  const float* sval = STAGE ? sval_l : S.rvals;
+
+  float ca = 1.f, cb = 0.f;
+  if (src.lincache) {
+    const double beta = ctl->beta;
+    ca = (float)(1.0 + beta);
+    cb = (float)(-beta);
+  }
+  const float sc = src.scale_div ? (float)(1.0 / *src.scale_div) : 1.f;
+  const float mk = src.mask ? (float)src.mask[col] : 1.f;
+  float* xf = reinterpret_cast<float*>(lds + b * ZS);     // this column's real input
+  float xv[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = G * r + s;
+    const size_t g = (size_t)col * M + k;
+    float x = ca * sa[g];
+    if (sb) x += cb * sb[g];
+    if (sc_) x -= sc_[g];
+    if (src.w) x *= src.w[k];
+    xv[r] = x * sc * mk;
+    xf[k] = xv[r];
+  }
+  tfwd_conv_from_lds<LOGM, PK>(lds, tws, twc, srow, sval, xv, tid, col0, spec, nn);
 }
 
 // t pass, inverse, convolution: planes -> C2R (length 2m) -> crop -> S^T -> epilogue
@@ -1055,6 +1071,120 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   }
 }
 
+// Inverse t pass of the u solve fused with the forward t pass of the
+// convolution that follows it (A u+, Algorithms 1 and 2): the solve's real
+// output column stays in LDS as the convolution's input, so u+ is not read
+// back and one launch and one table staging are saved.  Both passes work on
+// the same scan columns, so the spectrum buffer is reused in place (a block
+// reads its columns' solve planes before it writes their convolution
+// planes).  The block has the convolution pass's geometry (J columns, NT
+// threads); the solve phase runs on J x G_s of them (whole waves).
+template <int LOGM, bool PK>
+__global__ void __launch_bounds__(TGeo<LOGM>::NT)
+k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
+                 const float2* __restrict__ tw, const float2* __restrict__ twcg, SolveEpi ep,
+                 float scale, const DevCtl* ctl, size_t zs, int gate) {
+  using T = TGeo<LOGM>;
+  using TS = TGeo<LOGM - 1>;
+  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
+  constexpr int G = T::G, E = T::E, J = T::J, NT = T::NT;
+  constexpr int GS = TS::G, ES = TS::E;
+  static_assert(J * GS <= NT && (J * GS) % 64 == 0, "solve phase on whole waves");
+  constexpr int ZS = M + M / 8 + 4;
+  constexpr int LDS2 = (J * ZS > stg_size<J>(M + 1)) ? J * ZS : stg_size<J>(M + 1);
+  static_assert(stg_size<J>(H + 1) <= LDS2, "solve staging fits");
+  constexpr bool STAGE = M <= 1024;
+  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
+  __shared__ float2 lds[LDS2];
+  __shared__ float2 tws[M];
+  __shared__ float2 twc[M];
+  __shared__ int4 srow_l[STAGE ? M : 1];
+  __shared__ float sval_l[NNZ];
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  const CtlHead hd = ctl_head(ctl);
+  float* eout = vol_out(ep.out, hd, zo);
+  const float* eref = vol_in(ep.ref, hd, zo);
+  if (gated_off(hd, gate)) return;
+  zsh_tables(S, zo);
+  spec = zsh(spec, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  ep.partials = zsh(ep.partials, zo);
+  const int tid = threadIdx.x;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J;
+  for (int i = tid; i < M; i += NT) {
+    tws[i] = tw[i];
+    twc[i] = twcg[i];
+  }
+  if constexpr (STAGE) {
+    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
+    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
+  }
+  const int4* srow = STAGE ? srow_l : S.rows;
+  const float* sval = STAGE ? sval_l : S.rvals;
+  for (int it = tid; it < H * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
+  }
+  __syncthreads();
+  // solve phase: packed real inverse of length m (as k_tinv_solve)
+  const bool sact = tid < J * GS;
+  const int bs = tid / GS, ss = tid % GS;
+  float2 y[ES];
+  if (sact) {
+#pragma unroll
+    for (int r = 0; r < ES; ++r) {
+      const int k = brev(GS * r + ss, LOGH);
+      float2 Xk = lds[stg<J>(k, bs)];
+      float2 Xm = lds[stg<J>((H - k) & (H - 1), bs)];
+      if (k == 0) {
+        Xm = make_float2(Xk.y, 0.f);
+        Xk.y = 0.f;
+      }
+      const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
+      const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
+      const float2 wo = cmulc(o, tws[2 * k]);
+      y[r] = make_float2(e.x - wo.y, e.y + wo.x);
+    }
+  }
+  __syncthreads();                                 // staging consumed: the columns' LDS is reused
+  double acc = 0.0;
+  if (sact) {
+    dit_xlane<GS, ES>(y, ss, twc);
+    dit_inlane<GS, ES, ES / 2>(y, ss, twc);
+    const int col = col0 + bs;
+    float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
+    const float2* ref2 = eref ? reinterpret_cast<const float2*>(eref) + (size_t)col * H : nullptr;
+    float2* xf2 = lds + bs * ZS;                   // the column's real samples, as pairs
+#pragma unroll
+    for (int r = 0; r < ES; ++r) {
+      const int p = GS * r + ss;
+      const float2 v = cscale(y[r], scale);
+      out2[p] = v;
+      xf2[p] = v;
+      if (ref2) {
+        const float2 rv = ref2[p];
+        const float d0 = v.x - rv.x, d1 = v.y - rv.y;
+        acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
+      }
+    }
+  }
+  if (eref) {
+    double v[1] = {acc};
+    const int slots[1] = {SL_STEP};
+    block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);
+  }
+  __syncthreads();                                 // every column's u+ in LDS
+  // convolution phase: R_z, packed transform of length 2m, planes
+  const int b = tid / G, s = tid % G;
+  const float* xf = reinterpret_cast<const float*>(lds + b * ZS);
+  float xv[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) xv[r] = xf[G * r + s];
+  tfwd_conv_from_lds<LOGM, PK>(lds, tws, twc, srow, sval, xv, tid, col0, spec, nn);
+}
+
 // ---------------------------------------------------------------------------
 // H^ setup: the kernel h of eq. (3) is even in dx and dy, so its padded
 // spectrum is a real cosine sum in (kx, ky) and a complex exponential in kt:
@@ -1111,6 +1241,7 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
 // blocks of the t passes (their partial sums are indexed by block)
 int conv_blocks(int logn, int logm) { return (1 << (2 * logn)) / t_columns(logm); }
 int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / t_columns(logm - 1); }
+int fused_solve_blocks(int logn, int logm) { return conv_blocks(logn, logm); }
 
 #define CNLOS_TIMED(prof, kind, st, launch)                 \
   do {                                                     \
@@ -1123,7 +1254,7 @@ int solve_blocks(int logn, int logm) { return (1 << (2 * logn)) / t_columns(logm
 template <int LOGN, int LOGM>
 static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, bool adjoint,
                             int epi, const ConvEpi& ep, const DevCtl* ctl, const Batch& bt,
-                            hipStream_t st, Prof* prof) {
+                            hipStream_t st, Prof* prof, bool tfwd_done) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   // the register plane kernel takes the real planes kt = 0, m packed in one
   constexpr bool PK = LOGN <= 6;
@@ -1131,9 +1262,10 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   const int nb = NN / TG::J;
   const int nz = bt.nz, g = bt.gate;
   const size_t zs = bt.zs;
-  CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
-              hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, st, src,
-                                 tb.S, tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
+  if (!tfwd_done)
+    CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
+                hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, st,
+                                   src, tb.S, tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
   if constexpr (LOGN <= 6) {
     constexpr int LN = LOGN;
     if (adjoint)
@@ -1176,7 +1308,8 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
 template <int LOGN, int LOGM>
 static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& rs, float2* spec,
                              const double* c_dev, double c_val, double mu, const SolveEpi& ep,
-                             const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof) {
+                             const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof,
+                             bool fwd_next) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   using TG = TGeo<LOGM - 1>;
   const int nb = NN / TG::J;
@@ -1205,9 +1338,19 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& r
                                  dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
                                  tb.sig_t, c_dev, (float)c_val, (float)mu, ctl, zs, g));
   const float scale = (float)(2.0 / ((double)NN * (double)M));
-  CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
-              hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb, 1, nz), dim3(TG::NT), 0, st, spec,
-                                 NN, tb.tw_t, tb.twc_t, ep, scale, ctl, zs, g));
+  if (fwd_next) {
+    // with the forward t pass of the convolution of the result
+    using TC = TGeo<LOGM>;
+    constexpr bool PK = LOGN <= 6;
+    CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
+                hipLaunchKernelGGL((k_tinv_solve_fwd<LOGM, PK>), dim3(NN / TC::J, 1, nz),
+                                   dim3(TC::NT), 0, st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep,
+                                   scale, ctl, zs, g));
+  } else {
+    CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
+                hipLaunchKernelGGL(k_tinv_solve<LOGM>, dim3(nb, 1, nz), dim3(TG::NT), 0, st, spec,
+                                   NN, tb.tw_t, tb.twc_t, ep, scale, ctl, zs, g));
+  }
   return hipGetLastError();
 }
 
@@ -1236,15 +1379,16 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& r
 
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       const Batch& bt, hipStream_t st, Prof* prof) {
-  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof)
+                       const Batch& bt, hipStream_t st, Prof* prof, bool tfwd_done) {
+  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof, tfwd_done)
 }
 
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, const RhsSrc& rs,
                         float2* spec, const double* c_dev, double c_val, double mu,
                         const SolveEpi& ep, const DevCtl* ctl, const Batch& bt, hipStream_t st,
-                        Prof* prof) {
-  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, rs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof)
+                        Prof* prof, bool fwd_next) {
+  CNLOS_DISPATCH_NM(solve_impl, tb, rhs, rs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof,
+                    fwd_next)
 }
 
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
