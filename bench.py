@@ -280,12 +280,13 @@ def algorithmic_bytes(kind, n, m, dual):
         return 2 * spec_c + hq
     if kind == "t_fwd_conv":       # the adjoint's first pass reads 3 volumes (the forward
         return spec_c + 3 * f      # operator's runs inside the u solve's last pass)
-    if kind == "t_inv_conv":       # forward launch also reads A u^k, A u^{k-1}
-        return spec_c + f + (2 * f) / 2
-    if kind == "t_fwd_solve":      # right-hand side formed in the t pass from its inputs:
-        u_in = 6 * f               # u solve: ubar, grad f, Lambda (3), phi
-        tau_in = 8 * f + n * n     # tau solve: A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau
-        return spec_s + ((u_in + tau_in) / 2 if dual else u_in)
+    if kind == "t_inv_conv":       # forward: writes A u+, reads A u^k, A u^{k-1};
+        fwd = spec_c + 3 * f       # adjoint: with the u solve's first pass (reads ubar,
+        adj = spec_c + 5 * f + spec_s  # Lambda (3), phi; writes the solve planes)
+        return (fwd + adj) / 2
+    if kind == "t_fwd_solve":      # the tau solve's (the u solve's runs in the adjoint's last
+        tau_in = 8 * f + n * n     # pass): A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau
+        return spec_s + tau_in
     if kind == "plane_solve":
         return 2 * spec_s
     if kind == "t_inv_solve":      # u solve: reads ubar, writes u+ and A u+'s first planes;

@@ -598,14 +598,18 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.out = fixed(p->gf);
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
-    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
+    // grad f stays on chip: the adjoint's last pass also runs the u solve's
+    // first (right-hand side and forward t pass); the solve's last pass also
+    // starts A u+ (forward t pass of the convolution)
+    const RhsSrc ru = rhs_u(mu);
+    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G | G_FIRST),
+                       p->st, &p->prof, false, &ru));
     SolveEpi se{};
     se.out = role(R_U_TR);
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
-    // the solve's last pass also starts A u+ (forward t pass of the convolution)
-    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu), p->spec, &ctl->L, 0.0, mu, se, ctl,
-                        gated(G | G_FIRST), p->st, &p->prof, true));
+    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, ru, p->spec, &ctl->L, 0.0, mu, se, ctl,
+                        gated(G | G_FIRST), p->st, &p->prof, true, true));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);
@@ -653,13 +657,15 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ea.out = fixed(p->gf);
     ea.au = fixed(nullptr);
     ea.au_prev = fixed(nullptr);
-    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G), p->st, &p->prof));
+    const RhsSrc ru = rhs_u(mu1);
+    HIPCHK(launch_conv(ln, lm, p->tb, sa, p->spec, true, EPI_PLAIN, ea, ctl, gated(G | G_FIRST),
+                       p->st, &p->prof, false, &ru));
     SolveEpi se{};
     se.out = role(R_U_TR);
     se.ref = role(R_UB_CUR);
     se.partials = p->partials;
-    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rhs_u(mu1), p->spec, &ctl->L, 0.0, mu1, se, ctl,
-                        gated(G | G_FIRST), p->st, &p->prof, true));
+    HIPCHK(launch_solve(ln, lm, p->tb, nullptr, ru, p->spec, &ctl->L, 0.0, mu1, se, ctl,
+                        gated(G | G_FIRST), p->st, &p->prof, true, true));
     ConvSrc sf{};
     sf.a = role(R_U_TR);
     sf.b = fixed(nullptr);

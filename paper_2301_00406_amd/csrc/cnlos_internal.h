@@ -311,17 +311,21 @@ struct Batch {
 };
 constexpr Batch kSingle{1, 0, G_NONE};
 
-// tfwd_done: the forward t pass already ran (fused into the preceding solve)
+// tfwd_done: the forward t pass already ran (fused into the preceding solve);
+// rhs_next: the inverse t pass (plain epilogue) also runs the forward t pass
+// of the u solve with this right-hand side (RHS_U, grad f kept on chip; its
+// output is not stored), and launch_solve follows with tfwd_done
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       const Batch& bt, hipStream_t st, Prof* prof, bool tfwd_done = false);
+                       const Batch& bt, hipStream_t st, Prof* prof, bool tfwd_done = false,
+                       const RhsSrc* rhs_next = nullptr);
 // fwd_next: the last pass also runs the forward t pass of the convolution of
 // the result (no weight, mask or offset); its step partials then come from
 // fused_solve_blocks blocks, and launch_conv follows with tfwd_done
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, const RhsSrc& rs,
                         float2* spec, const double* c_dev, double c_val, double mu,
                         const SolveEpi& ep, const DevCtl* ctl, const Batch& bt, hipStream_t st,
-                        Prof* prof, bool fwd_next = false);
+                        Prof* prof, bool fwd_next = false, bool tfwd_done = false);
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
                            const double* cosn, double invZ, hipStream_t st);
 int conv_blocks(int logn, int logm);          // blocks of the convolution t passes

@@ -852,11 +852,14 @@ __device__ __forceinline__ PPair p_pair(const float* __restrict__ xb, const floa
 // y - 1 neighbour's p_y comes from the neighbouring column through LDS (a
 // halo column when that column is in another block) and the t - 1
 // neighbour's p_t from the previous lane.
+// (gfl: grad f of the block's columns in LDS, [J][m], instead of rs.gf;
+// active: this thread's wave takes part, the others only meet the barrier)
 template <int SRC, int G, int E, int J, int M, int NT>
 __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, const DevCtl* ctl,
                                           const float* __restrict__ xb,
                                           const float* __restrict__ au, int col0, int b, int s,
-                                          int tid, int nn, float* pyl) {
+                                          int tid, int nn, float* pyl,
+                                          const float* gfl = nullptr, bool active = true) {
   const int logn = rs.logn;
   const uint32_t N = 1u << logn, V = (uint32_t)nn * M;
   const float mu = rs.mu, inv_mu = 1.f / mu;
@@ -879,6 +882,7 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
   float t1[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
+    if (!active) break;
     const uint32_t k = 2 * (G * r + s), kn = (k + 2) & (M - 1);
     const PPair q = p_pair(xb, rs.lam, rs.phi, mu, inv_mu, V, c, cxp, cyp, k, kn);
     const PPair qm = p_pair(xb, rs.lam, rs.phi, mu, inv_mu, V, cxm, c, cxmyp, k, kn);
@@ -887,7 +891,7 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
     float b0, b1;
     if constexpr (SRC == RHS_U) {
       const float L = (float)ctl->L;
-      const float2 g = ld2(rs.gf, c + k);
+      const float2 g = gfl ? *reinterpret_cast<const float2*>(gfl + b * M + k) : ld2(rs.gf, c + k);
       b0 = L * q.xb.x - g.x;
       b1 = L * q.xb.y - g.y;
     } else {
@@ -911,8 +915,9 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
   // of the previous r for s = 0; bin m - 1 for k = 0)
   float up[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) up[r] = __shfl(t1[r], (s + G - 1) & (G - 1), G);
+  for (int r = 0; r < E; ++r) up[r] = active ? __shfl(t1[r], (s + G - 1) & (G - 1), G) : 0.f;
   __syncthreads();
+  if (!active) return;
   // slot of the y - 1 neighbour column: previous column, the same row's last
   // column when the block holds whole rows, else the halo
   const int ym = j > 0 ? b : (J >= (int)N ? b + (int)N : 0);
@@ -921,6 +926,59 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
     const int k = 2 * (G * r + s);
     x[r].x += pyl[ym * M + k] + (s > 0 ? up[r] : up[(r + E - 1) % E]);
     x[r].y += pyl[ym * M + k + 1];
+  }
+}
+
+// Forward t pass of a diagonal solve from the right-hand side in registers
+// (x[r] = bins 2p, 2p + 1, p = G r + s): complex transform of length m/2,
+// untangle, planes kt = 0 .. m/2 - 1 (bins 0 and m/2 packed in plane 0),
+// staged coalesced writes.  J columns per block; waves with !act only meet
+// the barriers.
+template <int LOGM, int J, int NT>
+__device__ __forceinline__ void tfwd_solve_from_regs(float2 (&x)[TGeo<LOGM - 1>::E], bool act,
+                                                     float2* lds, const float2* tws,
+                                                     const float2* twc, int tid, int col0,
+                                                     float2* __restrict__ spec, int nn) {
+  using T = TGeo<LOGM - 1>;
+  constexpr int M = 1 << LOGM, H = M / 2, LOGH = LOGM - 1;
+  constexpr int G = T::G, E = T::E, ZS = H + H / 8 + 4;
+  const int b = tid / G, s = tid % G;
+  __syncthreads();
+  float2* z = lds + b * ZS;
+  if (act) {
+    dif_inlane<G, E, E / 2>(x, s, twc);
+    dif_xlane<G, E>(x, s, twc);
+#pragma unroll
+    for (int r = 0; r < E; ++r) z[zix(G * r + s)] = x[r];
+  }
+  __syncthreads();
+  float2 X[E];
+  if (act) {
+    float2 XH = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int r = 0; r <= E; ++r) {
+      const int k = r < E ? G * r + s : H;
+      if (r == E && s != 0) break;
+      const float2 zk = z[zix(brev(k & (H - 1), LOGH))];
+      const float2 zm = z[zix(brev((H - k) & (H - 1), LOGH))];
+      const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      const float2 o = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+      const float2 wk = k < H ? tws[2 * k] : make_float2(-1.f, 0.f);
+      const float2 wo = cmul(wk, o);
+      const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
+      if (r < E) X[r] = v; else XH = v;
+    }
+    if (s == 0) X[0].y = XH.x;
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
+  }
+  __syncthreads();
+  for (int it = tid; it < H * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
   }
 }
 
@@ -968,37 +1026,7 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
     rhs_pairs<SRC, G, E, J, M, NT>(x, rs, ctl, xb, au, col0, b, s, tid, nn,
                                    reinterpret_cast<float*>(lds));
   }
-  __syncthreads();
-  dif_inlane<G, E, E / 2>(x, s, twc);
-  dif_xlane<G, E>(x, s, twc);
-  float2* z = lds + b * ZS;
-#pragma unroll
-  for (int r = 0; r < E; ++r) z[zix(G * r + s)] = x[r];
-  __syncthreads();
-  float2 X[E];
-  float2 XH = make_float2(0.f, 0.f);
-#pragma unroll
-  for (int r = 0; r <= E; ++r) {
-    const int k = r < E ? G * r + s : H;
-    if (r == E && s != 0) break;
-    const float2 zk = z[zix(brev(k & (H - 1), LOGH))];
-    const float2 zm = z[zix(brev((H - k) & (H - 1), LOGH))];
-    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    const float2 o = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-    const float2 wk = k < H ? tws[2 * k] : make_float2(-1.f, 0.f);
-    const float2 wo = cmul(wk, o);
-    const float2 v = make_float2(e.x + wo.y, e.y - wo.x);
-    if (r < E) X[r] = v; else XH = v;
-  }
-  if (s == 0) X[0].y = XH.x;
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
-  __syncthreads();
-  for (int it = tid; it < H * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
-  }
+  tfwd_solve_from_regs<LOGM, J, NT>(x, true, lds, tws, twc, tid, col0, spec, nn);
 }
 
 // t pass, inverse, diagonal solve: planes kt = 0 .. m/2 - 1 (plane 0 packed
@@ -1069,6 +1097,119 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
     const int slots[1] = {SL_STEP};
     block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);
   }
+}
+
+// Inverse t pass of the adjoint convolution (grad f = A^T (A ubar - tau0),
+// eq. (10)) fused with the forward t pass of the u solve that consumes it
+// (eq. (11)): grad f of the block's columns stays in LDS, where the solve's
+// right-hand side reads it pointwise; its neighbour terms come from ubar,
+// Lambda and phi, which this launch does not change.  grad f is not written
+// to HBM.  Block geometry of the convolution pass; the solve phase runs on
+// J x G_s threads (whole waves).  The spectrum buffer is reused in place.
+template <int LOGM, bool PK>
+__global__ void __launch_bounds__(TGeo<LOGM>::NT)
+k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
+                const float2* __restrict__ tw, const float2* __restrict__ twcg, ConvEpi ep,
+                float scale, RhsSrc rs, DevCtl* ctl, size_t zs, int gate) {
+  using T = TGeo<LOGM>;
+  using TS = TGeo<LOGM - 1>;
+  constexpr int M = 1 << LOGM, H = M / 2, G = T::G, E = T::E, J = T::J, NT = T::NT;
+  constexpr int GS = TS::G, ES = TS::E;
+  static_assert(J * GS <= NT && (J * GS) % 64 == 0, "solve phase on whole waves");
+  constexpr int ZS = M + M / 8 + 4;
+  constexpr int LDS2 = (J * ZS > stg_size<J>(M + 1)) ? J * ZS : stg_size<J>(M + 1);
+  // LDS as floats: the C2R samples [0, J (m + 4)), the p_y rows of the
+  // right-hand side [0, (J + 1) m), grad f at the top [2 LDS2 - J m, 2 LDS2)
+  static_assert(2 * LDS2 >= J * (2 * M + 4) && 2 * LDS2 >= (2 * J + 1) * M, "LDS regions");
+  constexpr int GFL = 2 * LDS2 - J * M;
+  constexpr bool STAGE = M <= 1024;
+  constexpr int NNZ = STAGE ? 3 * M + 64 : 1;
+  __shared__ float2 lds[LDS2];
+  __shared__ float2 tws[M];
+  __shared__ float2 twc[M];
+  __shared__ int4 scol_l[STAGE ? M : 1];
+  __shared__ float sval_l[NNZ];
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  const CtlHead hd = ctl_head(ctl);
+  const float* xb = vol_resolve(rs.xb, hd, zo);
+  if (gated_off(hd, gate)) return;
+  if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
+  zsh_tables(S, zo);
+  tw = zsh(tw, zo);
+  twcg = zsh(twcg, zo);
+  spec = zsh(spec, zo);
+  ep.w = zsh(ep.w, zo);
+  ep.mask = zsh(ep.mask, zo);
+  rs.lam = zsh(rs.lam, zo);
+  rs.phi = zsh(rs.phi, zo);
+  const int tid = threadIdx.x, b = tid / G, s = tid % G;
+  const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
+  for (int i = tid; i < M; i += NT) {
+    tws[i] = tw[i];
+    twc[i] = twcg[i];
+  }
+  if constexpr (STAGE) {
+    for (int i = tid; i < M; i += NT) scol_l[i] = S.cols[i];
+    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.cvals[i];
+  }
+  const int4* scol = STAGE ? scol_l : S.cols;
+  const float* sval = STAGE ? sval_l : S.cvals;
+  constexpr int NP = PK ? M : M + 1;
+  for (int it = tid; it < NP * J; it += NT) {
+    const int bb = it % J, k = it / J;
+    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
+  }
+  __syncthreads();
+  // adjoint inverse t pass (as k_tinv_conv, plain epilogue)
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = brev(G * r + s, LOGM);
+    float2 Xk = lds[stg<J>(k, b)];
+    float2 Xm = lds[stg<J>(PK ? (M - k) & (M - 1) : M - k, b)];
+    if (PK && k == 0) {
+      Xm = make_float2(Xk.y, 0.f);
+      Xk.y = 0.f;
+    }
+    const float2 e = make_float2(0.5f * (Xk.x + Xm.x), 0.5f * (Xk.y - Xm.y));
+    const float2 o = make_float2(0.5f * (Xk.x - Xm.x), 0.5f * (Xk.y + Xm.y));
+    const float2 wo = cmulc(o, tws[k]);
+    x[r] = make_float2(e.x - wo.y, e.y + wo.x);
+  }
+  dit_xlane<G, E>(x, s, twc);
+  dit_inlane<G, E, E / 4>(x, s, twc);
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) x[r] = cadd(x[r], cmulc(x[r + E / 2], tws[2 * (G * r + s)]));
+  __syncthreads();                                 // staging consumed
+  float2* g2 = lds + b * (H + 2);
+#pragma unroll
+  for (int r = 0; r < E / 2; ++r) g2[G * r + s] = cscale(x[r], scale);
+  __syncthreads();
+  float* gfl = reinterpret_cast<float*>(lds) + GFL;
+  {
+    const float* g = reinterpret_cast<const float*>(g2);
+    const float mk = ep.mask ? (float)ep.mask[col] : 1.f;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = G * r + s;
+      const int4 ci = scol[k];
+      float tk = 0.f;
+      if (ci.y > 0) tk += sval[ci.z] * g[ci.x];
+      if (ci.y > 1) tk += sval[ci.z + 1] * g[ci.x + 1];
+      if (ci.y > 2) tk += sval[ci.z + 2] * g[ci.x + 2];
+      if (ep.w) tk *= ep.w[k];
+      gfl[b * M + k] = tk * mk;
+    }
+  }
+  __syncthreads();                                 // grad f in LDS; the samples are free
+  // forward t pass of the u solve with its right-hand side
+  const bool sact = tid < J * GS;
+  const int bs = tid / GS, ss = tid % GS;
+  float2 y[ES];
+  rhs_pairs<RHS_U, GS, ES, J, M, NT>(y, rs, ctl, xb, nullptr, col0, bs, ss, tid, nn,
+                                     reinterpret_cast<float*>(lds), gfl, sact);
+  tfwd_solve_from_regs<LOGM, J, NT>(y, sact, lds, tws, twc, tid, col0, spec, nn);
 }
 
 // Inverse t pass of the u solve fused with the forward t pass of the
@@ -1254,7 +1395,7 @@ int fused_solve_blocks(int logn, int logm) { return conv_blocks(logn, logm); }
 template <int LOGN, int LOGM>
 static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, bool adjoint,
                             int epi, const ConvEpi& ep, const DevCtl* ctl, const Batch& bt,
-                            hipStream_t st, Prof* prof, bool tfwd_done) {
+                            hipStream_t st, Prof* prof, bool tfwd_done, const RhsSrc* rhs_next) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   // the register plane kernel takes the real planes kt = 0, m packed in one
   constexpr bool PK = LOGN <= 6;
@@ -1291,6 +1432,13 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
                                      tb.twc_xy, ctl, zs, g));
   }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
+  if (rhs_next) {
+    CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                hipLaunchKernelGGL((k_tinv_conv_rhs<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0,
+                                   st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, *rhs_next,
+                                   const_cast<DevCtl*>(ctl), zs, g));
+    return hipGetLastError();
+  }
 #define CNLOS_TINV(E)                                                                         \
   CNLOS_TIMED(prof, KK_T_INV_CONV, st,                                                        \
               hipLaunchKernelGGL((k_tinv_conv<LOGM, E, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, \
@@ -1309,29 +1457,31 @@ template <int LOGN, int LOGM>
 static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& rs, float2* spec,
                              const double* c_dev, double c_val, double mu, const SolveEpi& ep,
                              const DevCtl* ctl, const Batch& bt, hipStream_t st, Prof* prof,
-                             bool fwd_next) {
+                             bool fwd_next, bool tfwd_done) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
   using TG = TGeo<LOGM - 1>;
   const int nb = NN / TG::J;
   const int nz = bt.nz, g = bt.gate;
   const size_t zs = bt.zs;
   DevCtl* c = const_cast<DevCtl*>(ctl);
-  switch (rs.mode) {
-    case RHS_U:
-      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
-                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_U>), dim3(nb, 1, nz), dim3(TG::NT), 0,
-                                     st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
-      break;
-    case RHS_TAU:
-      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
-                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_TAU>), dim3(nb, 1, nz), dim3(TG::NT), 0,
-                                     st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
-      break;
-    default:
-      CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
-                  hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_LOAD>), dim3(nb, 1, nz), dim3(TG::NT),
-                                     0, st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
-      break;
+  if (!tfwd_done) {
+    switch (rs.mode) {
+      case RHS_U:
+        CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                    hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_U>), dim3(nb, 1, nz), dim3(TG::NT), 0,
+                                       st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+        break;
+      case RHS_TAU:
+        CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                    hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_TAU>), dim3(nb, 1, nz), dim3(TG::NT), 0,
+                                       st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+        break;
+      default:
+        CNLOS_TIMED(prof, KK_T_FWD_SOLVE, st,
+                    hipLaunchKernelGGL((k_tfwd_solve<LOGM, RHS_LOAD>), dim3(nb, 1, nz), dim3(TG::NT),
+                                       0, st, rhs, rs, tb.tw_t, tb.twc_t, spec, NN, c, zs, g));
+        break;
+    }
   }
   CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
               hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2, 1, nz),
@@ -1379,16 +1529,18 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& r
 
 hipError_t launch_conv(int logn, int logm, const Tables& tb, const ConvSrc& src, float2* spec,
                        bool adjoint, int epi, const ConvEpi& ep, const DevCtl* ctl,
-                       const Batch& bt, hipStream_t st, Prof* prof, bool tfwd_done) {
-  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof, tfwd_done)
+                       const Batch& bt, hipStream_t st, Prof* prof, bool tfwd_done,
+                       const RhsSrc* rhs_next) {
+  CNLOS_DISPATCH_NM(conv_impl, tb, src, spec, adjoint, epi, ep, ctl, bt, st, prof, tfwd_done,
+                    rhs_next)
 }
 
 hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, const RhsSrc& rs,
                         float2* spec, const double* c_dev, double c_val, double mu,
                         const SolveEpi& ep, const DevCtl* ctl, const Batch& bt, hipStream_t st,
-                        Prof* prof, bool fwd_next) {
+                        Prof* prof, bool fwd_next, bool tfwd_done) {
   CNLOS_DISPATCH_NM(solve_impl, tb, rhs, rs, spec, c_dev, c_val, mu, ep, ctl, bt, st, prof,
-                    fwd_next)
+                    fwd_next, tfwd_done)
 }
 
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
