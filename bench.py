@@ -280,13 +280,15 @@ def algorithmic_bytes(kind, n, m, dual):
         return 2 * spec_c + hq
     if kind == "t_fwd_conv":       # the adjoint's first pass reads 3 volumes (the forward
         return spec_c + 3 * f      # operator's runs inside the u solve's last pass)
-    if kind == "t_inv_conv":       # forward: writes A u+, reads A u^k, A u^{k-1};
-        fwd = spec_c + 3 * f       # adjoint: with the u solve's first pass (reads ubar,
+    if kind == "t_inv_conv":       # adjoint: with the u solve's first pass (reads ubar,
         adj = spec_c + 5 * f + spec_s  # Lambda (3), phi; writes the solve planes)
+        if dual:                   # forward: writes A u+, reads A u^k, A u^{k-1}, and the
+            fwd = spec_c + 3 * f + 7 * f + n * n + spec_s  # tau solve's first pass (taubar,
+        else:                      # Lambda3, tau0, Lambda2 (3), phi_tau; solve planes)
+            fwd = spec_c + 4 * f   # object: A u+, A u^k, A u^{k-1}, tau0
         return (fwd + adj) / 2
-    if kind == "t_fwd_solve":      # the tau solve's (the u solve's runs in the adjoint's last
-        tau_in = 8 * f + n * n     # pass): A u+, taubar, Lambda3, tau0, Lambda2 (3), phi_tau
-        return spec_s + tau_in
+    if kind == "t_fwd_solve":      # standalone (both solves' first passes run inside the
+        return spec_s + 8 * f + n * n  # convolutions' last passes in the iteration loop)
     if kind == "plane_solve":
         return 2 * spec_s
     if kind == "t_inv_solve":      # u solve: reads ubar, writes u+ and A u+'s first planes;

@@ -676,11 +676,9 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ef.au = role(R_AU_CUR);
     ef.au_prev = role(R_AU_PREV);
     ef.partials = p->partials;
-    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st,
-                       &p->prof, true));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
-                                   gated(G), p->st));
-    const int GA = G | G_AFTER_CHECK;
+    // the forward operator's last pass also runs the tau solve's first (its
+    // right-hand side reads A u+ on chip); on a rejected trial the rest of
+    // the tau solve is gated off and the spectrum it wrote is discarded
     RhsSrc rt;
     rt.mode = RHS_TAU;
     rt.xb = role(R_TB_CUR);
@@ -694,12 +692,17 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     rt.lambda = (float)lam;
     rt.mu3 = (float)mu3;
     rt.logn = ln;
+    HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st,
+                       &p->prof, true, &rt));
+    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
+                                   gated(G), p->st));
+    const int GA = G | G_AFTER_CHECK;
     SolveEpi st2{};
     st2.out = role(R_T_TR);
     st2.ref = fixed(nullptr);
     st2.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rt, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl,
-                        gated(GA), p->st, &p->prof));
+                        gated(GA), p->st, &p->prof, false, true));
     const PostArgs pu{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu1, phi_args(p, 2, false)};
     const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_TB_CUR), role(R_TB_NEW), p->lam2,

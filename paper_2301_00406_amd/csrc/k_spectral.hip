@@ -852,9 +852,10 @@ __device__ __forceinline__ PPair p_pair(const float* __restrict__ xb, const floa
 // y - 1 neighbour's p_y comes from the neighbouring column through LDS (a
 // halo column when that column is in another block) and the t - 1
 // neighbour's p_t from the previous lane.
-// (gfl: grad f of the block's columns in LDS, [J][m], instead of rs.gf;
+// (PL: the pointwise operand of the block's columns is in LDS, gfl [J][m]:
+// grad f (RHS_U) instead of rs.gf, A u+ (RHS_TAU) instead of au;
 // active: this thread's wave takes part, the others only meet the barrier)
-template <int SRC, int G, int E, int J, int M, int NT>
+template <int SRC, int G, int E, int J, int M, int NT, bool PL = false>
 __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, const DevCtl* ctl,
                                           const float* __restrict__ xb,
                                           const float* __restrict__ au, int col0, int b, int s,
@@ -891,11 +892,16 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
     float b0, b1;
     if constexpr (SRC == RHS_U) {
       const float L = (float)ctl->L;
-      const float2 g = gfl ? *reinterpret_cast<const float2*>(gfl + b * M + k) : ld2(rs.gf, c + k);
+      float2 g;
+      if constexpr (PL) g = *reinterpret_cast<const float2*>(gfl + b * M + k);
+      else g = ld2(rs.gf, c + k);
       b0 = L * q.xb.x - g.x;
       b1 = L * q.xb.y - g.y;
     } else {
-      const float2 a = ld2(au, c + k), l3 = ld2(rs.lam3, c + k), t0 = ld2(rs.tau0, c + k);
+      float2 a;
+      if constexpr (PL) a = *reinterpret_cast<const float2*>(gfl + b * M + k);
+      else a = ld2(au, c + k);
+      const float2 l3 = ld2(rs.lam3, c + k), t0 = ld2(rs.tau0, c + k);
       const bool kept = rs.mask[col] != 0;
       const float ik = 1.f / (rs.lambda + rs.mu3), im = 1.f / rs.mu3;
       const float f0 = f_at(q.xb.x, l3.x, t0.x, kept, rs.lambda, rs.mu3, ik, im);
@@ -1099,18 +1105,25 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   }
 }
 
-// Inverse t pass of the adjoint convolution (grad f = A^T (A ubar - tau0),
-// eq. (10)) fused with the forward t pass of the u solve that consumes it
-// (eq. (11)): grad f of the block's columns stays in LDS, where the solve's
-// right-hand side reads it pointwise; its neighbour terms come from ubar,
-// Lambda and phi, which this launch does not change.  grad f is not written
-// to HBM.  Block geometry of the convolution pass; the solve phase runs on
-// J x G_s threads (whole waves).  The spectrum buffer is reused in place.
-template <int LOGM, bool PK>
+// Inverse t pass of a convolution fused with the forward t pass of the
+// diagonal solve that consumes its output pointwise:
+//   EPI_PLAIN:    the adjoint, grad f = A^T (A ubar - tau0) (eq. (10)), into
+//                 the u solve's right-hand side (eq. (11)); grad f is not
+//                 written to HBM;
+//   EPI_FWD_DUAL: the forward operator, A u+ (written, with the backtracking
+//                 partial), into the tau solve's right-hand side (Algorithm 2).
+// The output of the block's columns stays in LDS, where the right-hand side
+// reads it; the right-hand side's neighbour terms come from volumes this
+// launch does not change.  Block geometry of the convolution pass; the solve
+// phase runs on J x G_s threads (whole waves).  The spectrum buffer is
+// reused in place.
+template <int LOGM, bool PK, int EPI>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
 k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
                 const float2* __restrict__ tw, const float2* __restrict__ twcg, ConvEpi ep,
                 float scale, RhsSrc rs, DevCtl* ctl, size_t zs, int gate) {
+  static_assert(EPI == EPI_PLAIN || EPI == EPI_FWD_DUAL, "fused epilogues");
+  constexpr int SRC = EPI == EPI_PLAIN ? RHS_U : RHS_TAU;
   using T = TGeo<LOGM>;
   using TS = TGeo<LOGM - 1>;
   constexpr int M = 1 << LOGM, H = M / 2, G = T::G, E = T::E, J = T::J, NT = T::NT;
@@ -1133,6 +1146,9 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
   ctl = zsh(ctl, zo);
   const CtlHead hd = ctl_head(ctl);
   const float* xb = vol_resolve(rs.xb, hd, zo);
+  float* eout = EPI == EPI_FWD_DUAL ? vol_out(ep.out, hd, zo) : nullptr;
+  const float* eau = EPI == EPI_FWD_DUAL ? vol_in(ep.au, hd, zo) : nullptr;
+  const float* eaup = EPI == EPI_FWD_DUAL ? vol_in(ep.au_prev, hd, zo) : nullptr;
   if (gated_off(hd, gate)) return;
   if ((gate & G_FIRST) && blockIdx.x == 0 && threadIdx.x == 0) ctl->reject = 0;
   zsh_tables(S, zo);
@@ -1141,8 +1157,12 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
   spec = zsh(spec, zo);
   ep.w = zsh(ep.w, zo);
   ep.mask = zsh(ep.mask, zo);
+  ep.partials = zsh(ep.partials, zo);
   rs.lam = zsh(rs.lam, zo);
   rs.phi = zsh(rs.phi, zo);
+  rs.lam3 = zsh(rs.lam3, zo);
+  rs.tau0 = zsh(rs.tau0, zo);
+  rs.mask = zsh(rs.mask, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
   for (int i = tid; i < M; i += NT) {
@@ -1190,6 +1210,13 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
   {
     const float* g = reinterpret_cast<const float*>(g2);
     const float mk = ep.mask ? (float)ep.mask[col] : 1.f;
+    float ca = 1.f, cb = 0.f;
+    if constexpr (EPI == EPI_FWD_DUAL) {
+      const double beta = ctl->beta;
+      ca = (float)(1.0 + beta);
+      cb = (float)(-beta);
+    }
+    double acc0 = 0.0;
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int k = G * r + s;
@@ -1199,16 +1226,29 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
       if (ci.y > 1) tk += sval[ci.z + 1] * g[ci.x + 1];
       if (ci.y > 2) tk += sval[ci.z + 2] * g[ci.x + 2];
       if (ep.w) tk *= ep.w[k];
-      gfl[b * M + k] = tk * mk;
+      if constexpr (EPI == EPI_PLAIN) {
+        gfl[b * M + k] = tk * mk;
+      } else {
+        const size_t gi = (size_t)col * M + k;
+        eout[gi] = tk;
+        gfl[b * M + k] = tk;
+        const float d = tk - (ca * eau[gi] + cb * eaup[gi]);
+        acc0 += (double)d * (double)d;
+      }
+    }
+    if constexpr (EPI == EPI_FWD_DUAL) {
+      double v[1] = {acc0};
+      const int slots[1] = {SL_CHECK};
+      block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);
     }
   }
-  __syncthreads();                                 // grad f in LDS; the samples are free
+  __syncthreads();                                 // the output in LDS; the samples are free
   // forward t pass of the u solve with its right-hand side
   const bool sact = tid < J * GS;
   const int bs = tid / GS, ss = tid % GS;
   float2 y[ES];
-  rhs_pairs<RHS_U, GS, ES, J, M, NT>(y, rs, ctl, xb, nullptr, col0, bs, ss, tid, nn,
-                                     reinterpret_cast<float*>(lds), gfl, sact);
+  rhs_pairs<SRC, GS, ES, J, M, NT, true>(y, rs, ctl, xb, nullptr, col0, bs, ss, tid, nn,
+                                         reinterpret_cast<float*>(lds), gfl, sact);
   tfwd_solve_from_regs<LOGM, J, NT>(y, sact, lds, tws, twc, tid, col0, spec, nn);
 }
 
@@ -1433,10 +1473,18 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
   if (rhs_next) {
-    CNLOS_TIMED(prof, KK_T_INV_CONV, st,
-                hipLaunchKernelGGL((k_tinv_conv_rhs<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0,
-                                   st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep, scale, *rhs_next,
-                                   const_cast<DevCtl*>(ctl), zs, g));
+    if (epi == EPI_FWD_DUAL)
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv_rhs<LOGM, PK, EPI_FWD_DUAL>), dim3(nb, 1, nz),
+                                     dim3(TG::NT), 0, st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep,
+                                     scale, *rhs_next, const_cast<DevCtl*>(ctl), zs, g));
+    else if (epi == EPI_PLAIN)
+      CNLOS_TIMED(prof, KK_T_INV_CONV, st,
+                  hipLaunchKernelGGL((k_tinv_conv_rhs<LOGM, PK, EPI_PLAIN>), dim3(nb, 1, nz),
+                                     dim3(TG::NT), 0, st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep,
+                                     scale, *rhs_next, const_cast<DevCtl*>(ctl), zs, g));
+    else
+      return hipErrorInvalidValue;
     return hipGetLastError();
   }
 #define CNLOS_TINV(E)                                                                         \
