@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel event times of one extra reconstruction to stderr")
     ap.add_argument("--no-batch", action="store_true",
