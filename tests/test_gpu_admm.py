@@ -280,3 +280,37 @@ def test_medium_workload_iterations_match_oracle():
     et = rel_l2(to_host(P.signal()), s2.tau)
     say(f"  rel L2 u = {eu:.3e}, tau = {et:.3e}")
     assert eu <= 1e-4 and et <= 1e-4
+
+
+# Shapes at the edges of the fused t-pass geometry: solve-phase waves left idle
+# (m <= 128), blocks of 8 and 4 scan columns (m = 1024, 2048), a block holding
+# whole rows of the scan grid (n = 8), unpacked real planes (n = 128).
+# (n, m, warm-start iterations, dual iterations); the oracle is slow at large m.
+EDGE_SHAPES = [(8, 16, 2, 2), (8, 1024, 1, 1), (8, 2048, 1, 1), (32, 64, 2, 2), (128, 32, 2, 2)]
+
+
+@pytest.mark.parametrize("shape", EDGE_SHAPES)
+def test_algorithm2_edge_shapes_match_oracle(shape):
+    torch = need_gpu()
+    n, m, i1, i2 = shape
+    say(f"alg2 {n}x{n}x{m} {i1}+{i2} (edge geometry)")
+    sc = scenes.scene_custom(n, m, 500 + n + m, wall=0.8, bin_ps=32.0 * 128 / m, density=0.4,
+                             peak=20.0, background=0.2)
+    raw, op, tau0, _ = _setup(sc, 600 + n + m)
+    L0o = _oracle_L0(op, True, iters=2)
+    L0d = _oracle_L0(op, False, iters=2)
+    p = O.Params(a=1.5e-4, b=4e-5, mu=0.1, a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, lam=200.0)
+    s1, s2 = O.run_alg2(tau0, op, p, i1, i2, L0_obj=L0o, L0_dual=L0d)
+    cfg = _cfg(sc, model=C.MODEL_DUAL, max_iters=i2, init_iters=i1, a_u=p.a_u, b_u=p.b_u,
+               a_tau=p.a_tau, b_tau=p.b_tau, warm_a=p.a, warm_b=p.b, mu=p.mu, lam=p.lam,
+               L0=L0o, L0_dual=L0d)
+    P = C.Problem(cfg, sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    P.run(i1)
+    e1 = rel_l2(to_host(P.volume()), s1.u)
+    P.run()
+    eu = rel_l2(to_host(P.volume()), s2.u)
+    et = rel_l2(to_host(P.signal()), s2.tau)
+    say(f"  rel L2 warm u = {e1:.3e}, u = {eu:.3e}, tau = {et:.3e}")
+    assert e1 <= 1e-4 and eu <= 1e-4 and et <= 1e-4
+    P.close()
