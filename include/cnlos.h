@@ -240,18 +240,25 @@ cnlos_status cnlos_set_info(cnlos_problem* p, const cnlos_info* in);
  * Synchronizes the stream. */
 cnlos_status cnlos_get_log(cnlos_problem* p, double* host, int32_t cap, int32_t* n);
 
-/* Kernel kinds of the per-kernel timer (bit k of a mask selects kind k). */
+/* Kernel kinds of the per-kernel timer (bit k of a mask selects kind k).
+ * In the iteration loop the first pass of each diagonal solve runs inside the
+ * convolution pass before it (timed as T_INV_CONV) and the first pass of the
+ * forward operator of u+ inside the u solve's last pass (timed as
+ * T_INV_SOLVE); T_FWD_SOLVE and the forward operator's T_FWD_CONV then do not
+ * occur as launches of their own. */
 typedef enum {
   CNLOS_KK_T_FWD_CONV = 0,   /* convolution: resample + R2C along t           */
   CNLOS_KK_PLANE_CONV = 1,   /* convolution: padded (x, y) transform with H^  */
-  CNLOS_KK_T_INV_CONV = 2,   /* convolution: C2R along t + R_t^{-1} + epilogue */
+  CNLOS_KK_T_INV_CONV = 2,   /* convolution: C2R along t + R_t^{-1} + epilogue
+                                (+ a solve's right-hand side and R2C)          */
   CNLOS_KK_T_FWD_SOLVE = 3,  /* diagonal solve: right-hand side + R2C along t */
   CNLOS_KK_PLANE_SOLVE = 4,  /* diagonal solve: (x, y) transform and divide    */
-  CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t                   */
+  CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t (+ the first pass
+                                of the forward operator of the result)        */
   CNLOS_KK_VSTEP = 6,        /* reserved (v, w, f are recomputed where used)   */
   CNLOS_KK_FSTEP = 7,        /* reserved                                       */
-  CNLOS_KK_RHS_U = 8,        /* reserved (formed inside T_FWD_SOLVE)           */
-  CNLOS_KK_RHS_TAU = 9,      /* reserved (formed inside T_FWD_SOLVE)           */
+  CNLOS_KK_RHS_U = 8,        /* reserved (formed inside the solve's first pass) */
+  CNLOS_KK_RHS_TAU = 9,      /* reserved (formed inside the solve's first pass) */
   CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature: u (object
                                 model); u and tau in one kernel (dual model)   */
   CNLOS_KK_POST_TAU = 11,    /* reserved (the tau side runs inside POST_U)     */
