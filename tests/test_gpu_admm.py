@@ -300,7 +300,7 @@ def test_algorithm2_edge_shapes_match_oracle(shape):
     L0o = _oracle_L0(op, True, iters=2)
     L0d = _oracle_L0(op, False, iters=2)
     p = O.Params(a=1.5e-4, b=4e-5, mu=0.1, a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, lam=200.0)
-    s1, s2 = O.run_alg2(tau0, op, p, i1, i2, L0_obj=L0o, L0_dual=L0d)
+    s1, s2 = O.run_alg2(tau0, op, p, iters=i2, init_iters=i1, L0_obj=L0o, L0_dual=L0d)
     cfg = _cfg(sc, model=C.MODEL_DUAL, max_iters=i2, init_iters=i1, a_u=p.a_u, b_u=p.b_u,
                a_tau=p.a_tau, b_tau=p.b_tau, warm_a=p.a, warm_b=p.b, mu=p.mu, lam=p.lam,
                L0=L0o, L0_dual=L0d)
