@@ -524,9 +524,17 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
       col_fwd<LOGN>(c, s, tws, twc);
+      // frequency of position 8r + s: brev(8r + s) = 16 brev3(s) + brev4(r)
+      // (the register part is a constant), folded to the quarter; the column
+      // frequency once per column
+      int ky = brev(col, LOGL);
+      ky = ky <= N ? ky : L - ky;
+      const int kxs = brev(s, 3) << (LOGL - 3);
 #pragma unroll
       for (int r = 0; r < RE; ++r) {
-        const float2 h = Hp[hq_index<LOGN>(8 * r + s, col)];
+        int kx = kxs + brev(r, LOGL - 3);
+        kx = kx <= N ? kx : L - kx;
+        const float2 h = Hp[kx * N1 + ky];
         c[r] = ADJ ? cmulc(c[r], h) : cmul(c[r], h);
       }
       col_inv<LOGN>(c, s, tws, twc);
