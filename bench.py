@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium",
-                    choices=["small", "medium", "large", "batch", "serve"])
+                    choices=["small", "medium", "large", "batch", "serve", "ablation"])
     ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -184,6 +184,111 @@ def batched_comparison(torch, C, scenes, mix):
         "batched_voxel_iters_per_s": voxel_iters / t_batch,
         "results_bitwise_equal": bool(same),
     }
+
+
+def _ssim(x, y, sigma=1.5, data_range=1.0):
+    """Mean structural similarity of two images (Wang, Bovik, Sheikh and
+    Simoncelli 2004): Gaussian window of width sigma (radius 3.5 sigma),
+    constants K1 = 0.01, K2 = 0.03."""
+    from scipy.ndimage import gaussian_filter
+    f = lambda a: gaussian_filter(a, sigma, truncate=3.5, mode="reflect")
+    c1, c2 = (0.01 * data_range) ** 2, (0.03 * data_range) ** 2
+    mx, my = f(x), f(y)
+    vx, vy, cxy = f(x * x) - mx * mx, f(y * y) - my * my, f(x * y) - mx * my
+    s = ((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2))
+    return float(s.mean())
+
+
+def image_quality(u, u_true):
+    """Reconstruction quality against the ground truth on the front view (the
+    maximum-intensity projection along depth, each normalized to a peak of 1):
+    accuracy (1 - mean absolute error), RMSE, PSNR and SSIM, and the relative L2
+    error of the volume after the best scalar scaling (the reconstruction is
+    in normalized units)."""
+    img = u.max(axis=2)
+    ref = u_true.max(axis=2)
+    img = img / img.max() if img.max() > 0 else img
+    ref = ref / ref.max()
+    err = img - ref
+    rmse = float(np.sqrt(np.mean(err ** 2)))
+    uu = float(np.sum(u * u))
+    a = float(np.sum(u * u_true)) / uu if uu > 0 else 0.0
+    vol = float(np.linalg.norm(a * u - u_true) / np.linalg.norm(u_true))
+    return {"accuracy": 1.0 - float(np.mean(np.abs(err))), "rmse": rmse,
+            "psnr_db": 20.0 * float(np.log10(1.0 / max(rmse, 1e-12))),
+            "ssim": _ssim(img, ref), "volume_rel_err": vol}
+
+
+def _trv_weights(pr):
+    """TRV's phi = sqrt(a + b k^2) meets a at k = 0 and b|k| for large |k| when
+    its weights are the squares of the TAC/TSC ones."""
+    return {k: (v * v if k in ("a_u", "b_u", "a_tau", "b_tau", "warm_a", "warm_b") else v)
+            for k, v in pr.items()}
+
+
+def ablation(torch, C, scenes, n_scenes=4, seed=7000):
+    """Curvature functions phi (TRV, TAC, TSC) and plain TV (b = 0) for both
+    algorithms on synthetic scenes of the 64x64x512 geometry with known ground
+    truth: two scene kinds (three solid planar patches; the benchmark's five
+    point-sampled ellipsoid shells and a letter patch), each under two scan
+    masks (a regular 6x6 grid of scan points, the sparse setting of the
+    paper's curvature comparison, and 25% random points).  Every variant gets
+    the same weights (squared for TRV).  Stands in for the paper's comparison
+    on measured data, which is not available here."""
+    dev = torch.device("cuda", 0)
+    base = scenes.scene_medium()
+    n, m = base.n, base.m
+    pw = WORKLOADS["medium"]["params"]
+    variants = [("TRV", C.PHI_TRV, False), ("TAC", C.PHI_TAC, False), ("TSC", C.PHI_TSC, False),
+                ("TV", C.PHI_TSC, True)]
+    models = [("Algorithm 1", C.MODEL_OBJECT, dict(a_u=pw["warm_a"], b_u=pw["warm_b"], mu=pw["mu"]),
+               0, 250),
+              ("Algorithm 2", C.MODEL_DUAL, pw, 50, 200)]
+    kinds = [("planes", lambda s: scenes.scene_custom(n, m, s, wall=base.wall_w, bin_ps=base.bin_ps,
+                                                       density=0.25, n_planes=3, n_shells=0,
+                                                       peak=base.peak, background=base.background)),
+             ("shells", scenes.scene_medium)]
+    rows = {}
+    t0 = time.perf_counter()
+    for i, (kind, make) in ((i, k) for k in kinds for i in range(n_scenes)):
+        sc = make(seed + i)
+        opP = C.Problem(C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
+                                         bin_ps=sc.bin_ps, model=C.MODEL_OPERATOR,
+                                         falloff=C.FALLOFF_LITERAL),
+                        np.ones((n, n), np.uint8), device=dev)
+        clean = opP.apply_A(torch.tensor(sc.u_true.astype(np.float32), device=dev))
+        opP.close()
+        raw = scenes.poisson_counts(clean.double().cpu().numpy(), sc.peak, sc.background,
+                                    np.random.Generator(np.random.PCG64(sc.seed)))
+        raw = torch.tensor(raw.astype(np.float32), device=dev)
+        grid = scenes.strided_dropout_mask(n, 11, 1.0, np.random.Generator(np.random.PCG64(0)))
+        for mask_name, mask in (("6x6 grid", grid), ("25% random", sc.mask)):
+            for mname, model, params, init, iters in models:
+                for vname, phi, tv in variants:
+                    pr = _trv_weights(params) if phi == C.PHI_TRV else dict(params)
+                    if tv:
+                        pr.update({k: 0.0 for k in ("b_u", "b_tau", "warm_b") if k in pr})
+                    cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w,
+                                           wall_h_m=sc.wall_h, bin_ps=sc.bin_ps, phi=phi,
+                                           model=model, max_iters=iters, init_iters=init, **pr)
+                    P = C.Problem(cfg, mask, device=dev)
+                    P.set_measurement(raw)
+                    P.run()
+                    u = P.volume().double().cpu().numpy()
+                    P.close()
+                    rows.setdefault((kind, mask_name, mname, vname), []).append(
+                        image_quality(u, sc.u_true))
+    table = []
+    for (kind, mask_name, mname, vname), vals in rows.items():
+        r = {"scene": kind, "mask": mask_name, "method": mname, "phi": vname}
+        for k in vals[0]:
+            r[k] = float(np.mean([v[k] for v in vals]))
+        table.append(r)
+    return {"scenes": n_scenes,
+            "scene": f"{n}x{n}x{m}, {base.wall_w} m wall, {base.bin_ps:g} ps bins, "
+                     f"{base.peak:g} photons at the peak, background {base.background / base.peak:.0%}",
+            "iterations": {"Algorithm 1": 250, "Algorithm 2": "50 warm-start + 200"},
+            "seconds": time.perf_counter() - t0, "table": table}
 
 
 def serve_workload(torch, C, scenes, n_req, rate, seed=5000):
@@ -413,6 +518,15 @@ def main():
             "reconstructions_per_s": sv["reconstructions_per_s"],
             "latency_ms": sv["latency_ms"], "serving": sv, "roofline": None,
         }))
+        return
+    if args.workload == "ablation":
+        ab = ablation(torch, C, scenes)
+        for r in ab["table"]:
+            print(f"{r['scene']:6s} {r['mask']:10s} {r['method']:12s} {r['phi']:4s} accuracy {r['accuracy']:.4f}  "
+                  f"RMSE {r['rmse']:.4f}  PSNR {r['psnr_db']:6.2f} dB  SSIM {r['ssim']:.4f}  "
+                  f"volume error {r['volume_rel_err']:.4f}", file=sys.stderr)
+        print(json.dumps({"metric": "reconstruction quality by curvature function (ablation)",
+                          "data": "synthetic (seeded scenes, Poisson noise)", "ablation": ab}))
         return
     wl = WORKLOADS[args.workload]
     sc = getattr(scenes, wl["scene"])()

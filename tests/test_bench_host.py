@@ -1,0 +1,59 @@
+"""Host-side logic of the benchmark script: the image-quality measures of the
+curvature-function comparison (Table II's Accuracy, RMSE, PSNR and SSIM)."""
+import math
+
+import numpy as np
+
+import bench
+
+
+def _ssim_direct(x, y, sigma=1.5):
+    """SSIM by explicit weighted window sums over a mirror-padded image (the
+    padding scipy calls 'reflect': the edge sample repeats)."""
+    r = int(3.5 * sigma + 0.5)
+    k = np.exp(-0.5 * (np.arange(-r, r + 1) / sigma) ** 2)
+    w = np.outer(k, k) / np.outer(k, k).sum()
+    xp, yp = np.pad(x, r, mode="symmetric"), np.pad(y, r, mode="symmetric")
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    vals = []
+    for i in range(x.shape[0]):
+        for j in range(x.shape[1]):
+            a, b = xp[i:i + 2 * r + 1, j:j + 2 * r + 1], yp[i:i + 2 * r + 1, j:j + 2 * r + 1]
+            mx, my = (w * a).sum(), (w * b).sum()
+            vx, vy = (w * (a - mx) ** 2).sum(), (w * (b - my) ** 2).sum()
+            cxy = (w * (a - mx) * (b - my)).sum()
+            vals.append((2 * mx * my + c1) * (2 * cxy + c2) / ((mx * mx + my * my + c1) * (vx + vy + c2)))
+    return float(np.mean(vals))
+
+
+def test_ssim_matches_direct_window_sums():
+    rng = np.random.default_rng(3)
+    x = rng.random((17, 13))
+    y = np.clip(x + 0.2 * rng.standard_normal(x.shape), 0, 1)
+    assert abs(bench._ssim(x, y) - _ssim_direct(x, y)) < 1e-10
+    assert abs(bench._ssim(x, x) - 1.0) < 1e-12
+
+
+def test_image_quality_of_known_images():
+    u_true = np.zeros((8, 8, 4))
+    u_true[2:5, 3:6, 1] = 2.0
+    q = bench.image_quality(3.0 * u_true, u_true)          # any positive scale is exact
+    assert q["accuracy"] == 1.0 and q["rmse"] == 0.0 and q["volume_rel_err"] < 1e-15
+    assert abs(q["ssim"] - 1.0) < 1e-12
+    u = u_true.copy()
+    u[0, 0, 0] = 1.0                                        # one stray pixel at half the peak
+    q = bench.image_quality(u, u_true)
+    assert abs(q["rmse"] - math.sqrt(0.25 / 64)) < 1e-15
+    assert abs(q["accuracy"] - (1.0 - 0.5 / 64)) < 1e-15
+    assert abs(q["psnr_db"] + 20.0 * math.log10(math.sqrt(0.25 / 64))) < 1e-12
+
+
+def test_trv_weights_meet_the_other_phis_at_zero_and_infinity():
+    pr = dict(a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, warm_a=1.5e-4, warm_b=4e-5, mu=0.1,
+              lam=200.0)
+    t = bench._trv_weights(pr)
+    assert t["mu"] == 0.1 and t["lam"] == 200.0
+    for a, b in (("a_u", "b_u"), ("a_tau", "b_tau"), ("warm_a", "warm_b")):
+        assert math.isclose(math.sqrt(t[a]), pr[a])
+        kappa = 1e6
+        assert math.isclose(math.sqrt(t[a] + t[b] * kappa ** 2), pr[b] * kappa, rel_tol=1e-6)
