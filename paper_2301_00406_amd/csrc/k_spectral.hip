@@ -1374,6 +1374,9 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
   tfwd_conv_from_lds<LOGM, PK>(lds, tws, twc, srow, sval, xv, tid, col0, spec, nn);
 }
 
+// exponentials staged in LDS by the H^ setup (2m <= this; 32 KB at most)
+constexpr int kHqStagedExp = 2048;
+
 // ---------------------------------------------------------------------------
 // H^ setup: the kernel h of eq. (3) is even in dx and dy, so its padded
 // spectrum is a real cosine sum in (kx, ky) and a complex exponential in kt:
@@ -1381,41 +1384,60 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
 //                    cos(pi ky dy / n) exp(-pi i kt dq(dx,dy) / m),
 // c_0 = 1, c_d = 2.  One block per (kt, chunk of ky); FP64 accumulation; the
 // inner dy sum is staged in LDS.  Stored for kx, ky in [0, n] (the quarter).
+// The kernel offsets dq (n <= 64) and, with ET, the exponential table
+// exp(-pi i j / m), j < 2m (dynamic LDS, 2m entries), are staged in LDS; 2m is
+// a power of two, so the phase index kt q mod 2m is a mask (kt q < 2^31 for
+// m <= 2^15).  Offsets outside the cone (dq < 0) enter with weight 0, so the
+// sums run branch-free and unrolled (their loads issue together).  Both LDS
+// tables a wave sweeps are laid out with the lane index fastest (dq
+// transposed to [dy][dx], the inner sums as [dx][ky]): no bank conflicts.
 // ---------------------------------------------------------------------------
-template <int LOGN>
+template <int LOGN, bool ET>
 __global__ void __launch_bounds__(256)
 k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
            const double2* __restrict__ etab, const double* __restrict__ cosn, double invZ) {
   constexpr int N = 1 << LOGN, N1 = N + 1, KYC = N1 < 32 ? N1 : 32;
-  __shared__ double2 G[KYC * N];
+  constexpr bool DQ = N <= 64;
+  __shared__ double2 G[N * KYC];                   // [dx][ky - ky0]
   __shared__ double cs[2 * N];
+  __shared__ int dq_l[DQ ? N * N : 1];
+  extern __shared__ double2 et_l[];
   const int kt = blockIdx.x, ky0 = blockIdx.y * KYC, tid = threadIdx.x;
   const int nky = (N1 - ky0) < KYC ? (N1 - ky0) : KYC;
-  const int two_m = 2 * m;
+  const int pmask = 2 * m - 1;
   for (int i = tid; i < 2 * N; i += blockDim.x) cs[i] = cosn[i];
+  if constexpr (DQ) {
+    for (int i = tid; i < N * N; i += blockDim.x) dq_l[(i % N) * N + i / N] = dq[i];
+  }
+  if constexpr (ET) {
+    for (int i = tid; i < 2 * m; i += blockDim.x) et_l[i] = etab[i];
+  }
+  const double2* ets = ET ? et_l : etab;
   __syncthreads();
   // inner sum over dy for this block's ky range
   for (int it = tid; it < nky * N; it += blockDim.x) {
     const int kyl = it / N, dx = it % N, ky = ky0 + kyl;
     double sr = 0.0, si = 0.0;
+#pragma unroll 8
     for (int dy = 0; dy < N; ++dy) {
-      const int q = dq[dx * N + dy];
-      if (q < 0) continue;
-      const double w = (dy ? 2.0 : 1.0) * cs[(ky * dy) % (2 * N)];
-      const double2 e = etab[(int)(((long long)kt * q) % two_m)];
+      const int q = DQ ? dq_l[dy * N + dx] : dq[dx * N + dy];
+      const bool in = q >= 0;
+      const double2 e = ets[(kt * (in ? q : 0)) & pmask];
+      const double w = in ? (dy ? 2.0 : 1.0) * cs[(ky * dy) & (2 * N - 1)] : 0.0;
       sr += w * e.x;
       si += w * e.y;
     }
-    G[kyl * N + dx] = make_double2(sr, si);
+    G[dx * KYC + kyl] = make_double2(sr, si);
   }
   __syncthreads();
   // outer sum over dx
   for (int it = tid; it < N1 * nky; it += blockDim.x) {
     const int kx = it / nky, kyl = it % nky;
     double ar = 0.0, ai = 0.0;
+#pragma unroll 8
     for (int dx = 0; dx < N; ++dx) {
-      const double w = (dx ? 2.0 : 1.0) * cs[(kx * dx) % (2 * N)];
-      const double2 gv = G[kyl * N + dx];
+      const double w = (dx ? 2.0 : 1.0) * cs[(kx * dx) & (2 * N - 1)];
+      const double2 gv = G[dx * KYC + kyl];
       ar += w * gv.x;
       ai += w * gv.y;
     }
@@ -1604,14 +1626,25 @@ hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const 
   const int m = 1 << logm, n1 = (1 << logn) + 1;
   const int kyc = n1 < 32 ? n1 : 32;
   const dim3 grid(m + 1, (n1 + kyc - 1) / kyc);
+  const bool et = 2 * m <= kHqStagedExp;
+#define CNLOS_HQ(LN)                                                                           \
+  case LN:                                                                                     \
+    if (et)                                                                                    \
+      hipLaunchKernelGGL((k_build_hq<LN, true>), grid, dim3(256), 2 * m * sizeof(double2), st,  \
+                         hq, m, dq, etab, cosn, invZ);                                         \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_build_hq<LN, false>), grid, dim3(256), 0, st, hq, m, dq, etab,      \
+                         cosn, invZ);                                                          \
+    break;
   switch (logn) {
-    case 3: hipLaunchKernelGGL(k_build_hq<3>, grid, dim3(256), 0, st, hq, m, dq, etab, cosn, invZ); break;
-    case 4: hipLaunchKernelGGL(k_build_hq<4>, grid, dim3(256), 0, st, hq, m, dq, etab, cosn, invZ); break;
-    case 5: hipLaunchKernelGGL(k_build_hq<5>, grid, dim3(256), 0, st, hq, m, dq, etab, cosn, invZ); break;
-    case 6: hipLaunchKernelGGL(k_build_hq<6>, grid, dim3(256), 0, st, hq, m, dq, etab, cosn, invZ); break;
-    case 7: hipLaunchKernelGGL(k_build_hq<7>, grid, dim3(256), 0, st, hq, m, dq, etab, cosn, invZ); break;
+    CNLOS_HQ(3)
+    CNLOS_HQ(4)
+    CNLOS_HQ(5)
+    CNLOS_HQ(6)
+    CNLOS_HQ(7)
     default: return hipErrorInvalidValue;
   }
+#undef CNLOS_HQ
   return hipGetLastError();
 }
 
