@@ -36,14 +36,13 @@ __device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
 }
 
 // ---------------------------------------------------------------------------
-// launch shapes
-// ---------------------------------------------------------------------------
-
-// ---------------------------------------------------------------------------
-// t passes.  A block handles J = 8 scan columns; each column's FFT lives in
-// the registers of a group of G lanes (lane s keeps positions G*r + s).
-// Spectrum planes are exchanged with global memory through an LDS staging
-// tile [kt][J], so every plane access is a 64-byte segment.
+// t passes.  A block handles J scan columns (t_columns); each column's FFT
+// lives in the registers of a group of G <= 64 lanes, so within one wave
+// (lane s keeps positions G*r + s).  Spectrum planes are exchanged with global
+// memory through an LDS staging tile [kt][J], so every plane access is a
+// J * 8-byte segment (128 bytes up to m = 512).  Fewer lanes per column (more
+// elements per lane, fewer cross-lane stages) measured slower: the passes are
+// bound by the latency of their phases, and fewer waves hide less of it.
 // ---------------------------------------------------------------------------
 // Columns per block of a t pass of length 2^logf: 16 (128-byte plane
 // segments) while the staging tile fits LDS next to the tables, then fewer.
