@@ -259,10 +259,11 @@ typedef enum {
   CNLOS_KK_FSTEP = 7,        /* reserved                                       */
   CNLOS_KK_RHS_U = 8,        /* reserved (formed inside the solve's first pass) */
   CNLOS_KK_RHS_TAU = 9,      /* reserved (formed inside the solve's first pass) */
-  CNLOS_KK_POST_U = 10,      /* multiplier, extrapolation, curvature: u (object
-                                model); u and tau in one kernel (dual model)   */
+  CNLOS_KK_POST_U = 10,      /* backtracking decision, then multiplier,
+                                extrapolation, curvature: u (object model); u
+                                and tau in one kernel (dual model)             */
   CNLOS_KK_POST_TAU = 11,    /* reserved (the tau side runs inside POST_U)     */
-  CNLOS_KK_CONTROL = 12,     /* backtracking decision and iteration finalize   */
+  CNLOS_KK_CONTROL = 12,     /* iteration finalize (energy, log, L, FISTA t)   */
   CNLOS_KK_OTHER = 13,       /* warm-start hand-over                           */
   CNLOS_KK_COUNT = 14
 } cnlos_kernel_kind;

@@ -624,14 +624,14 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ef.partials = p->partials;
     HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_OBJ, ef, ctl, gated(G), p->st,
                        &p->prof, true));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
-                                   gated(G), p->st));
+    // the post kernel takes the backtracking decision; k_finalize applies it
+    const CheckArgs ck{p->nb_conv, p->nb_step, c.backtracking ? 1 : 0};
     const PostArgs pa{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu, phi_args(p, 1, false)};
-    TIMED(KK_POST_U, launch_post(ln, lm, pa, p->partials, ctl, gated(G | G_AFTER_CHECK), p->st));
+    TIMED(KK_POST_U, launch_post(ln, lm, pa, p->partials, ck, ctl, gated(G), p->st));
     // the data term of the energy comes from the forward pass (SL_DATA)
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu,
-                                      gated(G | G_AFTER_CHECK), p->st));
+                                      gated(G), p->st));
   }
   if (c.model != CNLOS_MODEL_DUAL) return CNLOS_OK;
 
@@ -677,8 +677,9 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     ef.au_prev = role(R_AU_PREV);
     ef.partials = p->partials;
     // the forward operator's last pass also runs the tau solve's first (its
-    // right-hand side reads A u+ on chip); on a rejected trial the rest of
-    // the tau solve is gated off and the spectrum it wrote is discarded
+    // right-hand side reads A u+ on chip); the tau solve writes the trial
+    // buffers only, so it runs before the backtracking decision, which the
+    // post kernel takes (a rejected trial's tau is recomputed in the next slot)
     RhsSrc rt;
     rt.mode = RHS_TAU;
     rt.xb = role(R_TB_CUR);
@@ -694,23 +695,21 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     rt.logn = ln;
     HIPCHK(launch_conv(ln, lm, p->tb, sf, p->spec, false, EPI_FWD_DUAL, ef, ctl, gated(G), p->st,
                        &p->prof, true, &rt));
-    TIMED(KK_CONTROL, launch_check(ctl, p->partials, p->nb_conv, p->nb_step, c.backtracking ? 1 : 0,
-                                   gated(G), p->st));
-    const int GA = G | G_AFTER_CHECK;
     SolveEpi st2{};
     st2.out = role(R_T_TR);
     st2.ref = fixed(nullptr);
     st2.partials = p->partials;
     HIPCHK(launch_solve(ln, lm, p->tb, nullptr, rt, p->spec, nullptr, 1.0 + mu3, mu2, st2, ctl,
-                        gated(GA), p->st, &p->prof, false, true));
+                        gated(G), p->st, &p->prof, false, true));
     const PostArgs pu{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu1, phi_args(p, 2, false)};
     const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_TB_CUR), role(R_TB_NEW), p->lam2,
                       p->phi_tau, (float)mu2, phi_args(p, 2, true)};
+    const CheckArgs ck{p->nb_conv, p->nb_step, c.backtracking ? 1 : 0};
     TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->lam3, mu3, lam, role(R_AU_TR), p->tau0,
-                                      p->mask, p->partials, ctl, gated(GA), p->st));
+                                      p->mask, p->partials, ck, ctl, gated(G), p->st));
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1,
-                                      gated(GA), p->st));
+                                      gated(G), p->st));
   }
   return CNLOS_OK;
 }

@@ -91,15 +91,17 @@ enum Role : int {
   R_COUNT = 11
 };
 
-// Phase gate of an iteration kernel (bits): which stage it belongs to and
-// whether it comes after the backtracking check of its iteration.
-enum Gate : int { G_NONE = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_AFTER_CHECK = 4, G_FIRST = 8 };
+// Phase gate of an iteration kernel (bits): which stage it belongs to, and
+// whether it is the first kernel of an iteration slot (it clears the previous
+// slot's rejection).
+enum Gate : int { G_NONE = 0, G_STAGE1 = 1, G_STAGE2 = 2, G_FIRST = 8 };
 
 // Scalars shared by the host driver and the kernels, resident in the workspace.
 // Every kernel of the ADMM iteration returns at once while `halt` is set, so a
-// batch of enqueued iterations stops cleanly at an error or a stop; a rejected
-// trial only sets `reject`, which makes the rest of its iteration slot a no-op,
-// and the next slot retries the iteration with the larger L.
+// batch of enqueued iterations stops cleanly at an error or a stop.  The post
+// kernel takes the backtracking decision; a rejected trial sets `reject`, the
+// post kernel stops, k_finalize doubles L instead of advancing, and the next
+// slot retries the iteration.
 struct DevCtl {
   // the fields every kernel's phase gate reads, in one 32-byte block at the
   // start (one scalar load at kernel start)
@@ -158,10 +160,8 @@ __device__ __forceinline__ CtlHead ctl_head(const DevCtl* c) {
 }
 __device__ __forceinline__ bool gated_off(const CtlHead& h, int gate) {
   const bool s1 = (gate & G_STAGE1) != 0, s2 = (gate & G_STAGE2) != 0;
-  const bool ac = (gate & G_AFTER_CHECK) != 0;
   return h.valid & ((h.halt != 0) | ((gate != G_NONE) & (h.iter >= h.target)) |
-                    (s1 & ((h.stage != 1) | (h.iter >= h.stage1_end))) | (s2 & (h.stage != 2)) |
-                    (ac & (h.reject != 0)));
+                    (s1 & ((h.stage != 1) | (h.iter >= h.stage1_end))) | (s2 & (h.stage != 2)));
 }
 
 // true when a kernel with phase gate `gate` has nothing to do for this scene
@@ -170,11 +170,10 @@ __device__ __forceinline__ bool gated_off(const CtlHead& h, int gate) {
 __device__ __forceinline__ bool gated_off(const DevCtl* c, int gate) {
   if (c == nullptr) return false;
   const int halt = c->halt, iter = c->iter, target = c->target, stage = c->stage;
-  const int s1end = c->stage1_end, rej = c->reject;
+  const int s1end = c->stage1_end;
   const bool s1 = (gate & G_STAGE1) != 0, s2 = (gate & G_STAGE2) != 0;
-  const bool ac = (gate & G_AFTER_CHECK) != 0;
   return (halt != 0) | ((gate != G_NONE) & (iter >= target)) |
-         (s1 & ((stage != 1) | (iter >= s1end))) | (s2 & (stage != 2)) | (ac & (rej != 0));
+         (s1 & ((stage != 1) | (iter >= s1end))) | (s2 & (stage != 2));
 }
 
 // A volume operand: the fixed pointer p[0] (role < 0), or the buffer p[slot]
@@ -356,15 +355,21 @@ struct PostArgs {
   PhiArgs pa;
 };
 
+// Inputs of the backtracking decision that the post kernels take: the block
+// counts of the check (forward pass) and step (u solve) partial sums, and
+// whether backtracking is on.
+struct CheckArgs {
+  int nb_conv;
+  int nb_step;
+  int bt_on;
+};
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
                             float* lam3, double mu3, double lambda, Vol au, const float* tau0,
-                            const uint8_t* mask, double* partials, const DevCtl* ctl,
-                            const Batch& bt, hipStream_t st);
+                            const uint8_t* mask, double* partials, const CheckArgs& ck,
+                            const DevCtl* ctl, const Batch& bt, hipStream_t st);
 hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
-                       const DevCtl* ctl, const Batch& bt, hipStream_t st);
+                       const CheckArgs& ck, const DevCtl* ctl, const Batch& bt, hipStream_t st);
 int stencil_blocks(int logn, int logm);
-hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
-                        const Batch& bt, hipStream_t st);
 hipError_t launch_finalize(DevCtl* ctl, double* log, const double* partials, int nb_conv,
                            int nb_sten, int dual, double lambda, double mu_res, const Batch& bt,
                            hipStream_t st);

@@ -40,6 +40,69 @@ __device__ __forceinline__ bool iter_head(DevCtl*& ctl, size_t zo, int gate) {
   ctl = zsh(ctl, zo);
   return iter_gate(ctl, ctl_head(ctl), gate);
 }
+// Backtracking decision (Beck-Teboulle).  For the quadratic data term f the
+// sufficient-decrease test f(u+) <= f(ubar) + <u+ - ubar, grad f(ubar)> +
+// L/2 |u+ - ubar|^2 is exactly |B (u+ - ubar)|^2 <= L |u+ - ubar|^2, B = A_D
+// (object) or A (dual); the left side comes from the difference of A u+ and
+// the cached A ubar, free of the cancellation of the literal form.  Every
+// block of the post kernel takes the decision from the same fixed-order FP64
+// sums of the check and step partials, so all blocks agree; L changes only in
+// k_finalize, after the post kernel.
+enum Decision : int { D_ACCEPT = 0, D_REJECT = 1, D_NONFINITE = 2 };
+__device__ __forceinline__ int check_decision(const double* __restrict__ partials,
+                                              const CheckArgs& ck, double L) {
+  constexpr int NW = kStencilThreads / 64;
+  __shared__ double red[2][NW];
+  __shared__ int dec;
+  double a = 0.0, b = 0.0;
+  const int nmax = ck.nb_conv > ck.nb_step ? ck.nb_conv : ck.nb_step;
+  for (int i = threadIdx.x; i < nmax; i += kStencilThreads) {
+    const double pa = i < ck.nb_conv ? partials[(size_t)SL_CHECK * kMaxBlocks + i] : 0.0;
+    const double pb = i < ck.nb_step ? partials[(size_t)SL_STEP * kMaxBlocks + i] : 0.0;
+    a += pa;
+    b += pb;
+  }
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = a;
+    red[1][wid] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      sa += red[0][w];
+      sb += red[1][w];
+    }
+    dec = (!isfinite(sa) || !isfinite(sb)) ? D_NONFINITE
+          : (ck.bt_on && !(sa <= L * sb)) ? D_REJECT
+                                          : D_ACCEPT;
+  }
+  __syncthreads();
+  return dec;
+}
+
+// The post kernel's blocks stop at a rejected or non-finite trial; block 0
+// records the outcome (the rest of the slot is then a no-op, and k_finalize
+// does the bookkeeping of a rejection).
+__device__ __forceinline__ bool trial_accepted(DevCtl* ctl, const double* partials,
+                                               const CheckArgs& ck, double L) {
+  const int dec = check_decision(partials, ck, L);
+  if (dec == D_ACCEPT) return true;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (dec == D_NONFINITE) {
+      ctl->halt = 1;
+      ctl->reason = HR_NONFINITE;
+    } else {
+      ctl->reject = 1;
+    }
+  }
+  return false;
+}
+
 __device__ __forceinline__ float* vol_at(const Vol& v, const DevCtl* c, size_t zo) {
   return vol_resolve(v, c, zo);
 }
@@ -201,21 +264,22 @@ __device__ __forceinline__ void post_pair(const float* __restrict__ xn,
 
 // Algorithm 1's updates after the accepted step (u side).
 __global__ void __launch_bounds__(kStencilThreads)
-k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs,
-       int gate) {
+k_post(PostArgs pu, double* __restrict__ partials, CheckArgs ck, int logn, int logm, DevCtl* ctl,
+       size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
   const CtlHead hd = ctl_head(ctl);
+  const double L = ctl->L, t = ctl->t;
   const float* xn = vol_resolve(pu.xn, hd, zo);
   const float* xo = vol_resolve(pu.xo, hd, zo);
   const float* xb = vol_resolve(pu.xb, hd, zo);
   float* xbn = vol_resolve(pu.xbn, hd, zo);
   if (!iter_gate(ctl, hd, gate)) return;
+  partials = zsh(partials, zo);
+  if (!trial_accepted(ctl, partials, ck, L)) return;
   pu.lam = zsh(pu.lam, zo);
   pu.phi = zsh(pu.phi, zo);
-  partials = zsh(partials, zo);
   const uint32_t V = 1u << (2 * logn + logm), P = V / 2;
-  const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)((t - 1.0) / tn);
   const float eta2 = pu.pa.eta * pu.pa.eta;
@@ -234,10 +298,12 @@ k_post(PostArgs pu, double* __restrict__ partials, int logn, int logm, DevCtl* c
 __global__ void __launch_bounds__(kStencilThreads)
 k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float lambda,
             Vol au_v, const float* __restrict__ tau0, const uint8_t* __restrict__ mask,
-            double* __restrict__ partials, int logn, int logm, DevCtl* ctl, size_t zs, int gate) {
+            double* __restrict__ partials, CheckArgs ck, int logn, int logm, DevCtl* ctl,
+            size_t zs, int gate) {
   const size_t zo = (size_t)blockIdx.z * zs;
   ctl = zsh(ctl, zo);
   const CtlHead hd = ctl_head(ctl);
+  const double L = ctl->L, t = ctl->t;
   const float* uxn = vol_resolve(pu.xn, hd, zo);
   const float* uxo = vol_resolve(pu.xo, hd, zo);
   const float* uxb = vol_resolve(pu.xb, hd, zo);
@@ -248,6 +314,8 @@ k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float
   float* txbn = vol_resolve(pt.xbn, hd, zo);
   const float* au = vol_resolve(au_v, hd, zo);
   if (!iter_gate(ctl, hd, gate)) return;
+  partials = zsh(partials, zo);
+  if (!trial_accepted(ctl, partials, ck, L)) return;
   pu.lam = zsh(pu.lam, zo);
   pu.phi = zsh(pu.phi, zo);
   pt.lam = zsh(pt.lam, zo);
@@ -255,9 +323,7 @@ k_post_dual(PostArgs pu, PostArgs pt, float* __restrict__ lam3, float mu3, float
   lam3 = zsh(lam3, zo);
   tau0 = zsh(tau0, zo);
   mask = zsh(mask, zo);
-  partials = zsh(partials, zo);
   const uint32_t V = 1u << (2 * logn + logm), P = V / 2;
-  const double t = ctl->t;
   const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
   const float beta = (float)((t - 1.0) / tn);
   const float eu = pu.pa.eta * pu.pa.eta, et = pt.pa.eta * pt.pa.eta;
@@ -287,48 +353,9 @@ k_phi_of(const float* __restrict__ x, float* __restrict__ phi, PhiArgs pa, int l
   }
 }
 
-// Backtracking decision (Beck-Teboulle).  For the quadratic data term f the
-// sufficient-decrease test f(u+) <= f(ubar) + <u+ - ubar, grad f(ubar)> +
-// L/2 |u+ - ubar|^2 is exactly |B (u+ - ubar)|^2 <= L |u+ - ubar|^2, B = A_D
-// (object) or A (dual); the left side comes from the difference of A u+ and
-// the cached A ubar, free of the cancellation of the literal form.
-__global__ void __launch_bounds__(kCtlThreads)
-k_check(DevCtl* ctl, const double* __restrict__ partials, int nb_conv, int nb_step, int bt_on,
-        size_t zs, int gate) {
-  const size_t zo = (size_t)blockIdx.z * zs;
-  ctl = zsh(ctl, zo);
-  partials = zsh(partials, zo);
-  // every controller field the decision needs is read up front, with the
-  // gate fields (not after the reduction's barriers)
-  const CtlHead hd = ctl_head(ctl);
-  const double L = ctl->L, bt_factor = ctl->bt_factor;
-  const int bt_rejects = ctl->bt_rejects, bt_max = ctl->bt_max_trials;
-  if (!iter_gate(ctl, hd, gate)) return;
-  const int slots[2] = {SL_CHECK, SL_STEP}, nbs[2] = {nb_conv, nb_step};
-  double sums[2];
-  block_sum_partials_k<2>(partials, slots, nbs, kMaxBlocks, sums);
-  const double s_chk = sums[0], s_step = sums[1];
-  if (threadIdx.x == 0) {
-    if (!isfinite(s_chk) || !isfinite(s_step)) {
-      ctl->halt = 1;
-      ctl->reason = HR_NONFINITE;
-    } else if (bt_on && !(s_chk <= L * s_step)) {
-      const int trials = hd.trials + 1;
-      ctl->trials = trials;
-      ctl->bt_rejects = bt_rejects + 1;
-      if (trials > bt_max) {
-        ctl->halt = 1;
-        ctl->reason = HR_BACKTRACK;
-      } else {
-        // the rest of this slot is skipped; the next slot redoes the iteration
-        ctl->reject = 1;
-        ctl->L = L * bt_factor;
-      }
-    }
-  }
-}
-
-// Energy, residuals, log row, FISTA t update, stopping rule.
+// After a rejected trial: one more trial for this iteration with L doubled,
+// or a halt when the trials are exhausted.  After an accepted one: energy,
+// residuals, log row, FISTA t update, stopping rule.
 __global__ void __launch_bounds__(kCtlThreads)
 k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ partials,
            int nb_conv, int nb_sten, int dual, double lambda, double mu_res, size_t zs, int gate) {
@@ -340,8 +367,24 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
   // fields (not after the reduction's barriers)
   const CtlHead hd = ctl_head(ctl);
   const double Ep = ctl->energy_prev, L = ctl->L, t = ctl->t, eps_stop = ctl->eps_stop;
-  const int log_count = ctl->log_count;
+  const double bt_factor = ctl->bt_factor;
+  const int log_count = ctl->log_count, bt_rejects = ctl->bt_rejects, bt_max = ctl->bt_max_trials;
   if (!iter_gate(ctl, hd, gate)) return;
+  if (hd.reject) {
+    if (threadIdx.x == 0) {
+      const int trials = hd.trials + 1;
+      ctl->trials = trials;
+      ctl->bt_rejects = bt_rejects + 1;
+      if (trials > bt_max) {
+        ctl->halt = 1;
+        ctl->reason = HR_BACKTRACK;
+      } else {
+        // the next slot repeats the iteration
+        ctl->L = L * bt_factor;
+      }
+    }
+    return;
+  }
   double E, prim, dres;
   if (!dual) {
     const int slots[4] = {SL_TV_U, SL_PRIMAL, SL_DUAL, SL_DATA};
@@ -570,26 +613,19 @@ hipError_t launch_fstep(int logn, int logm, const float* taubar, const float* la
 
 hipError_t launch_post_dual(int logn, int logm, const PostArgs& pu, const PostArgs& pt,
                             float* lam3, double mu3, double lambda, Vol au, const float* tau0,
-                            const uint8_t* mask, double* partials, const DevCtl* ctl,
-                            const Batch& bt, hipStream_t st) {
+                            const uint8_t* mask, double* partials, const CheckArgs& ck,
+                            const DevCtl* ctl, const Batch& bt, hipStream_t st) {
   hipLaunchKernelGGL(k_post_dual, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pu, pt,
-                     lam3, (float)mu3, (float)lambda, au, tau0, mask, partials, logn, logm,
+                     lam3, (float)mu3, (float)lambda, au, tau0, mask, partials, ck, logn, logm,
                      const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 
 
 hipError_t launch_post(int logn, int logm, const PostArgs& pa, double* partials,
-                       const DevCtl* ctl, const Batch& bt, hipStream_t st) {
+                       const CheckArgs& ck, const DevCtl* ctl, const Batch& bt, hipStream_t st) {
   hipLaunchKernelGGL(k_post, sgrid_z(logn, logm, bt), dim3(kStencilThreads), 0, st, pa, partials,
-                     logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
-  return hipGetLastError();
-}
-
-hipError_t launch_check(DevCtl* ctl, const double* partials, int nb_conv, int nb_step, int bt_on,
-                        const Batch& bt, hipStream_t st) {
-  hipLaunchKernelGGL(k_check, dim3(1, 1, bt.nz), dim3(kCtlThreads), 0, st, ctl, partials, nb_conv,
-                     nb_step, bt_on, bt.zs, bt.gate);
+                     ck, logn, logm, const_cast<DevCtl*>(ctl), bt.zs, bt.gate);
   return hipGetLastError();
 }
 

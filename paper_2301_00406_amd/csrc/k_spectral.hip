@@ -811,7 +811,7 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
 //
 // With SRC != RHS_LOAD the source is the solve's right-hand side, computed
 // here per bin (RhsSrc) instead of being read from a stored volume; the u
-// solve's instance is the first rejection-aware kernel of an iteration slot
+// solve's instance is the first kernel of an iteration slot
 // and clears the previous slot's rejection (G_FIRST).
 // p = mu v + Lambda at the two bins k, k + 1 (k even) of one scan column,
 // v = shrink(grad xbar - Lambda/mu, phi/mu) as in the v-step (eq. (7)).
