@@ -230,6 +230,8 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
   double acc[K];
   // every load is issued before the first add (fixed trip counts, unrolled):
   // one memory round trip instead of K
+  // (a load under a condition compiles to a branch with a wait after it, so
+  // the index is clamped and the value masked instead)
   constexpr int kPer = 4;   // covers 4 x blockDim >= max_blocks partials (1024 threads)
   double vals[K][kPer];
 #pragma unroll
@@ -237,13 +239,16 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
       const int i = threadIdx.x + j * (int)blockDim.x;
-      vals[k][j] = i < nb[k] ? partials[(size_t)slot[k] * max_blocks + i] : 0.0;
+      vals[k][j] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
     }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     acc[k] = 0.0;
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) acc[k] += vals[k][j];
+    for (int j = 0; j < kPer; ++j) {
+      const int i = threadIdx.x + j * (int)blockDim.x;
+      acc[k] += i < nb[k] ? vals[k][j] : 0.0;
+    }
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

@@ -54,13 +54,18 @@ __device__ __forceinline__ int check_decision(const double* __restrict__ partial
   constexpr int NW = kStencilThreads / 64;
   __shared__ double red[2][NW];
   __shared__ int dec;
-  double a = 0.0, b = 0.0;
+  // both slots' loads of a step issue together: index clamped, value masked
+  // (a load under a per-lane condition compiles to a branch with a wait after
+  // it); one step per kStencilThreads partials
+  const double* pc = partials + (size_t)SL_CHECK * kMaxBlocks;
+  const double* ps = partials + (size_t)SL_STEP * kMaxBlocks;
   const int nmax = ck.nb_conv > ck.nb_step ? ck.nb_conv : ck.nb_step;
+  double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nmax; i += kStencilThreads) {
-    const double pa = i < ck.nb_conv ? partials[(size_t)SL_CHECK * kMaxBlocks + i] : 0.0;
-    const double pb = i < ck.nb_step ? partials[(size_t)SL_STEP * kMaxBlocks + i] : 0.0;
-    a += pa;
-    b += pb;
+    const double va = pc[i < ck.nb_conv ? i : 0];
+    const double vb = ps[i < ck.nb_step ? i : 0];
+    a += i < ck.nb_conv ? va : 0.0;
+    b += i < ck.nb_step ? vb : 0.0;
   }
   a = wave_sum(a);
   b = wave_sum(b);
