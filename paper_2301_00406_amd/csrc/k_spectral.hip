@@ -68,6 +68,45 @@ constexpr int stg_size(int rows) { return rows * (J + 1) + rows / 8 + J; }
 // that bit-reversed access patterns spread over the banks.
 __device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
 
+// The resampling sums below are branch-free: a load under a per-lane
+// condition compiles to a branch with a wait after it, so the indices of
+// absent taps are clamped into the row (or to 0 for an empty row) and their
+// terms masked by selects; all of a lane's table and sample loads can then
+// issue together.  The sums keep the order of the tap-by-tap form.
+//
+// R_z of one z bin from its row (first sample k0, cnt taps, weights at off):
+// rows of more than 3 taps (interior weights exactly 1) from the exclusive
+// prefix sums pf, shorter rows tap by tap.
+__device__ __forceinline__ float rz_row(const int4 ri, const float* sval, const float* xf,
+                                        const float* pf) {
+  const int cnt = ri.y;
+  const bool any = cnt > 0;
+  const int k0 = any ? ri.x : 0, off = any ? ri.z : 0;
+  const int t1 = any ? cnt - 1 : 0, i1 = cnt > 1 ? 1 : 0;
+  const float wa = sval[off], wb = sval[off + t1], wm = sval[off + i1];
+  const float xa = xf[k0], xb = xf[k0 + t1], xm = xf[k0 + i1];
+  const float pa = pf[k0 + t1], pb = pf[k0 + i1];
+  const float acc_l = wa * xa + (pa - pb) + wb * xb;
+  float acc_s = wa * xa;
+  acc_s = cnt == 3 ? fmaf(wm, xm, acc_s) : acc_s;
+  acc_s = cnt >= 2 ? fmaf(wb, xb, acc_s) : acc_s;
+  return cnt > 3 ? acc_l : (any ? acc_s : 0.f);
+}
+
+// S^T of one t bin from its column of at most 3 taps (first sample x, weights
+// at z; checked on the host).
+__device__ __forceinline__ float st_taps(const int4 ci, const float* sval, const float* g) {
+  const int cnt = ci.y;
+  const int x = cnt > 0 ? ci.x : 0, z = cnt > 0 ? ci.z : 0;
+  const int i1 = cnt > 1 ? 1 : 0, i2 = cnt > 2 ? 2 : i1;
+  const float w0 = sval[z], w1 = sval[z + i1], w2 = sval[z + i2];
+  const float g0 = g[x], g1 = g[x + i1], g2 = g[x + i2];
+  float tk = cnt > 0 ? w0 * g0 : 0.f;
+  tk = cnt > 1 ? fmaf(w1, g1, tk) : tk;
+  tk = cnt > 2 ? fmaf(w2, g2, tk) : tk;
+  return tk;
+}
+
 // t pass, forward, convolution: x -> R_z x -> zero-pad to 2m -> R2C -> planes.
 // The real length-2m transform is a complex length-m transform of the packed
 // pairs (x[2p], x[2p+1]); its upper half is zero, so the first DIF stage is a
@@ -115,24 +154,7 @@ __device__ __forceinline__ void tfwd_conv_from_lds(float2* lds, const float2* tw
     const int p = G * r + s;
     float v[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int4 ri = srow[2 * p + h];
-      const int k0 = ri.x, cnt = ri.y, off = ri.z;
-      float acc = 0.f;
-      if (cnt > 0) {
-        const int t1 = cnt - 1;
-        const float wa = sval[off], wb = sval[off + t1];
-        const float xa = xf[k0], xb = xf[k0 + t1];
-        if (cnt > 3) {
-          acc = wa * xa + (pf[k0 + t1] - pf[k0 + 1]) + wb * xb;
-        } else {
-          acc = wa * xa;
-          if (cnt == 3) acc += sval[off + 1] * xf[k0 + 1];
-          if (cnt >= 2) acc += wb * xb;
-        }
-      }
-      v[h] = acc;
-    }
+    for (int h = 0; h < 2; ++h) v[h] = rz_row(srow[2 * p + h], sval, xf, pf);
     x[r] = make_float2(v[0], v[1]);
   }
 #pragma unroll
@@ -226,15 +248,31 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   const float sc = src.scale_div ? (float)(1.0 / *src.scale_div) : 1.f;
   const float mk = src.mask ? (float)src.mask[col] : 1.f;
   float* xf = reinterpret_cast<float*>(lds + b * ZS);     // this column's real input
-  float xv[E];
+  // every operand is loaded unconditionally (an absent one from a stand-in,
+  // a, and replaced by the identity), so all of a lane's loads issue at once:
+  // a load under a condition compiles to a branch with a wait after it
+  const bool hb = sb != nullptr, hc = sc_ != nullptr, hw = src.w != nullptr;
+  const float* pb = hb ? sb : sa;
+  const float* pc = hc ? sc_ : sa;
+  const float* pw = hw ? src.w : sa;
+  float va[E], vb[E], vc[E], vw[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = G * r + s;
     const size_t g = (size_t)col * M + k;
-    float x = ca * sa[g];
-    if (sb) x += cb * sb[g];
-    if (sc_) x -= sc_[g];
-    if (src.w) x *= src.w[k];
+    va[r] = sa[g];
+    vb[r] = pb[g];
+    vc[r] = pc[g];
+    vw[r] = pw[k];
+  }
+  float xv[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = G * r + s;
+    float x = ca * va[r];
+    x += cb * (hb ? vb[r] : 0.f);
+    x -= hc ? vc[r] : 0.f;
+    x *= hw ? vw[r] : 1.f;
     xv[r] = x * sc * mk;
     xf[k] = xv[r];
   }
@@ -327,15 +365,27 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
     cb = (float)(-beta);
   }
   const float mk = ep.mask ? (float)ep.mask[col] : 1.f;
+  // global operands loaded unconditionally, absent ones from a stand-in (the
+  // output column) and replaced by the identity, so the loads issue at once
+  const bool hw = ep.w != nullptr;
+  const float* pw = hw ? ep.w : eout + (size_t)col * M;
+  float vw[E], vau[E], vaup[E], vt0[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int k = G * r + s;
-    const int4 ci = scol[k];               // at most 3 taps (checked on the host)
-    float tk = 0.f;
-    if (ci.y > 0) tk += sval[ci.z] * g[ci.x];
-    if (ci.y > 1) tk += sval[ci.z + 1] * g[ci.x + 1];
-    if (ci.y > 2) tk += sval[ci.z + 2] * g[ci.x + 2];
-    if (ep.w) tk *= ep.w[k];
+    const size_t gi = (size_t)col * M + k;
+    vw[r] = pw[k];
+    if constexpr (EPI == EPI_FWD_OBJ || EPI == EPI_FWD_DUAL) {
+      vau[r] = eau[gi];
+      vaup[r] = eaup[gi];
+    }
+    if constexpr (EPI == EPI_FWD_OBJ) vt0[r] = ep.tau0[gi];
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int k = G * r + s;
+    float tk = st_taps(scol[k], sval, g);
+    tk *= hw ? vw[r] : 1.f;
     const size_t gi = (size_t)col * M + k;
     if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
       tk *= mk;
@@ -343,13 +393,12 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
       if (EPI == EPI_NORM) acc0 += (double)tk * (double)tk;
     } else {
       eout[gi] = tk;
-      const float d = tk - (ca * eau[gi] + cb * eaup[gi]);
+      const float d = tk - (ca * vau[r] + cb * vaup[r]);
       if (EPI == EPI_FWD_OBJ) {
-        if (mk != 0.f) {
-          acc0 += (double)d * (double)d;
-          const float rr = tk - ep.tau0[gi];
-          acc1 += (double)rr * (double)rr;
-        }
+        const float rr = tk - vt0[r];
+        const bool kept = mk != 0.f;
+        acc0 += kept ? (double)d * (double)d : 0.0;
+        acc1 += kept ? (double)rr * (double)rr : 0.0;
       } else {
         acc0 += (double)d * (double)d;
       }
@@ -1093,17 +1142,20 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   dit_inlane<G, E, E / 2>(x, s, twc);
   double acc = 0.0;
   float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
-  const float2* ref2 = eref ? reinterpret_cast<const float2*>(eref) + (size_t)col * H : nullptr;
+  // the reference is read unconditionally (the output column stands in when
+  // there is none), so its loads are not each behind a branch and a wait
+  const bool hr = eref != nullptr;
+  const float2* ref2 = reinterpret_cast<const float2*>(hr ? eref : eout) + (size_t)col * H;
+  float2 rv[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) rv[r] = ref2[G * r + s];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = G * r + s;
     const float2 y = cscale(x[r], scale);
     out2[p] = y;
-    if (ref2) {
-      const float2 rv = ref2[p];
-      const float d0 = y.x - rv.x, d1 = y.y - rv.y;
-      acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
-    }
+    const float d0 = y.x - rv[r].x, d1 = y.y - rv[r].y;
+    acc += hr ? (double)d0 * (double)d0 + (double)d1 * (double)d1 : 0.0;
   }
   if (eref) {
     double v[1] = {acc};
@@ -1224,22 +1276,32 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
       cb = (float)(-beta);
     }
     double acc0 = 0.0;
+    // global operands loaded up front, unconditionally (see k_tinv_conv)
+    const bool hw = ep.w != nullptr;
+    const float* pw = hw ? ep.w : xb + (size_t)col * M;
+    float vw[E], vau[E], vaup[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
       const int k = G * r + s;
-      const int4 ci = scol[k];
-      float tk = 0.f;
-      if (ci.y > 0) tk += sval[ci.z] * g[ci.x];
-      if (ci.y > 1) tk += sval[ci.z + 1] * g[ci.x + 1];
-      if (ci.y > 2) tk += sval[ci.z + 2] * g[ci.x + 2];
-      if (ep.w) tk *= ep.w[k];
+      vw[r] = pw[k];
+      if constexpr (EPI == EPI_FWD_DUAL) {
+        const size_t gi = (size_t)col * M + k;
+        vau[r] = eau[gi];
+        vaup[r] = eaup[gi];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int k = G * r + s;
+      float tk = st_taps(scol[k], sval, g);
+      tk *= hw ? vw[r] : 1.f;
       if constexpr (EPI == EPI_PLAIN) {
         gfl[b * M + k] = tk * mk;
       } else {
         const size_t gi = (size_t)col * M + k;
         eout[gi] = tk;
         gfl[b * M + k] = tk;
-        const float d = tk - (ca * eau[gi] + cb * eaup[gi]);
+        const float d = tk - (ca * vau[r] + cb * vaup[r]);
         acc0 += (double)d * (double)d;
       }
     }
@@ -1343,19 +1405,21 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
     dit_inlane<GS, ES, ES / 2>(y, ss, twc);
     const int col = col0 + bs;
     float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
-    const float2* ref2 = eref ? reinterpret_cast<const float2*>(eref) + (size_t)col * H : nullptr;
+    // the reference is read unconditionally (see k_tinv_solve)
+    const bool hr = eref != nullptr;
+    const float2* ref2 = reinterpret_cast<const float2*>(hr ? eref : eout) + (size_t)col * H;
     float2* xf2 = lds + bs * ZS;                   // the column's real samples, as pairs
+    float2 rv[ES];
+#pragma unroll
+    for (int r = 0; r < ES; ++r) rv[r] = ref2[GS * r + ss];
 #pragma unroll
     for (int r = 0; r < ES; ++r) {
       const int p = GS * r + ss;
       const float2 v = cscale(y[r], scale);
       out2[p] = v;
       xf2[p] = v;
-      if (ref2) {
-        const float2 rv = ref2[p];
-        const float d0 = v.x - rv.x, d1 = v.y - rv.y;
-        acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
-      }
+      const float d0 = v.x - rv[r].x, d1 = v.y - rv[r].y;
+      acc += hr ? (double)d0 * (double)d0 + (double)d1 * (double)d1 : 0.0;
     }
   }
   if (eref) {
