@@ -968,10 +968,13 @@ __device__ __forceinline__ void rhs_pairs(float2 (&x)[E], const RhsSrc& rs, cons
     x[r].x = b0 - ((q.px[0] - qm.px[0]) + q.py[0] + q.pt[0]);
     x[r].y = b1 - ((q.px[1] - qm.px[1]) + q.py[1] + (q.pt[1] - q.pt[0]));
     t1[r] = q.pt[1];
-    // finish this pair here (no sinking of its arithmetic past the loop), one
-    // pair's loads in flight at a time: no spills
-    asm volatile("" : "+v"(x[r].x), "+v"(x[r].y), "+v"(t1[r]));
-    __builtin_amdgcn_sched_barrier(0);
+    // finish every second pair here (no sinking of its arithmetic past the
+    // loop): two pairs' loads in flight at a time, without spills
+    if ((r & 1) == 1 || r == E - 1) {
+      if (r & 1) asm volatile("" : "+v"(x[r - 1].x), "+v"(x[r - 1].y), "+v"(t1[r - 1]));
+      asm volatile("" : "+v"(x[r].x), "+v"(x[r].y), "+v"(t1[r]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   // p_t at bin k - 1: the second bin of the previous lane's pair (lane G - 1
   // of the previous r for s = 0; bin m - 1 for k = 0)
