@@ -57,6 +57,33 @@ struct TGeo {                                 // transform of length F = 2^LOGF
   static constexpr int NT = J * G;
 };
 
+// Block-strided copies with compile-time extents.  A loop whose trip count
+// depends on the thread index is not unrolled, and each of its iterations
+// then waits for its own load before its store; here a thread issues up to 8
+// loads (indices clamped into range) before its first store.
+template <int NT, int COUNT, typename Ld, typename St>
+__device__ __forceinline__ void block_copy(int tid, Ld ld, St st) {
+  constexpr int NS = (COUNT + NT - 1) / NT, CH = NS < 8 ? NS : 8;
+#pragma unroll
+  for (int c0 = 0; c0 < NS; c0 += CH) {
+    decltype(ld(0)) v[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int it = tid + (c0 + j) * NT;
+      v[j] = ld(it < COUNT ? it : COUNT - 1);
+    }
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int it = tid + (c0 + j) * NT;
+      if (c0 + j < NS && it < COUNT) st(it, v[j]);
+    }
+  }
+}
+template <int NT, int COUNT, typename T>
+__device__ __forceinline__ void table_to_lds(T* dst, const T* __restrict__ src, int tid) {
+  block_copy<NT, COUNT>(tid, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
+}
+
 // LDS index of staging element (kt, column b): rows of J + 1 plus one extra
 // slot every 8 rows, so that rows kt and kt + 8 (bit-reversed neighbours) and
 // consecutive rows fall into different banks.
@@ -64,6 +91,21 @@ template <int J>
 __device__ __forceinline__ int stg(int k, int b) { return k * (J + 1) + (k >> 3) + b; }
 template <int J>
 constexpr int stg_size(int rows) { return rows * (J + 1) + rows / 8 + J; }
+// planes k < NP of the block's J columns <-> the LDS staging tile
+template <int J, int NT, int NP>
+__device__ __forceinline__ void planes_to_lds(float2* lds, const float2* __restrict__ spec, int nn,
+                                              int col0, int tid) {
+  block_copy<NT, NP * J>(
+      tid, [&](int it) { return spec[(size_t)(it / J) * nn + col0 + it % J]; },
+      [&](int it, float2 v) { lds[stg<J>(it / J, it % J)] = v; });
+}
+template <int J, int NT, int NP>
+__device__ __forceinline__ void lds_to_planes(const float2* lds, float2* __restrict__ spec, int nn,
+                                              int col0, int tid) {
+  block_copy<NT, NP * J>(
+      tid, [&](int it) { return lds[stg<J>(it / J, it % J)]; },
+      [&](int it, float2 v) { spec[(size_t)(it / J) * nn + col0 + it % J] = v; });
+}
 // LDS index of a column's transform element p, padded every 8 elements so
 // that bit-reversed access patterns spread over the banks.
 __device__ __forceinline__ int zix(int p) { return p + (p >> 3); }
@@ -189,11 +231,8 @@ __device__ __forceinline__ void tfwd_conv_from_lds(float2* lds, const float2* tw
   for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
   if (!PK && s == 0) lds[stg<J>(M, b)] = XM;
   __syncthreads();
-  constexpr int NP = PK ? M : M + 1;
-  for (int it = tid; it < NP * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
-  }}
+  lds_to_planes<J, NT, PK ? M : M + 1>(lds, spec, nn, col0, tid);
+}
 
 template <int LOGM, bool PK>
 __global__ void __launch_bounds__(TGeo<LOGM>::NT)
@@ -228,13 +267,11 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   src.scale_div = zsh(src.scale_div, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) {
-    tws[i] = tw[i];
-    twc[i] = twcg[i];
-  }
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, M>(twc, twcg, tid);
   if constexpr (STAGE) {
-    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
-    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
+    table_to_lds<NT, M>(srow_l, S.rows, tid);
+    table_to_lds<NT, NNZ>(sval_l, S.rvals, tid);
   }
   const int4* srow = STAGE ? srow_l : S.rows;
   const float* sval = STAGE ? sval_l : S.rvals;
@@ -313,21 +350,15 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) {
-    tws[i] = tw[i];
-    twc[i] = twcg[i];
-  }
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, M>(twc, twcg, tid);
   if constexpr (STAGE) {
-    for (int i = tid; i < M; i += NT) scol_l[i] = S.cols[i];
-    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.cvals[i];
+    table_to_lds<NT, M>(scol_l, S.cols, tid);
+    table_to_lds<NT, NNZ>(sval_l, S.cvals, tid);
   }
   const int4* scol = STAGE ? scol_l : S.cols;
   const float* sval = STAGE ? sval_l : S.cvals;
-  constexpr int NP = PK ? M : M + 1;
-  for (int it = tid; it < NP * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
-  }
+  planes_to_lds<J, NT, PK ? M : M + 1>(lds, spec, nn, col0, tid);
   __syncthreads();
   // packed even/odd spectrum at this lane's bit-reversed positions:
   // Z[k] = 1/2 (X_k + conj X_{m-k}) + i/2 conj(W^k) (X_k - conj X_{m-k})
@@ -1041,10 +1072,7 @@ __device__ __forceinline__ void tfwd_solve_from_regs(float2 (&x)[TGeo<LOGM - 1>:
     for (int r = 0; r < E; ++r) lds[stg<J>(G * r + s, b)] = X[r];
   }
   __syncthreads();
-  for (int it = tid; it < H * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    spec[(size_t)k * nn + col0 + bb] = lds[stg<J>(k, bb)];
-  }
+  lds_to_planes<J, NT, H>(lds, spec, nn, col0, tid);
 }
 
 template <int LOGM, int SRC>
@@ -1071,8 +1099,8 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
   spec = zsh(spec, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) tws[i] = tw[i];
-  for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, H>(twc, twcg, tid);
   float2 x[E];
   if constexpr (SRC == RHS_LOAD) {
     src = zsh(src, zo);
@@ -1119,12 +1147,9 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) tws[i] = tw[i];
-  for (int i = tid; i < H; i += NT) twc[i] = twcg[i];
-  for (int it = tid; it < H * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
-  }
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, H>(twc, twcg, tid);
+  planes_to_lds<J, NT, H>(lds, spec, nn, col0, tid);
   __syncthreads();
   float2 x[E];
 #pragma unroll
@@ -1227,21 +1252,15 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
   rs.mask = zsh(rs.mask, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  for (int i = tid; i < M; i += NT) {
-    tws[i] = tw[i];
-    twc[i] = twcg[i];
-  }
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, M>(twc, twcg, tid);
   if constexpr (STAGE) {
-    for (int i = tid; i < M; i += NT) scol_l[i] = S.cols[i];
-    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.cvals[i];
+    table_to_lds<NT, M>(scol_l, S.cols, tid);
+    table_to_lds<NT, NNZ>(sval_l, S.cvals, tid);
   }
   const int4* scol = STAGE ? scol_l : S.cols;
   const float* sval = STAGE ? sval_l : S.cvals;
-  constexpr int NP = PK ? M : M + 1;
-  for (int it = tid; it < NP * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
-  }
+  planes_to_lds<J, NT, PK ? M : M + 1>(lds, spec, nn, col0, tid);
   __syncthreads();
   // adjoint inverse t pass (as k_tinv_conv, plain epilogue)
   float2 x[E];
@@ -1366,20 +1385,15 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J;
-  for (int i = tid; i < M; i += NT) {
-    tws[i] = tw[i];
-    twc[i] = twcg[i];
-  }
+  table_to_lds<NT, M>(tws, tw, tid);
+  table_to_lds<NT, M>(twc, twcg, tid);
   if constexpr (STAGE) {
-    for (int i = tid; i < M; i += NT) srow_l[i] = S.rows[i];
-    for (int i = tid; i < NNZ; i += NT) sval_l[i] = S.rvals[i];
+    table_to_lds<NT, M>(srow_l, S.rows, tid);
+    table_to_lds<NT, NNZ>(sval_l, S.rvals, tid);
   }
   const int4* srow = STAGE ? srow_l : S.rows;
   const float* sval = STAGE ? sval_l : S.rvals;
-  for (int it = tid; it < H * J; it += NT) {
-    const int bb = it % J, k = it / J;
-    lds[stg<J>(k, bb)] = spec[(size_t)k * nn + col0 + bb];
-  }
+  planes_to_lds<J, NT, H>(lds, spec, nn, col0, tid);
   __syncthreads();
   // solve phase: packed real inverse of length m (as k_tinv_solve)
   const bool sact = tid < J * GS;
