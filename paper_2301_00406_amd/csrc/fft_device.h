@@ -230,25 +230,23 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
   double acc[K];
   // every load is issued before the first add (fixed trip counts, unrolled):
   // one memory round trip instead of K
-  // (a load under a condition compiles to a branch with a wait after it, so
-  // the index is clamped and the value masked instead)
+  // (a load under a per-lane condition compiles to a branch with a wait after
+  // it, so the index is clamped and the value masked instead); chunks of
+  // blockDim partials, only as many as the longest array needs
   constexpr int kPer = 4;   // covers 4 x blockDim >= max_blocks partials (1024 threads)
-  double vals[K][kPer];
+  int nbmax = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k)
+  for (int k = 0; k < K; ++k) nbmax = nb[k] > nbmax ? nb[k] : nbmax;
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int i = threadIdx.x + j * (int)blockDim.x;
-      vals[k][j] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
-    }
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int j = 0; j < kPer && j * (int)blockDim.x < nbmax; ++j) {
+    const int i = threadIdx.x + j * (int)blockDim.x;
+    double vals[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    acc[k] = 0.0;
+    for (int k = 0; k < K; ++k)
+      vals[k] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int i = threadIdx.x + j * (int)blockDim.x;
-      acc[k] += i < nb[k] ? vals[k][j] : 0.0;
-    }
+    for (int k = 0; k < K; ++k) acc[k] += i < nb[k] ? vals[k] : 0.0;
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
