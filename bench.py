@@ -454,12 +454,16 @@ def cpu_baseline(sc, wl, cpu_iters):
     p = O.Params(a=pr.get("warm_a", pr["a_u"]), b=pr.get("warm_b", pr["b_u"]), mu=pr["mu"],
                  a_u=pr["a_u"], b_u=pr["b_u"], a_tau=pr.get("a_tau", 0.0),
                  b_tau=pr.get("b_tau", 0.0), lam=pr.get("lam", 200.0))
-    # step constants from short power estimates (untimed; they only set the scale)
+    # step constants from short power estimates (untimed; they only set the
+    # scale): masked for Algorithm 1, unmasked for Algorithm 2's u-step, as
+    # the GPU path does
     L0o = 2 * O.power_norm2(lambda x: O.apply_A(x, op, True), lambda y: O.apply_AT(y, op, True),
                             tau0.shape, 2)
+    L0d = 2 * O.power_norm2(lambda x: O.apply_A(x, op, False),
+                            lambda y: O.apply_AT(y, op, False), tau0.shape, 2)
     t0 = time.perf_counter()
     if wl["model"] == "dual":
-        O.run_alg2(tau0, op, p, cpu_iters, 1, L0_obj=L0o, L0_dual=L0o)
+        O.run_alg2(tau0, op, p, cpu_iters, 1, L0_obj=L0o, L0_dual=L0d)
         iters = cpu_iters + 1
     else:
         O.run_alg1(tau0, op, p, cpu_iters, L0=L0o)
