@@ -461,20 +461,32 @@ def cpu_baseline(sc, wl, cpu_iters):
                             tau0.shape, 2)
     L0d = 2 * O.power_norm2(lambda x: O.apply_A(x, op, False),
                             lambda y: O.apply_AT(y, op, False), tau0.shape, 2)
-    t0 = time.perf_counter()
+    fwdD = lambda x: O.apply_A(x, op, True)
+    adjD = lambda y: O.apply_AT(y, op, True)
     if wl["model"] == "dual":
-        O.run_alg2(tau0, op, p, cpu_iters, 1, L0_obj=L0o, L0_dual=L0d)
-        iters = cpu_iters + 1
+        # one warm-start iteration of Algorithm 1 (untimed), then the timed
+        # Algorithm-2 iterations: the steps of the oracle's run_alg2
+        fwd = lambda x: O.apply_A(x, op, False)
+        adj = lambda y: O.apply_AT(y, op, False)
+        s1 = O.alg1_init(tau0.shape, p, L0o)
+        O.alg1_step(s1, tau0, fwdD, adjD, p)
+        s2 = O.alg2_init(s1.u, p, L0d)
+        t0 = time.perf_counter()
+        for _ in range(cpu_iters):
+            O.alg2_step(s2, tau0, op.mask, fwd, adj, p)
+        what = f"{cpu_iters} Algorithm-2 iteration(s) after a 1-iteration warm start (untimed)"
     else:
-        O.run_alg1(tau0, op, p, cpu_iters, L0=L0o)
-        iters = cpu_iters
+        s1 = O.alg1_init(tau0.shape, p, L0o)
+        t0 = time.perf_counter()
+        for _ in range(cpu_iters):
+            O.alg1_step(s1, tau0, fwdD, adjD, p)
+        what = f"{cpu_iters} Algorithm-1 iteration(s)"
     dt = time.perf_counter() - t0
     V = sc.n * sc.n * sc.m
-    return {"value": V * iters / dt, "unit": "voxel-ADMM-iters/s", "cores": int(O.WORKERS),
+    return {"value": V * cpu_iters / dt, "unit": "voxel-ADMM-iters/s", "cores": int(O.WORKERS),
             "kind": "oracle",
-            "sample": f"{iters} ADMM iterations ({'1 warm-start + ' + str(cpu_iters) + ' dual' if wl['model'] == 'dual' else 'object model'}) "
-                      f"of the same {sc.n}x{sc.n}x{sc.m} scene, FP64 NumPy/SciPy FFT with "
-                      f"{O.WORKERS} workers, {dt:.1f} s"}
+            "sample": f"{what} of the same {sc.n}x{sc.n}x{sc.m} scene, FP64 NumPy/SciPy FFT "
+                      f"with {O.WORKERS} workers, {dt:.1f} s"}
 
 
 def main():
