@@ -145,7 +145,7 @@ typedef struct cnlos_info {
   double L0_obj;            /* step constant used by Algorithm 1 (and the warm start) */
   double L0_dual;           /* step constant used by Algorithm 2                      */
   double L;                 /* current step constant                                  */
-  double t;                 /* current FISTA t_k                                      */
+  double t;                 /* current FISTA t_k (1 after a restart)                  */
   double beta;              /* extrapolation weight that produced ubar^k              */
   double meas_scale;        /* normalization s of the measurement                     */
   double energy_prev;       /* last energy (NaN before the first iteration)           */
@@ -201,12 +201,16 @@ cnlos_status cnlos_apply_A(cnlos_problem* p, const float* u_dev, float* tau_dev,
  * of the data term, Section 3.1).  May not alias.  Asynchronous. */
 cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev, int32_t masked);
 
-/* Run ADMM iterations: iters > 0 runs that many more (counting warm-start
- * iterations of the dual model), iters <= 0 runs to completion
+/* Run ADMM iterations (Algorithm 1, or Algorithm 2 after init_iters
+ * iterations of Algorithm 1): iters > 0 runs that many more (counting
+ * warm-start iterations of the dual model), iters <= 0 runs to completion
  * (max_iters, plus init_iters for the dual model).  Resumable: two calls of
- * T1 and T2 iterations equal one call of T1 + T2.  Stops early when eps_stop > 0
- * and the relative energy change falls to eps_stop.  Requires a measurement.
- * Fills *out if it is not NULL.  Synchronizes the stream. */
+ * T1 and T2 iterations equal one call of T1 + T2.  A trial step that fails the
+ * backtracking test is repeated with L * bt_factor; when an accepted iterate's
+ * energy exceeds the previous one by more than a relative 1e-3, the FISTA
+ * sequence restarts (t = 1).  Stops early when eps_stop > 0 and the relative
+ * energy change falls to eps_stop.  Requires a measurement.  Fills *out if it
+ * is not NULL.  Synchronizes the stream. */
 cnlos_status cnlos_run(cnlos_problem* p, int32_t iters, cnlos_report* out);
 
 /* Zero the ADMM state (u = ubar = 0, multipliers 0, phi = a, t = 1, L = L0),
