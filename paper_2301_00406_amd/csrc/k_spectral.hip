@@ -528,16 +528,22 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
   }
   __syncthreads();
   float2 w[2][RE];
+  // frequency of position 8r + s: brev(8r + s) = 16 brev3(s) + brev4(r) (the
+  // register part is a constant); the column frequency once per column
+  const int kxs = brev(s, 3) << (LOGL - 3);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const int col = (tid >> 3) + half * N;
-    const int colp = brev((L - brev(col, LOGL)) & (L - 1), LOGL);
+    const int fy = brev(col, LOGL);
+    const int colp = brev((L - fy) & (L - 1), LOGL);
+    const int ky = fy <= N ? fy : L - fy;
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
       const int p = 8 * r + s;
-      const int pp = brev((L - brev(p, LOGL)) & (L - 1), LOGL);
+      const int fx = kxs + brev(r, LOGL - 3);
+      const int pp = brev((L - fx) & (L - 1), LOGL);
       const float2 own = Y[p * YS + col], par = Y[pp * YS + colp];
-      const int q = hq_index<LOGN>(p, col);
+      const int q = (fx <= N ? fx : L - fx) * (N + 1) + ky;
       const float h0 = H0[q].x, hm = Hm[q].x;
       const float a = 0.5f * (h0 + hm), b = 0.5f * (h0 - hm);
       w[half][r] = make_float2(a * own.x + b * par.x, a * own.y - b * par.y);
