@@ -280,7 +280,8 @@ struct Tables {
   ResampleTables S;
   const float* sig_xy;    // 4 sin^2(pi k / n), k < n
   const float* sig_t;     // 4 sin^2(pi k / m), k <= m/2
-  const float2* hq;       // H^ quarter spectrum [m+1][n+1][n+1]
+  const float2* hq;       // H^ per kt plane: lane-ordered [2n/8][2n][8] (n <= 64),
+                          // the quarter [n+1 (ky)][n+1 (kx)] (n = 128)
 };
 
 // ---------------------------------------------------------------- launchers

@@ -494,16 +494,6 @@ __device__ __forceinline__ void col_inv(float2 (&c)[PlaneRegCfg<LOGN>::RE], int 
   for (int r = 0; r < RE / 2; ++r) c[r] = cadd(c[r], cmulc(c[r + RE / 2], tws[8 * r + s]));
 }
 
-// quarter-spectrum index of the frequency at bit-reversed positions (px, py)
-template <int LOGN>
-__device__ __forceinline__ int hq_index(int px, int py) {
-  constexpr int N = 1 << LOGN, L = 2 * N;
-  int kx = brev(px, LOGN + 1), ky = brev(py, LOGN + 1);
-  kx = kx <= N ? kx : L - kx;
-  ky = ky <= N ? ky : L - ky;
-  return kx * (N + 1) + ky;
-}
-
 // column pass of block 0 (the packed real planes kt = 0 and kt = m).  The
 // forward column spectra Z^ of all 2n columns go to LDS (2n rows), then each
 // position combines its own value with the partner at (-kx, -ky):
@@ -528,22 +518,20 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
   }
   __syncthreads();
   float2 w[2][RE];
-  // frequency of position 8r + s: brev(8r + s) = 16 brev3(s) + brev4(r) (the
-  // register part is a constant); the column frequency once per column
+  // the partner of position 8r + s: frequency brev(8r + s) = 16 brev3(s) +
+  // brev4(r) (the register part is a constant), negated; the column's once
   const int kxs = brev(s, 3) << (LOGL - 3);
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const int col = (tid >> 3) + half * N;
-    const int fy = brev(col, LOGL);
-    const int colp = brev((L - fy) & (L - 1), LOGL);
-    const int ky = fy <= N ? fy : L - fy;
+    const int colp = brev((L - brev(col, LOGL)) & (L - 1), LOGL);
 #pragma unroll
     for (int r = 0; r < RE; ++r) {
       const int p = 8 * r + s;
       const int fx = kxs + brev(r, LOGL - 3);
       const int pp = brev((L - fx) & (L - 1), LOGL);
       const float2 own = Y[p * YS + col], par = Y[pp * YS + colp];
-      const int q = (fx <= N ? fx : L - fx) * (N + 1) + ky;
+      const int q = (r * L + col) * 8 + s;                // lane-ordered H^
       const float h0 = H0[q].x, hm = Hm[q].x;
       const float a = 0.5f * (h0 + hm), b = 0.5f * (h0 - hm);
       w[half][r] = make_float2(a * own.x + b * par.x, a * own.y - b * par.y);
@@ -580,7 +568,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   twcg = zsh(twcg, zo);
   const int tid = threadIdx.x;
   float2* P = spec + (size_t)blockIdx.x * N * N;
-  const float2* Hp = hq + (size_t)blockIdx.x * N1 * N1;
+  const float2* Hp = hq + (size_t)blockIdx.x * L * L;     // lane-ordered H^ of this plane
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
   __syncthreads();
@@ -598,7 +586,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    plane_conv_cols_packed<LOGN>(Y, hq, hq + (size_t)gridDim.x * N1 * N1, tws, twc, tid);
+    plane_conv_cols_packed<LOGN>(Y, hq, hq + (size_t)gridDim.x * L * L, tws, twc, tid);
   } else {
     // 2n spectrum columns, 8 lanes each, two columns per lane group
     const int s = tid & 7;
@@ -609,17 +597,11 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
       col_fwd<LOGN>(c, s, tws, twc);
-      // frequency of position 8r + s: brev(8r + s) = 16 brev3(s) + brev4(r)
-      // (the register part is a constant), folded to the quarter; the column
-      // frequency once per column
-      int ky = brev(col, LOGL);
-      ky = ky <= N ? ky : L - ky;
-      const int kxs = brev(s, 3) << (LOGL - 3);
+      // H^ at this lane's positions: a wave's load of register r reads 64
+      // consecutive entries
 #pragma unroll
       for (int r = 0; r < RE; ++r) {
-        int kx = kxs + brev(r, LOGL - 3);
-        kx = kx <= N ? kx : L - kx;
-        const float2 h = Hp[kx * N1 + ky];
+        const float2 h = Hp[(r * L + col) * 8 + s];
         c[r] = ADJ ? cmulc(c[r], h) : cmul(c[r], h);
       }
       col_inv<LOGN>(c, s, tws, twc);
@@ -703,7 +685,7 @@ __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, co
       for (int r = r0; r < r0 + 8; ++r) {
         int kx = brev(8 * r + s, LOGN + 1);
         kx = kx <= N ? kx : L - kx;
-        const float2 hv = Hp[kx * N1 + ky];
+        const float2 hv = Hp[ky * N1 + kx];
         c[r] = ADJ ? cmulc(c[r], hv) : cmul(c[r], hv);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -1462,6 +1444,13 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
 
 // exponentials staged in LDS by the H^ setup (2m <= this; 32 KB at most)
 constexpr int kHqStagedExp = 2048;
+// Layout of H^.  n <= 64 (the register plane kernel): lane-ordered, the full
+// 2n x 2n spectrum of each kt plane as [r][col][s], r < 2n / 8, col < 2n,
+// s < 8, holding the frequency at position 8r + s of column col (so a wave's
+// load of register r reads 64 consecutive entries).  n = 128 (the half-plane
+// kernel): the quarter kx, ky in [0, n] as [ky][kx].
+template <int LOGN>
+constexpr bool kHqLaneOrdered = LOGN <= 6;
 
 // ---------------------------------------------------------------------------
 // H^ setup: the kernel h of eq. (3) is even in dx and dy, so its padded
@@ -1469,7 +1458,8 @@ constexpr int kHqStagedExp = 2048;
 //   H^[kt][kx][ky] = (1/Z) sum_{dx,dy >= 0} c_dx c_dy cos(pi kx dx / n)
 //                    cos(pi ky dy / n) exp(-pi i kt dq(dx,dy) / m),
 // c_0 = 1, c_d = 2.  One block per (kt, chunk of ky); FP64 accumulation; the
-// inner dy sum is staged in LDS.  Stored for kx, ky in [0, n] (the quarter).
+// inner dy sum is staged in LDS.  Computed for kx, ky in [0, n] (the
+// quarter) and stored in the layout kHqLaneOrdered selects.
 // The kernel offsets dq (n <= 64) and, with ET, the exponential table
 // exp(-pi i j / m), j < 2m (dynamic LDS, 2m entries), are staged in LDS; 2m is
 // a power of two, so the phase index kt q mod 2m is a mask (kt q < 2^31 for
@@ -1518,7 +1508,7 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
   __syncthreads();
   // outer sum over dx
   for (int it = tid; it < N1 * nky; it += blockDim.x) {
-    const int kx = it / nky, kyl = it % nky;
+    const int kyl = it / N1, kx = it % N1, ky = ky0 + kyl;
     double ar = 0.0, ai = 0.0;
 #pragma unroll 8
     for (int dx = 0; dx < N; ++dx) {
@@ -1527,8 +1517,24 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
       ar += w * gv.x;
       ai += w * gv.y;
     }
-    hq[(size_t)kt * N1 * N1 + (size_t)kx * N1 + ky0 + kyl] =
-        make_float2((float)(ar * invZ), (float)(ai * invZ));
+    const float2 v = make_float2((float)(ar * invZ), (float)(ai * invZ));
+    if constexpr (kHqLaneOrdered<LOGN>) {
+      // every image (+-kx, +-ky) of the quarter entry, at the register r,
+      // column and lane s of the plane kernel that multiplies by it: the
+      // frequency fx (fy) sits at the bit-reversed position p = 8r + s (col)
+      constexpr int L = 2 * N, LOGL = LOGN + 1;
+      float2* Hk = hq + (size_t)kt * L * L;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int fx = (e & 1) ? (L - kx) & (L - 1) : kx;
+        const int fy = (e & 2) ? (L - ky) & (L - 1) : ky;
+        if (((e & 1) && (kx == 0 || kx == N)) || ((e & 2) && (ky == 0 || ky == N))) continue;
+        const int p = brev(fx, LOGL), col = brev(fy, LOGL);
+        Hk[((p >> 3) * L + col) * 8 + (p & 7)] = v;
+      }
+    } else {
+      hq[(size_t)kt * N1 * N1 + (size_t)ky * N1 + kx] = v;
+    }
   }
 }
 
