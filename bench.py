@@ -379,10 +379,9 @@ def algorithmic_bytes(kind, n, m, dual):
     V = n * n * m
     spec_c = (m + 1) * n * n * 8          # convolution spectrum, complex64
     spec_s = (m // 2 + 1) * n * n * 8     # solve spectrum
-    # kernel spectrum: the register plane kernel (n <= 64) reads each plane's
-    # full 2n x 2n spectrum, lane-ordered so that its loads coalesce; the
-    # half-plane kernel (n = 128) reads the quarter
-    hq = (m + 1) * (4 * n * n if n <= 64 else (n + 1) * (n + 1)) * 8
+    # kernel spectrum: the plane kernel reads each plane's full 2n x 2n
+    # spectrum, lane-ordered so that its loads coalesce
+    hq = (m + 1) * 4 * n * n * 8
     f = 4 * V
     if kind == "plane_conv":
         return 2 * spec_c + hq

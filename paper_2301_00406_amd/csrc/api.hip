@@ -257,9 +257,8 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
   const size_t V = (size_t)n * n * m;
   const size_t nn = (size_t)n * n;
   const size_t nspec = (size_t)(m + 1) * nn;
-  // H^: lane-ordered full 2n x 2n planes for the register plane kernel
-  // (n <= 64), the quarter (n + 1)^2 for the half-plane kernel (n = 128)
-  const size_t nhq = (size_t)(m + 1) * (n <= 64 ? (size_t)4 * n * n : (size_t)(n + 1) * (n + 1));
+  // H^: the full 2n x 2n spectrum of every kt plane, lane-ordered
+  const size_t nhq = (size_t)(m + 1) * 4 * n * n;
   DevCtl* ctl = cv.take<DevCtl>(1);
   double* partials = cv.take<double>((size_t)SL_COUNT * kMaxBlocks);
   double* logbuf = cv.take<double>((size_t)kLogRows * kLogCols);

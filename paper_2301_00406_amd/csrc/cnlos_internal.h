@@ -280,8 +280,8 @@ struct Tables {
   ResampleTables S;
   const float* sig_xy;    // 4 sin^2(pi k / n), k < n
   const float* sig_t;     // 4 sin^2(pi k / m), k <= m/2
-  const float2* hq;       // H^ per kt plane: lane-ordered [2n/8][2n][8] (n <= 64),
-                          // the quarter [n+1 (ky)][n+1 (kx)] (n = 128)
+  const float2* hq;       // H^: [m+1] planes of 4 n^2 entries, lane-ordered for the
+                          // plane kernel that reads them (hq_lane_index)
 };
 
 // ---------------------------------------------------------------- launchers

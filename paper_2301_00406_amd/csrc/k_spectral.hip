@@ -554,7 +554,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
                  size_t zs, int gate) {
   using PC = PlaneRegCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, NT = PC::NT;
-  constexpr int RE = PC::RE, YS = PC::YS, N1 = N + 1;
+  constexpr int RE = PC::RE, YS = PC::YS;
   // n rows of row spectra; block 0 uses all 2n rows for its column spectra
   __shared__ float2 Y[2 * N * YS];
   __shared__ float2 tws[N];
@@ -667,7 +667,7 @@ template <int LOGN, bool ADJ>
 __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, const float2* tws,
                                           const float2* twc, int g, int s) {
   using PC = PlaneHalfCfg<LOGN>;
-  constexpr int N = PC::N, L = PC::L, YS = PC::YS, G = PC::G, N1 = N + 1;
+  constexpr int N = PC::N, YS = PC::YS, G = PC::G;
   constexpr int RE = PlaneRegCfg<LOGN>::RE;
 #pragma unroll 1
   for (int i = 0; i < 2; ++i) {
@@ -676,16 +676,14 @@ __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, co
 #pragma unroll
     for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
     col_fwd<LOGN>(c, s, tws, twc);
-    int ky = 2 * brev(col, LOGN) + h;
-    ky = ky <= N ? ky : L - ky;
-    // H^ in chunks of 8, so that its loads do not all stay live at once
+    // H^ (lane-ordered: a wave's load reads 64 consecutive entries) in chunks
+    // of 8, so that its loads do not all stay live at once
+    const float2* Hh = Hp + ((size_t)h * RE * N + col) * 8 + s;
 #pragma unroll
     for (int r0 = 0; r0 < RE; r0 += 8) {
 #pragma unroll
       for (int r = r0; r < r0 + 8; ++r) {
-        int kx = brev(8 * r + s, LOGN + 1);
-        kx = kx <= N ? kx : L - kx;
-        const float2 hv = Hp[ky * N1 + kx];
+        const float2 hv = Hh[r * N * 8];
         c[r] = ADJ ? cmulc(c[r], hv) : cmul(c[r], hv);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -720,7 +718,6 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
                   size_t zs, int gate) {
   using PC = PlaneHalfCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, RN = PC::RN, YS = PC::YS;
-  constexpr int N1 = N + 1;
   static_assert(2 * G == N, "two rows per lane group");
   __shared__ float2 Y[N * YS];
   __shared__ float2 tws[N];
@@ -734,7 +731,7 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
   twcg = zsh(twcg, zo);
   const int tid = threadIdx.x, g = tid >> 3, s = tid & 7;
   float2* P = spec + (size_t)blockIdx.x * N * N;
-  const float2* Hp = hq + (size_t)blockIdx.x * N1 * N1;
+  const float2* Hp = hq + (size_t)blockIdx.x * L * L;     // lane-ordered H^ of this plane
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
   __syncthreads();
@@ -1444,13 +1441,23 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
 
 // exponentials staged in LDS by the H^ setup (2m <= this; 32 KB at most)
 constexpr int kHqStagedExp = 2048;
-// Layout of H^.  n <= 64 (the register plane kernel): lane-ordered, the full
-// 2n x 2n spectrum of each kt plane as [r][col][s], r < 2n / 8, col < 2n,
-// s < 8, holding the frequency at position 8r + s of column col (so a wave's
-// load of register r reads 64 consecutive entries).  n = 128 (the half-plane
-// kernel): the quarter kx, ky in [0, n] as [ky][kx].
+// Layout of H^: lane-ordered, the full 2n x 2n spectrum of each kt plane in
+// the order the plane kernel's lanes multiply it, so that a wave's load of
+// one register reads 64 consecutive entries.  Frequency (fx, fy) in [0, 2n)^2
+// sits at position p = brev(fx) (register p / 8, lane p % 8) of a column:
+//   n <= 64 (register kernel):  [r][col][s], col = brev(fy) < 2n;
+//   n = 128 (half-plane kernel): [h][r][col][s], h = fy % 2 (the ky half),
+//                                col = brev(fy / 2) < n.
 template <int LOGN>
-constexpr bool kHqLaneOrdered = LOGN <= 6;
+__device__ __forceinline__ int hq_lane_index(int fx, int fy) {
+  constexpr int N = 1 << LOGN, L = 2 * N, LOGL = LOGN + 1, RE = L / 8;
+  const int p = brev(fx, LOGL);
+  if constexpr (LOGN <= 6) {
+    return ((p >> 3) * L + brev(fy, LOGL)) * 8 + (p & 7);
+  } else {
+    return (((fy & 1) * RE + (p >> 3)) * N + brev(fy >> 1, LOGN)) * 8 + (p & 7);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // H^ setup: the kernel h of eq. (3) is even in dx and dy, so its padded
@@ -1459,7 +1466,7 @@ constexpr bool kHqLaneOrdered = LOGN <= 6;
 //                    cos(pi ky dy / n) exp(-pi i kt dq(dx,dy) / m),
 // c_0 = 1, c_d = 2.  One block per (kt, chunk of ky); FP64 accumulation; the
 // inner dy sum is staged in LDS.  Computed for kx, ky in [0, n] (the
-// quarter) and stored in the layout kHqLaneOrdered selects.
+// quarter) and stored lane-ordered (hq_lane_index).
 // The kernel offsets dq (n <= 64) and, with ET, the exponential table
 // exp(-pi i j / m), j < 2m (dynamic LDS, 2m entries), are staged in LDS; 2m is
 // a power of two, so the phase index kt q mod 2m is a mask (kt q < 2^31 for
@@ -1518,22 +1525,16 @@ k_build_hq(float2* __restrict__ hq, int m, const int* __restrict__ dq,
       ai += w * gv.y;
     }
     const float2 v = make_float2((float)(ar * invZ), (float)(ai * invZ));
-    if constexpr (kHqLaneOrdered<LOGN>) {
-      // every image (+-kx, +-ky) of the quarter entry, at the register r,
-      // column and lane s of the plane kernel that multiplies by it: the
-      // frequency fx (fy) sits at the bit-reversed position p = 8r + s (col)
-      constexpr int L = 2 * N, LOGL = LOGN + 1;
-      float2* Hk = hq + (size_t)kt * L * L;
+    // every image (+-kx, +-ky) of the quarter entry, where the plane kernel
+    // multiplies by it (H^ is even in kx and ky)
+    constexpr int L = 2 * N;
+    float2* Hk = hq + (size_t)kt * L * L;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int fx = (e & 1) ? (L - kx) & (L - 1) : kx;
-        const int fy = (e & 2) ? (L - ky) & (L - 1) : ky;
-        if (((e & 1) && (kx == 0 || kx == N)) || ((e & 2) && (ky == 0 || ky == N))) continue;
-        const int p = brev(fx, LOGL), col = brev(fy, LOGL);
-        Hk[((p >> 3) * L + col) * 8 + (p & 7)] = v;
-      }
-    } else {
-      hq[(size_t)kt * N1 * N1 + (size_t)ky * N1 + kx] = v;
+    for (int e = 0; e < 4; ++e) {
+      const int fx = (e & 1) ? (L - kx) & (L - 1) : kx;
+      const int fy = (e & 2) ? (L - ky) & (L - 1) : ky;
+      if (((e & 1) && (kx == 0 || kx == N)) || ((e & 2) && (ky == 0 || ky == N))) continue;
+      Hk[hq_lane_index<LOGN>(fx, fy)] = v;
     }
   }
 }

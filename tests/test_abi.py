@@ -108,15 +108,13 @@ def test_workspace_bytes_grow_with_model_and_size():
     big = C.workspace_bytes(C.default_config(nx=64, ny=64, nt=512, model=C.MODEL_DUAL))
     V = 64 * 64 * 512
     # the dual model keeps 23 volume-sized fields (v, w and f are recomputed,
-    # not stored) plus the convolution spectrum (about 2) and H^, which for
-    # n <= 64 is the lane-ordered full 2n x 2n spectrum of every kt plane
-    # (about 8)
+    # not stored) plus the convolution spectrum (about 2) and H^, the
+    # lane-ordered full 2n x 2n spectrum of every kt plane (about 8)
     assert 23 * 4 * V < big < 34 * 4 * V
     assert big % 256 == 0
-    # n = 128 keeps the quarter spectrum (about 2)
     V3 = 128 * 128 * 1024
     big3 = C.workspace_bytes(C.default_config(nx=128, ny=128, nt=1024, model=C.MODEL_DUAL))
-    assert 23 * 4 * V3 < big3 < 28 * 4 * V3
+    assert 23 * 4 * V3 < big3 < 34 * 4 * V3
 
 
 def test_create_rejects_before_touching_the_device():
