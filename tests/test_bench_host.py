@@ -1,5 +1,7 @@
 """Host-side logic of the benchmark script: the image-quality measures of the
-curvature-function comparison (Table II's Accuracy, RMSE, PSNR and SSIM)."""
+curvature-function comparison (Table II's Accuracy, RMSE, PSNR and SSIM), the
+roofline figures (flop count, the source-hash gate on measured traffic) and
+the one-GPU limit."""
 import math
 
 import numpy as np
@@ -57,3 +59,50 @@ def test_trv_weights_meet_the_other_phis_at_zero_and_infinity():
         assert math.isclose(math.sqrt(t[a]), pr[a])
         kappa = 1e6
         assert math.isclose(math.sqrt(t[a] + t[b] * kappa ** 2), pr[b] * kappa, rel_tol=1e-6)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    """Only one GPU is used: --gpus 2 stops before any device call."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], cwd=bench.ROOT,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus_requested"] == 2 and "one GPU" in msg["error"]
+
+
+def test_traffic_is_used_only_for_the_sources_it_was_measured_on(monkeypatch):
+    """The counter file carries the hash of the kernel sources it was taken
+    with; any other hash, or another workload, gives no traffic figure."""
+    import json
+    import os
+    with open(os.path.join(bench.ROOT, "profiles", "pmc_traffic.json")) as fh:
+        d = json.load(fh)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: d["source_hash"])
+    got = bench.load_traffic("plane_conv", d["workload"])
+    assert got == d["kernels"]["plane_conv"]["bytes_per_launch"]
+    assert bench.load_traffic("plane_conv", "large" if d["workload"] != "large" else "medium") is None
+    assert bench.load_traffic("no_such_kernel", d["workload"]) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.load_traffic("plane_conv", d["workload"]) is None
+
+
+def test_plane_pass_flops_count_the_pruned_transforms():
+    """Flops of one convolution's plane pass, counted transform by transform:
+    per kt plane the padded 2n x 2n transform skips the n zero rows forward
+    and the n cropped rows inverse, so n row and 2n column transforms each
+    way, 5 L log2 L flops per length-L complex transform, plus 6 flops per
+    complex product at the (2n)^2 positions."""
+    for n, m in [(8, 16), (16, 128), (64, 512), (128, 1024)]:
+        L = 2 * n
+        stages = int(round(math.log2(L)))
+        per_transform = 0
+        for _ in range(stages):          # radix-2: L/2 butterflies of 10 flops per stage
+            per_transform += (L // 2) * 10
+        schedule = ["row"] * n + ["col"] * L + ["col"] * L + ["row"] * n
+        per_plane = len(schedule) * per_transform + 6 * L * L
+        assert bench.algorithmic_flops("plane_conv", n, m) == m * per_plane
+    assert bench.algorithmic_flops("plane_conv", 64, 512) == 931135488
+    assert bench.algorithmic_flops("post_u", 64, 512) == 0.0
