@@ -465,10 +465,12 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 // separates with the partner frequency -k (see plane_conv_cols_packed); the
 // result is conv(P_0) + i conv(P_m).
 // ---------------------------------------------------------------------------
+// YS: LDS row stride of the transposes; a pad of 2 entries measured faster
+// than 8 (fewer bank conflicts on the column accesses).
 template <int LOGN>
 struct PlaneRegCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 8 * N;
-  static constexpr int RE = L / 8, YS = L + 8;
+  static constexpr int RE = L / 8, YS = L + 2;
 };
 
 // forward column transform of a zero-padded column whose first n entries are
@@ -637,7 +639,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
 template <int LOGN>
 struct PlaneHalfCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 4 * N, G = NT / 8;
-  static constexpr int RN = N / 8, YS = N + 8;
+  static constexpr int RN = N / 8, YS = N + 2;   // row stride: pad 2 (as PlaneRegCfg)
 };
 
 // rows of the half-split plane kernel: forward n-point DIF of the two rows
@@ -775,10 +777,14 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
 }
 
 // Register-resident plane kernel of the diagonal solve (n <= 128): rows and
-// columns of length n by 8 lanes each, divide at the column step.
+// columns of length n by LN lanes each (16 at n = 64, so that a block has 16
+// waves to hide its phases' latencies; 8 otherwise), divide at the column step.
+// YS is the LDS row stride of the transpose: pads of 2 (n = 64) and 4
+// (n = 128) entries, the fastest of the pads measured.
 template <int LOGN>
 struct PlaneSolveCfg {
-  static constexpr int N = 1 << LOGN, NT = 8 * N, E = N / 8, YS = N + 8;
+  static constexpr int N = 1 << LOGN, LN = LOGN == 6 ? 16 : 8, NT = LN * N, E = N / LN,
+                       YS = N + (LOGN == 6 ? 2 : LOGN == 7 ? 4 : 8);
 };
 
 template <int LOGN>
@@ -788,7 +794,7 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
                   const double* c_dev, float c_val, float mu, const DevCtl* ctl, size_t zs,
                   int gate) {
   using PC = PlaneSolveCfg<LOGN>;
-  constexpr int N = PC::N, NT = PC::NT, E = PC::E, YS = PC::YS;
+  constexpr int N = PC::N, LN = PC::LN, NT = PC::NT, E = PC::E, YS = PC::YS;
   __shared__ float2 Y[N * YS];
   __shared__ float2 twc[N];
   __shared__ float sg[N];
@@ -808,14 +814,14 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
     sg[i] = sig_xy[i];
   }
   __syncthreads();
-  const int g = tid >> 3, s = tid & 7;
+  const int g = tid / LN, s = tid % LN;
   float2 x[E];
 #pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = P[g * N + 8 * r + s];
-  dif_inlane<8, E, E / 2>(x, s, twc);
-  dif_xlane<8, E>(x, s, twc);
+  for (int r = 0; r < E; ++r) x[r] = P[g * N + LN * r + s];
+  dif_inlane<LN, E, E / 2>(x, s, twc);
+  dif_xlane<LN, E>(x, s, twc);
 #pragma unroll
-  for (int r = 0; r < E; ++r) Y[g * YS + 8 * r + s] = x[r];
+  for (int r = 0; r < E; ++r) Y[g * YS + LN * r + s] = x[r];
   __syncthreads();
   const float c = c_dev ? (float)(*c_dev) : c_val;
   if (plane == 0) {
@@ -826,44 +832,44 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
     float2 xh[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const float2 a = Y[(8 * r + s) * YS + g];
-      const float2 d = Y[(8 * r + s) * YS + gp];
+      const float2 a = Y[(LN * r + s) * YS + g];
+      const float2 d = Y[(LN * r + s) * YS + gp];
       x[r] = make_float2(0.5f * (a.x + d.x), 0.5f * (a.y - d.y));
       xh[r] = make_float2(0.5f * (a.y + d.y), 0.5f * (d.x - a.x));
     }
     __syncthreads();                               // partners read before any write-back
-    dif_inlane<8, E, E / 2>(x, s, twc);
-    dif_xlane<8, E>(x, s, twc);
-    dif_inlane<8, E, E / 2>(xh, s, twc);
-    dif_xlane<8, E>(xh, s, twc);
+    dif_inlane<LN, E, E / 2>(x, s, twc);
+    dif_xlane<LN, E>(x, s, twc);
+    dif_inlane<LN, E, E / 2>(xh, s, twc);
+    dif_xlane<LN, E>(xh, s, twc);
     const float base0 = c + mu * (sig_t[0] + sg[brev(g, LOGN)]);
     const float baseh = c + mu * (sig_t[gridDim.x] + sg[brev(g, LOGN)]);
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const float sk = mu * sg[brev(8 * r + s, LOGN)];
+      const float sk = mu * sg[brev(LN * r + s, LOGN)];
       const float2 y0 = cscale(x[r], 1.f / (base0 + sk)), yh = cscale(xh[r], 1.f / (baseh + sk));
       x[r] = make_float2(y0.x - yh.y, y0.y + yh.x);
     }
   } else {
 #pragma unroll
-    for (int r = 0; r < E; ++r) x[r] = Y[(8 * r + s) * YS + g];
-    dif_inlane<8, E, E / 2>(x, s, twc);
-    dif_xlane<8, E>(x, s, twc);
+    for (int r = 0; r < E; ++r) x[r] = Y[(LN * r + s) * YS + g];
+    dif_inlane<LN, E, E / 2>(x, s, twc);
+    dif_xlane<LN, E>(x, s, twc);
     const float base = c + mu * (sig_t[plane] + sg[brev(g, LOGN)]);
 #pragma unroll
-    for (int r = 0; r < E; ++r) x[r] = cscale(x[r], 1.f / (base + mu * sg[brev(8 * r + s, LOGN)]));
+    for (int r = 0; r < E; ++r) x[r] = cscale(x[r], 1.f / (base + mu * sg[brev(LN * r + s, LOGN)]));
   }
-  dit_xlane<8, E>(x, s, twc);
-  dit_inlane<8, E, E / 2>(x, s, twc);
+  dit_xlane<LN, E>(x, s, twc);
+  dit_inlane<LN, E, E / 2>(x, s, twc);
 #pragma unroll
-  for (int r = 0; r < E; ++r) Y[(8 * r + s) * YS + g] = x[r];
+  for (int r = 0; r < E; ++r) Y[(LN * r + s) * YS + g] = x[r];
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = Y[g * YS + 8 * r + s];
-  dit_xlane<8, E>(x, s, twc);
-  dit_inlane<8, E, E / 2>(x, s, twc);
+  for (int r = 0; r < E; ++r) x[r] = Y[g * YS + LN * r + s];
+  dit_xlane<LN, E>(x, s, twc);
+  dit_inlane<LN, E, E / 2>(x, s, twc);
 #pragma unroll
-  for (int r = 0; r < E; ++r) P[g * N + 8 * r + s] = x[r];
+  for (int r = 0; r < E; ++r) P[g * N + LN * r + s] = x[r];
 }
 
 // ---------------------------------------------------------------------------
