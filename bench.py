@@ -8,7 +8,7 @@ backtracking, and reading the volume back.  The metric is voxel-ADMM-
 iterations per second (64*64*512 voxels x 250 iterations per step, divided by
 the step time), with reconstructions/s and the p50/p99 step latency.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -494,7 +494,7 @@ def cpu_baseline(sc, wl, cpu_iters):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
     import torch
