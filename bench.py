@@ -25,9 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
-# FP32 vector FMA issue rate without packed FP32 (the library is built with
-# packed FP32 disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop
+# (FMA) x 2 (packed or dual-issued FP32) x 2.4 GHz
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+# the same without the packed/dual-issue factor: the ceiling of this library,
+# which is built with packed FP32 disabled
+VALU_NONPACKED_TFLOPS = VALU_PEAK_TFLOPS / 2
 # kernels whose bound is the vector ALU (rocprofv3 SQ counters), reported
 # against VALU_PEAK_TFLOPS with their algorithmic flops
 ALU_BOUND = ("plane_conv",)
@@ -46,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--profile-all", action="store_true",
                     help="print per-kernel event times of one extra reconstruction to stderr")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the rates of the other single-scene workloads")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-one-at-a-time comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -373,18 +378,23 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000):
     }
 
 
+def hq_bytes(n, m, layout=False):
+    """Bytes of the kernel spectrum H^ per convolution: the quarter (n + 1)^2
+    of each kt plane that its evenness in kx and ky determines (the method's
+    own bytes), or the full 2n x 2n plane the plane kernel reads, lane-ordered
+    so that its loads coalesce (the layout's bytes)."""
+    return (m + 1) * (4 * n * n if layout else (n + 1) * (n + 1)) * 8
+
+
 def algorithmic_bytes(kind, n, m, dual):
     """Bytes a kernel kind must move per launch (inputs read once, outputs
     written once), averaged over its launches in one ADMM iteration."""
     V = n * n * m
     spec_c = (m + 1) * n * n * 8          # convolution spectrum, complex64
     spec_s = (m // 2 + 1) * n * n * 8     # solve spectrum
-    # kernel spectrum: the plane kernel reads each plane's full 2n x 2n
-    # spectrum, lane-ordered so that its loads coalesce
-    hq = (m + 1) * 4 * n * n * 8
     f = 4 * V
     if kind == "plane_conv":
-        return 2 * spec_c + hq
+        return 2 * spec_c + hq_bytes(n, m)
     if kind == "t_fwd_conv":       # the adjoint's first pass reads 3 volumes (the forward
         return spec_c + 3 * f      # operator's runs inside the u solve's last pass)
     if kind == "t_inv_conv":       # adjoint: with the u solve's first pass (reads ubar,
@@ -443,8 +453,9 @@ def load_traffic(kind, workload):
     return None if e is None else float(e["bytes_per_launch"])
 
 
-def cpu_baseline(sc, wl, cpu_iters):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(sc, wl, cpu_iters, single_worker=True):
+    """The FP64 oracle on a bounded sample of the same workload, with every
+    host core and (single_worker) again with one FFT worker."""
     from oracle import cnlos_oracle as O
     from paper_2301_00406_amd import scenes
     opL = O.make_operator(sc.n, sc.n, sc.m, sc.wall_w, sc.wall_h, sc.bin_ps, O.FALLOFF_LITERAL)
@@ -485,10 +496,137 @@ def cpu_baseline(sc, wl, cpu_iters):
         what = f"{cpu_iters} Algorithm-1 iteration(s)"
     dt = time.perf_counter() - t0
     V = sc.n * sc.n * sc.m
-    return {"value": V * cpu_iters / dt, "unit": "voxel-ADMM-iters/s", "cores": int(O.WORKERS),
-            "kind": "oracle",
-            "sample": f"{what} of the same {sc.n}x{sc.n}x{sc.m} scene, FP64 NumPy/SciPy FFT "
-                      f"with {O.WORKERS} workers, {dt:.1f} s"}
+    out = {"value": V * cpu_iters / dt, "unit": "voxel-ADMM-iters/s", "cores": int(O.WORKERS),
+           "kind": "oracle",
+           "sample": f"{what} of the same {sc.n}x{sc.n}x{sc.m} scene, FP64 NumPy/SciPy FFT "
+                     f"with {O.WORKERS} workers, {dt:.1f} s"}
+    if single_worker and wl["model"] == "dual":
+        workers = O.WORKERS
+        O.WORKERS = 1
+        try:
+            t0 = time.perf_counter()
+            O.alg2_step(s2, tau0, op.mask, fwd, adj, p)
+            d1 = time.perf_counter() - t0
+        finally:
+            O.WORKERS = workers
+        out["single_worker"] = {"value": V / d1, "cores": 1,
+                                "sample": f"the next Algorithm-2 iteration with one FFT worker, "
+                                          f"{d1:.1f} s"}
+    return out
+
+
+class Workload:
+    """One of the single-scene workloads, ready to be reconstructed again and
+    again: the scene, its measurement (the library's own literal-falloff
+    forward model + seeded Poisson noise, device-resident), the
+    configuration and one workspace."""
+
+    def __init__(self, torch, C, scenes, name):
+        wl = WORKLOADS[name]
+        self.torch, self.C, self.wl = torch, C, wl
+        sc = self.sc = getattr(scenes, wl["scene"])()
+        n, m = self.n, self.m = sc.n, sc.m
+        self.V = n * n * m
+        self.dual = wl["model"] == "dual"
+        self.iters_per_rec = wl["init"] + wl["iters"]
+        dev = self.dev = torch.device("cuda", 0)
+        op_cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
+                                  bin_ps=sc.bin_ps, model=C.MODEL_OPERATOR,
+                                  falloff=C.FALLOFF_LITERAL)
+        opP = C.Problem(op_cfg, np.ones((n, n), np.uint8), device=dev)
+        clean = opP.apply_A(torch.tensor(sc.u_true.astype(np.float32), device=dev))
+        raw_np = scenes.poisson_counts(clean.double().cpu().numpy(), sc.peak, sc.background,
+                                       np.random.Generator(np.random.PCG64(sc.seed)))
+        opP.close()
+        self.raw = torch.tensor(raw_np.astype(np.float32), device=dev)
+        self.cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
+                                    bin_ps=sc.bin_ps,
+                                    model=C.MODEL_DUAL if self.dual else C.MODEL_OBJECT,
+                                    max_iters=wl["iters"], init_iters=wl["init"], **wl["params"])
+        self.ws = torch.empty(C.workspace_bytes(self.cfg), dtype=torch.uint8, device=dev)
+        self.out = torch.empty((n, n, m), dtype=torch.float32, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+
+    def reconstruct(self, kinds=None, loop_events=None, stage_events=None):
+        """create + set_measurement + run + read volume.  loop_events: two
+        events around the run; stage_events: three, around the warm-start and
+        Algorithm-2 stages (two run calls)."""
+        C, st = self.C, self.stream
+        P = C.Problem(self.cfg, self.sc.mask, device=self.dev, stream=st, workspace=self.ws)
+        if kinds:
+            P.profile_enable(kinds)
+        P.set_measurement(self.raw)
+        if loop_events is not None:
+            loop_events[0].record(st)
+        if stage_events is not None:
+            stage_events[0].record(st)
+            P.run(self.wl["init"])
+            stage_events[1].record(st)
+            rep = P.run()
+            stage_events[2].record(st)
+        else:
+            rep = P.run()
+        if loop_events is not None:
+            loop_events[1].record(st)
+        self.out.copy_(P.volume())
+        prof = P.profile_read() if kinds else None
+        P.close()
+        return rep, prof
+
+    def timed(self, steps):
+        """Whole reconstructions, wall time each, and the run's event time."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        lat, loop_ms = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            self.reconstruct(loop_events=ev)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - ts) * 1e3)
+            loop_ms.append(ev[0].elapsed_time(ev[1]))
+        total_s = time.perf_counter() - t0
+        return total_s, lat, loop_ms
+
+    def stage_split(self):
+        """Iteration rates of the two stages (dual model) from one more
+        reconstruction with events between them."""
+        torch = self.torch
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        self.reconstruct(stage_events=ev)
+        torch.cuda.synchronize()
+        a1, a2 = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        i1, i2 = self.wl["init"], self.wl["iters"]
+        out = {"algorithm2_ms": a2, "algorithm2_iterations": i2,
+               "algorithm2_voxel_iters_per_s": self.V * i2 / (a2 * 1e-3)}
+        if i1:
+            out.update({"algorithm1_warm_start_ms": a1, "algorithm1_iterations": i1,
+                        "algorithm1_voxel_iters_per_s": self.V * i1 / (a1 * 1e-3)})
+        return out
+
+    def summary(self, steps, warmup):
+        """Rates of this workload alone (no roofline): the other configurations."""
+        for _ in range(max(warmup, 1)):
+            self.reconstruct()
+        total_s, lat, loop_ms = self.timed(steps)
+        ms = total_s * 1e3 / steps
+        loop = float(np.median(loop_ms))
+        sc = self.sc
+        out = {"workload": f"{self.n}x{self.n}x{self.m} "
+                           f"{'dual-domain (Algorithm 2)' if self.dual else 'object-domain (Algorithm 1)'}, "
+                           f"{int(sc.mask.sum())}/{self.n * self.n} scan points, "
+                           f"{self.wl['init']} warm-start + {self.wl['iters']} iterations",
+               "steps": steps, "ms_per_reconstruction": ms,
+               "reconstructions_per_s": 1e3 / ms,
+               "voxel_iters_per_s": self.V * self.iters_per_rec / (ms * 1e-3),
+               "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                              "p99": float(np.percentile(lat, 99))},
+               "iteration_loop_ms": loop,
+               "iteration_loop_voxel_iters_per_s": self.V * self.iters_per_rec / (loop * 1e-3)}
+        if self.dual:
+            out["stages"] = self.stage_split()
+        return out
 
 
 def main():
@@ -547,47 +685,9 @@ def main():
                           "data": "synthetic (seeded scenes, Poisson noise)", "ablation": ab}))
         return
     wl = WORKLOADS[args.workload]
-    sc = getattr(scenes, wl["scene"])()
-    n, m = sc.n, sc.m
-    V = n * n * m
-    dual = wl["model"] == "dual"
-    iters_per_rec = wl["init"] + wl["iters"]
-    dev = torch.device("cuda", 0)
-
-    # measurement: the library's own literal-falloff forward model + seeded Poisson noise
-    op_cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
-                              bin_ps=sc.bin_ps, model=C.MODEL_OPERATOR,
-                              falloff=C.FALLOFF_LITERAL)
-    full = np.ones((n, n), np.uint8)
-    opP = C.Problem(op_cfg, full, device=dev)
-    clean = opP.apply_A(torch.tensor(sc.u_true.astype(np.float32), device=dev))
-    raw_np = scenes.poisson_counts(clean.double().cpu().numpy(), sc.peak, sc.background,
-                                   np.random.Generator(np.random.PCG64(sc.seed)))
-    opP.close()
-    raw = torch.tensor(raw_np.astype(np.float32), device=dev)
-
-    cfg = C.default_config(nx=n, ny=n, nt=m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
-                           bin_ps=sc.bin_ps,
-                           model=C.MODEL_DUAL if dual else C.MODEL_OBJECT,
-                           max_iters=wl["iters"], init_iters=wl["init"], **wl["params"])
-    ws = torch.empty(C.workspace_bytes(cfg), dtype=torch.uint8, device=dev)
-    out = torch.empty((n, n, m), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
-
-    def reconstruct(kinds=None, loop_events=None):
-        P = C.Problem(cfg, sc.mask, device=dev, stream=stream, workspace=ws)
-        if kinds:
-            P.profile_enable(kinds)
-        P.set_measurement(raw)
-        if loop_events is not None:
-            loop_events[0].record(stream)
-        rep = P.run()
-        if loop_events is not None:
-            loop_events[1].record(stream)
-        out.copy_(P.volume())
-        prof = P.profile_read() if kinds else None
-        P.close()
-        return rep, prof
+    W = Workload(torch, C, scenes, args.workload)
+    sc, n, m, V, dual, iters_per_rec = W.sc, W.n, W.m, W.V, W.dual, W.iters_per_rec
+    reconstruct = W.reconstruct
 
     for _ in range(max(args.warmup, 1)):
         rep, _ = reconstruct()
@@ -629,11 +729,17 @@ def main():
     traffic = load_traffic(dominant, args.workload)
     if dominant in ALU_BOUND:
         aflops = algorithmic_flops(dominant, n, m)
+        achieved = aflops / (avg_us * 1e-6) / 1e12
+        layout_bytes = abytes - hq_bytes(n, m) + hq_bytes(n, m, layout=True)
         roof = {"bound": "alu", "kernel": dominant,
-                "achieved": aflops / (avg_us * 1e-6) / 1e12, "peak": VALU_PEAK_TFLOPS,
+                "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "traffic": traffic, "avg_launch_us": avg_us,
+                "peak_nonpacked": VALU_NONPACKED_TFLOPS,
+                "frac_nonpacked": achieved / VALU_NONPACKED_TFLOPS,
                 "algorithmic_flops_per_launch": aflops,
                 "algorithmic_bytes_per_launch": abytes,
+                "layout_bytes_per_launch": layout_bytes,
+                "layout_over_algorithmic_bytes": layout_bytes / abytes,
                 "hbm_GBs": abytes / (avg_us * 1e-6) / 1e9}
     else:
         roof = {"bound": "hbm", "kernel": dominant,
@@ -667,10 +773,18 @@ def main():
         "iteration_loop": {
             "ms_per_reconstruction": float(np.median(loop_ms)),
             "voxel_iters_per_s": V * iters_per_rec / (float(np.median(loop_ms)) * 1e-3),
+            **(W.stage_split() if dual else {}),
         },
         "roofline": roof,
         "context": {"paper_titan_rtx_alg2_seconds_64x64x512": 15.0},
     }
+    if not args.no_other_workloads:
+        # the other single-scene configurations, rates only
+        result["other_workloads"] = {}
+        for name, steps in (("small", 20), ("large", 2)):
+            if name != args.workload:
+                result["other_workloads"][name] = Workload(torch, C, scenes, name).summary(steps, 1)
+                torch.cuda.empty_cache()
     if not args.no_batch:
         result["batched"] = batched_comparison(torch, C, scenes, MIX_SMALL)
     if not args.no_cpu_baseline:

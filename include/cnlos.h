@@ -102,7 +102,9 @@ typedef struct cnlos_config {
   double L0_dual;             /* dual model: Algorithm-2 step constant; <= 0: 2 * estimate of ||A||^2 */
   double bt_factor;           /* L <- bt_factor * L on rejection (> 1)                         */
   int32_t power_iters;        /* power-iteration steps for the estimate (from the ones vector) */
-  int32_t reserved0;
+  int32_t fista_restart;      /* 0: the extrapolation exactly as Algorithms 1-2 print it (default);
+                                 1: also restart it (t = 1) after an energy rise of more than a
+                                 relative 1e-3 (function-value restart, O'Donoghue-Candes)      */
 } cnlos_config;
 
 /* Fields of the ADMM state, for checkpoint/resume and inspection.
@@ -118,7 +120,7 @@ typedef enum {
   CNLOS_FIELD_TAU0 = 7,     /* normalized measurement (read-only)           */
   CNLOS_FIELD_TAU = 8,      /* dual model: tau^k                            */
   CNLOS_FIELD_TAUBAR = 9,   /* dual model: extrapolated taubar^k            */
-  CNLOS_FIELD_W = 10,       /* dual model: next w (derived, read-only)      */
+  CNLOS_FIELD_W = 10,       /* dual model: next w (derived from tau, read-only) */
   CNLOS_FIELD_LAM2 = 11,    /* dual model: Lambda_2                         */
   CNLOS_FIELD_F = 12,       /* dual model: next f (derived, read-only)      */
   CNLOS_FIELD_LAM3 = 13,    /* dual model: Lambda_3                         */
@@ -163,7 +165,7 @@ const char* cnlos_version(void);
  * full-sampling comparison of Section 5.2.1), mu1..3 = 1, 800, 2 (Section
  * 5.1), lambda = 200, eta = 1e-3, 50 iterations, 50 warm-start iterations,
  * eps = 0, backtracking on with factor 2 and 20 trials, L0 from 15 power
- * iterations.  cfg must not be NULL. */
+ * iterations, the printed FISTA step (no restart).  cfg must not be NULL. */
 void cnlos_config_default(cnlos_config* cfg);
 
 /* Check a configuration (and, if mask_host is not NULL, the mask: at least one
@@ -206,10 +208,12 @@ cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev
  * warm-start iterations of the dual model), iters <= 0 runs to completion
  * (max_iters, plus init_iters for the dual model).  Resumable: two calls of
  * T1 and T2 iterations equal one call of T1 + T2.  A trial step that fails the
- * backtracking test is repeated with L * bt_factor; when an accepted iterate's
- * energy exceeds the previous one by more than a relative 1e-3, the FISTA
- * sequence restarts (t = 1).  Stops early when eps_stop > 0 and the relative
- * energy change falls to eps_stop.  Requires a measurement.  Fills *out if it
+ * backtracking test is repeated with L * bt_factor.  With fista_restart = 1,
+ * when an accepted iterate's energy exceeds the previous one by more than a
+ * relative 1e-3 the FISTA sequence restarts (t = 1).  Algorithm 2's splitting
+ * steps of the signal (w and f) start from the last accepted tau; the
+ * extrapolated taubar is the data of its linearized u-step.  Stops early when
+ * eps_stop > 0 and the relative energy change falls to eps_stop.  Requires a measurement.  Fills *out if it
  * is not NULL.  Synchronizes the stream. */
 cnlos_status cnlos_run(cnlos_problem* p, int32_t iters, cnlos_report* out);
 
@@ -226,7 +230,7 @@ cnlos_status cnlos_get_signal(cnlos_problem* p, float* tau_dev);
 /* Copy a state field out / in (checkpoint and resume).  Sizes per cnlos_field
  * (V, LAM, W and LAM2 hold 3 volumes).  The splitting variables v, w and f are
  * not stored: reading them computes the values the next iteration will use
- * from ubar, Lambda, phi (taubar, Lambda2, phi_tau; taubar, Lambda3, tau0),
+ * from ubar, Lambda, phi (tau, Lambda2, phi_tau; tau, Lambda3, tau0),
  * so they are read-only, like TAU0; restoring the other fields restores them.
  * Dual-model fields need the dual model.  Asynchronous. */
 cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev);
@@ -300,7 +304,7 @@ const char* cnlos_last_error(void);
  * b_u, a_tau, b_tau, warm_a, warm_b, the penalties mu, mu1, mu2, mu3, lambda,
  * eta_curv and backtracking; they may differ in the wall extent, bin width,
  * mask, measurement, max_iters, init_iters, eps_stop, bt_factor,
- * bt_max_trials, L0, L0_dual and power_iters.
+ * bt_max_trials, L0, L0_dual, power_iters and fista_restart.
  * ------------------------------------------------------------------------ */
 typedef struct cnlos_batch cnlos_batch;   /* opaque */
 
@@ -384,6 +388,12 @@ cnlos_status cnlos_server_submit(cnlos_server* s, const cnlos_request* r);
  * receive the number of requests in slots and waiting after the step.
  * Synchronizes every group stream. */
 cnlos_status cnlos_server_step(cnlos_server* s, int32_t* active, int32_t* queued);
+
+/* Testing hook for failure handling: the next `count` slot-group creations
+ * fail with CNLOS_EHIP after the group's arena range, stream and host objects
+ * exist (they are released again), before any device work.  The request that
+ * needed the group completes with that status; the others are unaffected. */
+cnlos_status cnlos_server_fail_next_groups(cnlos_server* s, int32_t count);
 
 /* Completions since the last poll (up to cap; *n receives the count). */
 cnlos_status cnlos_server_poll(cnlos_server* s, cnlos_completion* out, int32_t cap, int32_t* n);

@@ -32,7 +32,17 @@ their reasons in the design notes):
 * backtracking (named in the abstract, not defined): Beck-Teboulle on the
   linearized data term, factor bt_factor, L never decreases.
 * Alg. 2 sub-problems (Section 4.1 gives only the Lagrangian): closed forms
-  derived from it, solved in the order v, w, f, u, tau, multipliers.
+  derived from it, solved in the order v, w, f, u, tau, multipliers.  The
+  extrapolated signal taubar is the data of the linearized u-step; the
+  signal-domain splitting steps (w, f) start from the last accepted tau.
+  Taking w and f at taubar as well makes the printed iteration unstable: the
+  w-step then leaves Lambda2 = mu2 grad(taubar - tau+), the extrapolation's
+  step scaled by mu2 (800 in Section 5.1), and the energy of eq. (13) grows
+  without bound on synthetic scenes (the oracle keeps that reading behind
+  ``Params.tau_split_at_bar`` to show it).
+* FISTA (Algorithms 1-2): the printed extrapolation by default; a
+  function-value restart (O'Donoghue and Candes) is available as an option
+  (``Params.fista_restart``).
 """
 from __future__ import annotations
 
@@ -268,12 +278,10 @@ def tv_weighted(u: np.ndarray, phi: np.ndarray) -> float:
     return float((phi * np.sqrt((g * g).sum(axis=0))).sum())
 
 
-# Momentum restart.  The paper reports a steadily decaying energy for both
-# algorithms (energy-decay figure, Section 5); with the plain FISTA
-# extrapolation inside the ADMM iteration the dual-domain energy grows without
-# bound on synthetic scenes.  Reading: restart the extrapolation sequence
-# (t = 1, so the next extrapolation weight is 0) whenever the energy of an
-# accepted iterate exceeds the previous one by more than RESTART_TOL
+# Optional momentum restart (not part of Algorithms 1-2, which print the plain
+# extrapolation; enabled by Params.fista_restart): restart the extrapolation
+# sequence (t = 1, so the next extrapolation weight is 0) whenever the energy
+# of an accepted iterate exceeds the previous one by more than RESTART_TOL
 # (function-value restart, O'Donoghue and Candes 2015).  The tolerance keeps
 # the decision away from round-off ties.
 RESTART_TOL = 1e-3
@@ -338,6 +346,8 @@ class Params:
     bt_max_trials: int = 20
     eps: float = 0.0             # 0 = fixed iteration count
     power_iters: int = 15
+    fista_restart: bool = False  # True: function-value restart; False: the printed step
+    tau_split_at_bar: bool = False  # Alg. 2: w, f from taubar (the unstable reading)
     # Algorithm 2 (a, b, mu above drive Algorithm 1 and the warm start)
     a_u: float = 5e-4
     b_u: float = 5e-5
@@ -431,7 +441,8 @@ def alg1_step(st: Alg1State, tau0: np.ndarray, fwd: Callable, adj: Callable, p: 
     dual = mu * math.sqrt(float((gd * gd).sum()))
     rel = abs(st.E_prev - E) / abs(E) if np.isfinite(st.E_prev) and E != 0 else float("inf")
     st.log.append((E, primal, dual, st.L, trials, rel))
-    momentum_restart(st, E)
+    if p.fista_restart:
+        momentum_restart(st, E)
     st.E_prev = E
     st.k += 1
 
@@ -496,12 +507,13 @@ def alg2_step(st: Alg2State, tau0: np.ndarray, mask: np.ndarray, fwd: Callable,
     unmasked A and A^T; mask selects the measured scan points."""
     mu1, mu2, mu3, lam = p.mu1, p.mu2, p.mu3, p.lam
     D = np.asarray(mask, dtype=np.float64)[:, :, None] * np.ones_like(tau0)
-    # v and w: weighted shrinkage on both gradients
+    # v and w: weighted shrinkage on both gradients; the signal-domain
+    # splitting steps (w, f) start from the last accepted tau
+    ts = st.taubar if p.tau_split_at_bar else st.tau
     st.v = shrink(grad(st.ubar) - st.Lam1 / mu1, st.phi_u / mu1)
-    st.w = shrink(grad(st.taubar) - st.Lam2 / mu2, st.phi_tau / mu2)
+    st.w = shrink(grad(ts) - st.Lam2 / mu2, st.phi_tau / mu2)
     # f: pointwise minimizer of lam/2 |f - tau0|^2_D + <Lam3, f - tau> + mu3/2 |f - tau|^2
-    st.f = np.where(D > 0, (lam * tau0 + mu3 * st.taubar - st.Lam3) / (lam + mu3),
-                    st.taubar - st.Lam3 / mu3)
+    st.f = np.where(D > 0, (lam * tau0 + mu3 * ts - st.Lam3) / (lam + mu3), ts - st.Lam3 / mu3)
     # u: linearized data term 1/2 |A u - taubar|^2 at ubar, FFT solve
     r = fwd(st.ubar) - st.taubar
     gf = adj(r)
@@ -545,7 +557,8 @@ def alg2_step(st: Alg2State, tau0: np.ndarray, mask: np.ndarray, fwd: Callable,
     dual = mu1 * math.sqrt(float((gd * gd).sum()))
     rel = abs(st.E_prev - E) / abs(E) if np.isfinite(st.E_prev) and E != 0 else float("inf")
     st.log.append((E, primal, dual, st.L, trials, rel))
-    momentum_restart(st, E)
+    if p.fista_restart:
+        momentum_restart(st, E)
     st.E_prev = E
     st.k += 1
 

@@ -42,7 +42,7 @@ class Config(ctypes.Structure):
         ("eps_stop", c_double),
         ("backtracking", c_int32), ("bt_max_trials", c_int32),
         ("L0", c_double), ("L0_dual", c_double), ("bt_factor", c_double),
-        ("power_iters", c_int32), ("reserved0", c_int32),
+        ("power_iters", c_int32), ("fista_restart", c_int32),
     ]
 
 
@@ -122,6 +122,7 @@ def load() -> ctypes.CDLL:
         "cnlos_server_submit": ([P, POINTER(Request)], c_int32),
         "cnlos_server_step": ([P, POINTER(c_int32), POINTER(c_int32)], c_int32),
         "cnlos_server_poll": ([P, POINTER(Completion), c_int32, POINTER(c_int32)], c_int32),
+        "cnlos_server_fail_next_groups": ([P, c_int32], c_int32),
         "cnlos_server_usage": ([P, POINTER(c_uint64), POINTER(c_int32)], c_int32),
         "cnlos_server_destroy": ([P], c_int32),
     }
@@ -456,6 +457,10 @@ class Server:
             out.append({f: getattr(c, f) for f, _ in Completion._fields_})
             self._keep.pop(int(c.id), None)
         return out
+
+    def fail_next_groups(self, count):
+        """Testing hook: the next ``count`` slot-group creations fail."""
+        check(self._lib.cnlos_server_fail_next_groups(self._h, int(count)))
 
     def usage(self):
         b, g = c_uint64(), c_int32()

@@ -136,6 +136,7 @@ struct cnlos_server {
   Arena arena;
   int K = 8, rounds = 8;
   long long step_no = 0;
+  int fail_next_groups = 0;   // test hook: slot-group creations to fail on purpose
   std::vector<SrvReq> queue;
   std::vector<SrvGroup*> groups;
   std::vector<cnlos_completion> done;
@@ -365,6 +366,7 @@ cnlos_status validate_cfg(const cnlos_config* c) {
   if (!(isfinite(c->bt_factor) && c->bt_factor > 1.0)) return fail(CNLOS_EINVAL, "bt_factor must be > 1");
   if (c->bt_max_trials < 0) return fail(CNLOS_EINVAL, "bt_max_trials must be >= 0");
   if (!isfinite(c->L0) || !isfinite(c->L0_dual)) return fail(CNLOS_EINVAL, "L0, L0_dual must be finite");
+  if (c->fista_restart != 0 && c->fista_restart != 1) return fail(CNLOS_EINVAL, "fista_restart must be 0 or 1");
   if ((c->L0 <= 0.0 || (c->model == CNLOS_MODEL_DUAL && c->L0_dual <= 0.0)) && c->power_iters < 1)
     return fail(CNLOS_EINVAL, "power_iters must be >= 1 when a step constant is estimated");
   if (c->model == CNLOS_MODEL_DUAL) {
@@ -683,7 +685,7 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     // post kernel takes (a rejected trial's tau is recomputed in the next slot)
     RhsSrc rt;
     rt.mode = RHS_TAU;
-    rt.xb = role(R_TB_CUR);
+    rt.xb = role(R_T_CUR);   // w and f start from the last accepted tau
     rt.au = role(R_AU_TR);
     rt.lam = p->lam2;
     rt.phi = p->phi_tau;
@@ -704,7 +706,7 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
                         gated(G), p->st, &p->prof, false, true));
     const PostArgs pu{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu1, phi_args(p, 2, false)};
-    const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_TB_CUR), role(R_TB_NEW), p->lam2,
+    const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_T_CUR), role(R_TB_NEW), p->lam2,
                       p->phi_tau, (float)mu2, phi_args(p, 2, true)};
     const CheckArgs ck{p->nb_conv, p->nb_step, c.backtracking ? 1 : 0};
     TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->lam3, mu3, lam, role(R_AU_TR), p->tau0,
@@ -982,6 +984,7 @@ void cnlos_config_default(cnlos_config* c) {
   c->L0_dual = 0.0;
   c->bt_factor = 2.0;
   c->power_iters = 15;
+  c->fista_restart = 0;
 }
 
 cnlos_status cnlos_validate(const cnlos_config* cfg, const uint8_t* mask_host) {
@@ -1013,44 +1016,31 @@ cnlos_status cnlos_create(const cnlos_config* cfg, const uint8_t* mask_host, voi
 
 namespace {
 
-cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
-                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
-  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
-  cnlos_status s = cnlos_validate(cfg, mask_host);
-  if (s != CNLOS_OK) return s;
-  const size_t need = carve(nullptr, *cfg, nullptr);
-  if (!workspace_dev) return fail(CNLOS_EINVAL, "workspace is NULL");
-  if (((uintptr_t)workspace_dev) % kAlign) return fail(CNLOS_EINVAL, "workspace must be 256-byte aligned");
-  if (workspace_bytes < need)
-    return fail(CNLOS_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
-
-  cnlos_problem* p = new (std::nothrow) cnlos_problem();
-  if (!p) return fail(CNLOS_ENOMEM, "host allocation failed");
-  p->cfg = *cfg;
-  p->logn = ilog2(cfg->nx);
-  p->logm = ilog2(cfg->nt);
-  const int n = cfg->nx, m = cfg->nt;
-  p->V = (size_t)n * n * m;
-  p->nn = n * n;
-  p->st = (hipStream_t)hip_stream;
-  p->ws = (uint8_t*)workspace_dev;
-  p->ws_bytes = workspace_bytes;
-  p->carve_bytes = carve(p, *cfg, p->ws);
+// Sizes, buffer addresses and launch geometry of a problem whose workspace
+// starts at ws.
+void layout_problem(cnlos_problem* p, const cnlos_config& cfg, uint8_t* ws, uint64_t ws_bytes,
+                    hipStream_t st) {
+  p->cfg = cfg;
+  p->logn = ilog2(cfg.nx);
+  p->logm = ilog2(cfg.nt);
+  p->V = (size_t)cfg.nx * cfg.nx * cfg.nt;
+  p->nn = cfg.nx * cfg.nx;
+  p->st = st;
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  p->carve_bytes = carve(p, cfg, ws);
   p->nb_conv = conv_blocks(p->logn, p->logm);
   p->nb_solve = solve_blocks(p->logn, p->logm);
   p->nb_step = fused_solve_blocks(p->logn, p->logm);
   p->nb_sten = stencil_blocks(p->logn, p->logm);
-  *out = p;   // from here on errors leave a handle the caller must destroy
+}
 
-  if (hipHostMalloc((void**)&p->ctl_host, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) {
-    p->ctl_host = nullptr;
-    p->poisoned = true;
-    return fail(CNLOS_EHIP, "pinned host allocation failed");
-  }
-  memset(p->ctl_host, 0, sizeof(DevCtl));
-
+// Operator tables of a problem laid out by carve(): twiddles, the R_z
+// resampling table (eq. (3)), falloff and compensation weights, difference-
+// operator symbols (eq. (11)), the mask, and H^ built on the device from the
+// cone kernel's support.  Waits for the copies before the host tables go.
+cnlos_status build_tables(cnlos_problem* p, const cnlos_config* cfg, const uint8_t* mask_host) {
+  const int n = cfg->nx, m = cfg->nt;
   // ---------------- host tables (FP64) ----------------
   const double PI = 3.14159265358979323846;
   std::vector<float2> tw_t(m), tw_xy(n);
@@ -1192,6 +1182,37 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
   p->tb.sig_xy = p->sig_xy;
   p->tb.sig_t = p->sig_t;
   p->tb.hq = p->hq;
+  HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
+                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
+  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
+  cnlos_status s = cnlos_validate(cfg, mask_host);
+  if (s != CNLOS_OK) return s;
+  const size_t need = carve(nullptr, *cfg, nullptr);
+  if (!workspace_dev) return fail(CNLOS_EINVAL, "workspace is NULL");
+  if (((uintptr_t)workspace_dev) % kAlign) return fail(CNLOS_EINVAL, "workspace must be 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(CNLOS_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+
+  cnlos_problem* p = new (std::nothrow) cnlos_problem();
+  if (!p) return fail(CNLOS_ENOMEM, "host allocation failed");
+  layout_problem(p, *cfg, (uint8_t*)workspace_dev, workspace_bytes, (hipStream_t)hip_stream);
+  *out = p;   // from here on errors leave a handle the caller must destroy
+
+  if (hipHostMalloc((void**)&p->ctl_host, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) {
+    p->ctl_host = nullptr;
+    p->poisoned = true;
+    return fail(CNLOS_EHIP, "pinned host allocation failed");
+  }
+  memset(p->ctl_host, 0, sizeof(DevCtl));
+
+  s = build_tables(p, cfg, mask_host);
+  if (s != CNLOS_OK) return s;
 
   DevCtl& c = *p->ctl_host;
   memset(&c, 0, sizeof(c));
@@ -1202,6 +1223,7 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
   c.bt_max_trials = cfg->bt_max_trials;
   c.bt_factor = cfg->bt_factor;
   c.eps_stop = cfg->eps_stop;
+  c.restart_tol = cfg->fista_restart ? kRestartTol : 0.0;
   c.lambda = cfg->lambda;
   c.meas_scale = 0.0;
   s = ctl_push(p);   // also waits for the tables and H^
@@ -1333,12 +1355,12 @@ cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev) {
     return CNLOS_OK;
   }
   if (dual && field == CNLOS_FIELD_W) {
-    HIPCHK(launch_vstep(p->logn, p->logm, p->TB[h.slot[R_TB_CUR]], p->lam2, p->phi_tau, dst_dev,
+    HIPCHK(launch_vstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam2, p->phi_tau, dst_dev,
                         p->cfg.mu2, p->st));
     return CNLOS_OK;
   }
   if (dual && field == CNLOS_FIELD_F) {
-    HIPCHK(launch_fstep(p->logn, p->logm, p->TB[h.slot[R_TB_CUR]], p->lam3, p->tau0, p->mask,
+    HIPCHK(launch_fstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam3, p->tau0, p->mask,
                         dst_dev, p->cfg.lambda, p->cfg.mu3, p->st));
     return CNLOS_OK;
   }
@@ -1565,6 +1587,7 @@ cnlos_status cnlos_batch_destroy(cnlos_batch* b) {
 namespace {
 
 cnlos_status srv_fail(cnlos_status st, const std::string& msg) { return fail(st, msg); }
+void srv_group_free(cnlos_server* sv, SrvGroup* g);
 
 // a group's device state starts parked: every slot's controller halted
 cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup** out) {
@@ -1593,19 +1616,7 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
     return srv_fail(CNLOS_EHIP, "stream creation failed");
   }
   uint8_t* ws = sv->arena.base + off;
-  p->cfg = cfg;
-  p->logn = ilog2(cfg.nx);
-  p->logm = ilog2(cfg.nt);
-  p->V = (size_t)cfg.nx * cfg.nx * cfg.nt;
-  p->nn = cfg.nx * cfg.nx;
-  p->st = g->st;
-  p->ws = ws;
-  p->ws_bytes = stride;
-  p->carve_bytes = carve(p, cfg, ws);
-  p->nb_conv = conv_blocks(p->logn, p->logm);
-  p->nb_solve = solve_blocks(p->logn, p->logm);
-  p->nb_step = fused_solve_blocks(p->logn, p->logm);
-  p->nb_sten = stencil_blocks(p->logn, p->logm);
+  layout_problem(p, cfg, ws, stride, g->st);
   p->tb.tw_t = p->tw_t;
   p->tb.tw_xy = p->tw_xy;
   p->tb.twc_t = p->twc_t;
@@ -1618,14 +1629,26 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
   p->tb.sig_t = p->sig_t;
   p->tb.hq = p->hq;
   g->layout = p;
+  // from here on a failure gives back the arena range, the stream and the
+  // host objects (srv_group_free on a group that is not yet listed)
+  if (sv->fail_next_groups > 0) {
+    --sv->fail_next_groups;
+    srv_group_free(sv, g);
+    return srv_fail(CNLOS_EHIP, "slot-group creation failed (injected by the test hook)");
+  }
   DevCtl parked;
   memset(&parked, 0, sizeof(parked));
   parked.halt = 1;
   for (int i = 0; i < g->K; ++i)
     if (hipMemcpyAsync(ws + (size_t)i * stride, &parked, sizeof(DevCtl), hipMemcpyHostToDevice,
-                       g->st) != hipSuccess)
+                       g->st) != hipSuccess) {
+      srv_group_free(sv, g);
       return srv_fail(CNLOS_EHIP, "controller initialization failed");
-  if (hipStreamSynchronize(g->st) != hipSuccess) return srv_fail(CNLOS_EHIP, "stream failed");
+    }
+  if (hipStreamSynchronize(g->st) != hipSuccess) {
+    srv_group_free(sv, g);
+    return srv_fail(CNLOS_EHIP, "stream failed");
+  }
   sv->groups.push_back(g);
   *out = g;
   return CNLOS_OK;
@@ -1641,6 +1664,16 @@ void srv_group_free(cnlos_server* sv, SrvGroup* g) {
   delete g->layout;
   sv->arena.give(g->off, (uint64_t)g->stride * g->K);
   delete g;
+}
+
+// a request that never reached a slot: its one completion carries the error
+void srv_reject(cnlos_server* sv, const SrvReq& q, cnlos_status st) {
+  cnlos_completion c{};
+  c.id = q.r.id;
+  c.status = st;
+  c.energy = NAN;
+  c.queued_steps = (double)(sv->step_no - q.submitted);
+  sv->done.push_back(c);
 }
 
 void srv_complete(cnlos_server* sv, SrvGroup* g, int i, cnlos_status st) {
@@ -1731,9 +1764,13 @@ cnlos_status cnlos_server_submit(cnlos_server* sv, const cnlos_request* r) {
 
 cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queued) {
   if (!sv) return fail(CNLOS_EINVAL, "server is NULL");
-  // admission, first come first served within each shape
-  std::vector<SrvReq> wait;
-  for (SrvReq& q : sv->queue) {
+  // admission, first come first served within each shape.  The queue is
+  // rebuilt from the requests that keep waiting, so no exit path leaves an
+  // admitted or moved-from request in it, and every request gets exactly one
+  // completion.
+  std::vector<SrvReq> pending;
+  pending.swap(sv->queue);
+  for (SrvReq& q : pending) {
     SrvGroup* g = nullptr;
     int free_slot = -1;
     for (SrvGroup* c : sv->groups) {
@@ -1760,15 +1797,18 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
         st = srv_group_new(sv, q.r.cfg, &g);
       }
       if (st == CNLOS_ENOMEM && !g) {
-        wait.push_back(std::move(q));
+        sv->queue.push_back(std::move(q));
         continue;
       }
-      if (st != CNLOS_OK) return st;
+      if (st != CNLOS_OK) {
+        // this request fails (its group could not be made); the others go on
+        srv_reject(sv, q, st);
+        continue;
+      }
       free_slot = 0;
     }
     srv_admit(sv, g, free_slot, q);
   }
-  sv->queue.swap(wait);
   // advance every group with occupants; all groups are enqueued before any wait
   std::vector<Group> views(sv->groups.size());
   std::vector<std::vector<SceneRun>> runs(sv->groups.size());
@@ -1817,6 +1857,12 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
   }
   if (active) *active = act;
   if (queued) *queued = (int32_t)sv->queue.size();
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_server_fail_next_groups(cnlos_server* sv, int32_t count) {
+  if (!sv || count < 0) return fail(CNLOS_EINVAL, "NULL server or negative count");
+  sv->fail_next_groups = count;
   return CNLOS_OK;
 }
 

@@ -66,6 +66,9 @@ enum Slot : int {
 };
 
 constexpr int kMaxBlocks = 4096;     // partial-sum capacity per slot
+// relative energy rise that restarts the FISTA sequence (t = 1) when the
+// optional function-value restart is on
+constexpr double kRestartTol = 1e-3;
 constexpr int kLogRows = 4096;       // per-iteration log ring
 constexpr int kLogCols = 6;
 
@@ -123,7 +126,7 @@ struct DevCtl {
   double meas_scale;
   double pow_est;
   double last_energy, last_primal, last_dual;
-  double reserved_d;
+  double restart_tol;  // > 0: function-value FISTA restart at this relative rise; 0: off
   int32_t bt_rejects;  // rejections since create/reset
   int32_t log_count;   // rows written to the log ring
   int32_t bt_max_trials;

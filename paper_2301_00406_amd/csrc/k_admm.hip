@@ -16,10 +16,6 @@ namespace cnlos {
 constexpr int kStencilThreads = 256;
 constexpr int kStencilMaxBlocks = 1024;   // 16 waves per CU; keeps the partial arrays short
 constexpr int kCtlThreads = 1024;
-// relative energy rise that restarts the FISTA sequence (t = 1): the paper
-// reports a decaying energy; the plain extrapolation inside the ADMM
-// iteration lets the dual-domain energy grow (function-value restart)
-constexpr double kRestartTol = 1e-3;
 
 int stencil_blocks(int logn, int logm) {
   const size_t V = (size_t)1 << (2 * logn + logm);
@@ -426,8 +422,10 @@ k_finalize(DevCtl* ctl, double* __restrict__ logbuf, const double* __restrict__ 
     ctl->log_count = log_count + 1;
     const double tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
     ctl->beta = (t - 1.0) / tn;
-    // momentum restart after an energy rise: the next extrapolation weight is 0
-    const bool restart = isfinite(Ep) && E > Ep * (1.0 + kRestartTol);
+    // optional momentum restart after an energy rise: the next extrapolation
+    // weight is 0 (off: the printed extrapolation)
+    const double rtol = ctl->restart_tol;
+    const bool restart = rtol > 0.0 && isfinite(Ep) && E > Ep * (1.0 + rtol);
     ctl->t = restart ? 1.0 : tn;
     ctl->iter = hd.iter + 1;
     ctl->trials = 0;

@@ -31,6 +31,15 @@ def rel_l2(got, ref):
     return float(np.linalg.norm(got - ref) / (den if den > 0 else 1.0))
 
 
+def max_rel(got, ref):
+    """Largest elementwise deviation relative to the reference's largest
+    magnitude (catches a wrong block edge that one norm could hide)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = float(np.abs(ref).max())
+    return float(np.abs(got - ref).max() / (den if den > 0 else 1.0))
+
+
 def f32(x):
     """The float32 value the GPU receives, as float64 for the oracle."""
     return np.asarray(x, dtype=np.float32).astype(np.float64)

@@ -23,7 +23,7 @@ def header_functions():
 def test_library_exports_every_declared_function():
     lib = C.load()
     names = header_functions()
-    assert len(names) == 33
+    assert len(names) == 34
     for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
@@ -38,9 +38,10 @@ def test_struct_layout_matches_header():
 #include <stdio.h>
 #include "cnlos.h"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
          offsetof(cnlos_config, power_iters), sizeof(cnlos_report), sizeof(cnlos_info),
-         offsetof(cnlos_info, iter), offsetof(cnlos_config, eps_stop));
+         offsetof(cnlos_info, iter), offsetof(cnlos_config, eps_stop),
+         offsetof(cnlos_config, fista_restart));
   return 0;
 }}
 """
@@ -53,7 +54,7 @@ int main(void) {{
         vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(C.Config), C.Config.lambda_.offset, C.Config.power_iters.offset,
                     ctypes.sizeof(C.Report), ctypes.sizeof(C.Info), C.Info.iter.offset,
-                    C.Config.eps_stop.offset]
+                    C.Config.eps_stop.offset, C.Config.fista_restart.offset]
 
 
 def test_defaults_follow_paper_parameters():
@@ -61,6 +62,7 @@ def test_defaults_follow_paper_parameters():
     assert (cfg.mu1, cfg.mu2, cfg.mu3) == (1.0, 800.0, 2.0)
     assert cfg.a_u == 5e-5 and cfg.b_u == 5e-5 and cfg.mu == 0.1
     assert cfg.bt_factor == 2.0 and cfg.power_iters == 15
+    assert cfg.fista_restart == 0          # the extrapolation as Algorithms 1-2 print it
     assert C.load().cnlos_version().decode() == "1.0"
 
 
@@ -71,7 +73,8 @@ def test_defaults_follow_paper_parameters():
     ("model", 3, C.EINVAL), ("phi", 7, C.EINVAL), ("falloff", 2, C.EINVAL),
     ("mu", 0.0, C.EINVAL), ("a_u", -1e-3, C.EINVAL), ("eta_curv", 0.0, C.EINVAL),
     ("bt_factor", 1.0, C.EINVAL), ("bt_max_trials", -1, C.EINVAL), ("max_iters", -3, C.EINVAL),
-    ("eps_stop", -1.0, C.EINVAL), ("power_iters", 0, C.EINVAL),
+    ("eps_stop", -1.0, C.EINVAL), ("power_iters", 0, C.EINVAL), ("fista_restart", 2, C.EINVAL),
+    ("fista_restart", -1, C.EINVAL),
 ])
 def test_validation_rejects_bad_configs(field, value, status):
     cfg = C.default_config()

@@ -13,7 +13,8 @@ import pytest
 from oracle import cnlos_oracle as O
 from paper_2301_00406_amd import cnlos as C
 from paper_2301_00406_amd import scenes
-from tests.gpu_helpers import f32, need_gpu, rel_l2, say, synth_measurement, to_dev, to_host
+from tests.gpu_helpers import (f32, max_rel, need_gpu, rel_l2, say, synth_measurement, to_dev,
+                               to_host)
 
 pytestmark = pytest.mark.gpu
 TOL_VOL = 1e-3
@@ -51,29 +52,34 @@ def test_power_estimate_and_measurement_normalization():
     assert rel_l2(got, tau0) <= 1e-6
 
 
-def test_algorithm1_small_workload_matches_oracle():
-    """16x16x128, 50% mask, 50 iterations of Algorithm 1 (the small workload)."""
+@pytest.mark.parametrize("restart", [0, 1])
+def test_algorithm1_small_workload_matches_oracle(restart):
+    """16x16x128, 50% mask, 50 iterations of Algorithm 1 (the small workload),
+    with the printed extrapolation and with the optional restart."""
     torch = need_gpu()
     sc = scenes.scene_small()
-    say("alg1 16x16x128 x50")
+    say(f"alg1 16x16x128 x50 restart={restart}")
     raw, op, tau0, _ = _setup(sc, 1)
     L0 = _oracle_L0(op)
-    p = O.Params(a=5e-5, b=5e-5, mu=0.1)
+    p = O.Params(a=5e-5, b=5e-5, mu=0.1, fista_restart=bool(restart))
     st = O.run_alg1(tau0, op, p, 50, L0=L0)
-    P = C.Problem(_cfg(sc, model=C.MODEL_OBJECT, max_iters=50, L0=L0, a_u=p.a, b_u=p.b, mu=p.mu),
-                  sc.mask)
+    P = C.Problem(_cfg(sc, model=C.MODEL_OBJECT, max_iters=50, L0=L0, a_u=p.a, b_u=p.b, mu=p.mu,
+                       fista_restart=restart), sc.mask)
     P.set_measurement(to_dev(torch, raw))
     rep = P.run()
     assert rep["iters_done"] == 50
     u = to_host(P.volume())
     err = rel_l2(u, st.u)
-    say(f"  rel L2 u = {err:.3e}")
+    say(f"  rel L2 u = {err:.3e}, max abs / max = {max_rel(u, st.u):.3e}")
     assert err <= TOL_VOL
+    assert max_rel(u, st.u) <= TOL_VOL
     log = P.log()
     E_ref = np.array([e[0] for e in st.log])
     assert np.max(np.abs(log[:, 0] - E_ref) / np.abs(E_ref)) <= 1e-4
     assert abs(rep["energy"] - E_ref[-1]) <= 1e-4 * abs(E_ref[-1])
     np.testing.assert_allclose(log[:, 1], [e[1] for e in st.log], rtol=2e-3, atol=1e-9)
+    np.testing.assert_allclose(log[:, 2], [e[2] for e in st.log], rtol=2e-3, atol=1e-9)
+    assert abs(P.info()["t"] - st.t) <= 1e-12 * st.t
 
 
 def test_algorithm1_fields_after_a_few_iterations():
@@ -118,19 +124,38 @@ def test_backtracking_step_sequence_matches_oracle():
     assert rel_l2(to_host(P.volume()), st.u) <= TOL_VOL
 
 
-def test_algorithm2_matches_oracle():
-    """Dual-domain model with an Algorithm-1 warm start."""
-    torch = need_gpu()
-    sc = scenes.scene_custom(16, 128, 41, wall=0.8, bin_ps=32.0, density=0.3, peak=20.0,
+def _alg2_small(seed_scene=41, seed_meas=4):
+    sc = scenes.scene_custom(16, 128, seed_scene, wall=0.8, bin_ps=32.0, density=0.3, peak=20.0,
                              background=0.2)
-    say("alg2 16x16x128 10+20")
-    raw, op, tau0, _ = _setup(sc, 4)
-    L0o = _oracle_L0(op, True)
-    L0d = _oracle_L0(op, False)
-    p = O.Params(a=1.5e-4, b=4e-5, mu=0.1, a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, lam=200.0)
-    s1, s2 = O.run_alg2(tau0, op, p, 20, 10, L0_obj=L0o, L0_dual=L0d)
-    cfg = _cfg(sc, model=C.MODEL_DUAL, max_iters=20, init_iters=10, a_u=p.a_u, b_u=p.b_u,
-               a_tau=p.a_tau, b_tau=p.b_tau, warm_a=p.a, warm_b=p.b, mu=p.mu, lam=p.lam)
+    raw, op, tau0, _ = _setup(sc, seed_meas)
+    return sc, raw, op, tau0, _oracle_L0(op, True), _oracle_L0(op, False)
+
+
+ALG2_P = dict(a=1.5e-4, b=4e-5, mu=0.1, a_u=5e-4, b_u=5e-5, a_tau=3e-3, b_tau=5e-4, lam=200.0)
+
+
+def _alg2_cfg(sc, p, iters, init, **kw):
+    return _cfg(sc, model=C.MODEL_DUAL, max_iters=iters, init_iters=init, a_u=p.a_u, b_u=p.b_u,
+                a_tau=p.a_tau, b_tau=p.b_tau, warm_a=p.a, warm_b=p.b, mu=p.mu, lam=p.lam,
+                phi=p.phi_kind, **kw)
+
+
+@pytest.mark.parametrize("restart", [0, 1])
+def test_algorithm2_matches_oracle(restart):
+    """Dual-domain model with an Algorithm-1 warm start (10 + 40 iterations at
+    16x16x128): the printed extrapolation, and the optional function-value
+    restart, which fires in this run (the energy rises after dual iteration
+    26).  u, tau, energies, the primal and dual residuals and t follow the
+    oracle."""
+    torch = need_gpu()
+    sc, raw, op, tau0, L0o, L0d = _alg2_small()
+    say(f"alg2 16x16x128 10+40 restart={restart}")
+    p = O.Params(**ALG2_P, fista_restart=bool(restart))
+    s1, s2 = O.run_alg2(tau0, op, p, 40, 10, L0_obj=L0o, L0_dual=L0d)
+    E_ref = np.array([e[0] for e in s2.log])
+    rises = E_ref[1:] > E_ref[:-1] * (1 + O.RESTART_TOL)
+    assert rises.any()                       # the restart has something to do
+    cfg = _alg2_cfg(sc, p, 40, 10, fista_restart=restart)
     # both step constants from the oracle's own power estimates
     P = C.Problem(cfg, sc.mask)
     info = P.info()
@@ -140,19 +165,76 @@ def test_algorithm2_matches_oracle():
     P.run(10)
     assert rel_l2(to_host(P.volume()), s1.u) <= TOL_VOL
     rep = P.run()
-    assert rep["total_iters"] == 30
+    assert rep["total_iters"] == 50
     assert P.info()["stage"] == 2
+    u, tau = to_host(P.volume()), to_host(P.signal())
+    eu, et = rel_l2(u, s2.u), rel_l2(tau, s2.tau)
+    say(f"  rel L2 u = {eu:.3e}, tau = {et:.3e}; max abs / max u = {max_rel(u, s2.u):.3e}, "
+        f"tau = {max_rel(tau, s2.tau):.3e}")
+    assert eu <= TOL_VOL and et <= TOL_VOL
+    assert max_rel(u, s2.u) <= TOL_VOL and max_rel(tau, s2.tau) <= TOL_VOL
+    log = P.log()
+    assert np.max(np.abs(log[10:, 0] - E_ref) / np.abs(E_ref)) <= 1e-3
+    np.testing.assert_allclose(log[10:, 1], [e[1] for e in s2.log], rtol=1e-3, atol=1e-9)
+    np.testing.assert_allclose(log[10:, 2], [e[2] for e in s2.log], rtol=1e-3, atol=1e-9)
+    assert abs(P.info()["t"] - s2.t) <= 1e-12 * s2.t
+
+
+@pytest.mark.parametrize("kind", [C.PHI_TAC, C.PHI_TRV])
+def test_algorithm2_phi_variants_match_oracle(kind):
+    """Algorithm 2 with the absolute-curvature and roto-translation weights."""
+    torch = need_gpu()
+    sc, raw, op, tau0, L0o, L0d = _alg2_small()
+    say(f"alg2 16x16x128 10+20 phi={kind}")
+    pr = dict(ALG2_P)
+    if kind == C.PHI_TRV:      # sqrt(a + b k^2): weights of the squared scale
+        pr.update({k: pr[k] ** 2 for k in ("a", "b", "a_u", "b_u", "a_tau", "b_tau")})
+    p = O.Params(**pr, phi_kind=kind)
+    s1, s2 = O.run_alg2(tau0, op, p, 20, 10, L0_obj=L0o, L0_dual=L0d)
+    P = C.Problem(_alg2_cfg(sc, p, 20, 10, L0=L0o, L0_dual=L0d), sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    P.run()
     eu = rel_l2(to_host(P.volume()), s2.u)
     et = rel_l2(to_host(P.signal()), s2.tau)
     say(f"  rel L2 u = {eu:.3e}, tau = {et:.3e}")
     assert eu <= TOL_VOL and et <= TOL_VOL
-    log = P.log()
-    E_ref = np.array([e[0] for e in s2.log])
-    assert np.max(np.abs(log[10:, 0] - E_ref) / np.abs(E_ref)) <= 1e-3
-    # the run restarts the FISTA sequence (energy rises well beyond the
-    # tolerance late in the run), and the GPU's t follows the oracle's
-    assert any(E_ref[k] > E_ref[k - 1] * (1 + 10 * O.RESTART_TOL) for k in range(1, len(E_ref)))
-    assert abs(P.info()["t"] - s2.t) <= 1e-12 * s2.t
+
+
+def test_algorithm2_early_stopping_matches_oracle():
+    """Algorithm 2's stopping rule on the relative change of the eq. (13)
+    energy: both sides stop after the same iteration with the same volume."""
+    torch = need_gpu()
+    sc, raw, op, tau0, L0o, L0d = _alg2_small()
+    p = O.Params(**ALG2_P, eps=5e-3)
+    s1, s2 = O.run_alg2(tau0, op, p, 200, 10, L0_obj=L0o, L0_dual=L0d)
+    assert len(s2.log) < 200
+    say(f"alg2 16x16x128 eps 5e-3: oracle stops after {len(s2.log)}")
+    P = C.Problem(_alg2_cfg(sc, p, 200, 10, L0=L0o, L0_dual=L0d, eps_stop=5e-3), sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    rep = P.run()
+    assert rep["stopped_early"] == 1
+    assert rep["total_iters"] == 10 + len(s2.log)
+    assert rel_l2(to_host(P.volume()), s2.u) <= TOL_VOL
+
+
+def test_algorithm1_literal_falloff_matches_oracle():
+    """Algorithm 1 on the literal radiometric weight of eq. (3) (m = 32: the
+    weight spans (2m)^3 = 2.6e5), with a dense measurement."""
+    torch = need_gpu()
+    sc = scenes.scene_custom(16, 32, 61, wall=1.0, bin_ps=128.0, density=0.5, peak=40.0,
+                             background=0.5)
+    say("alg1 16x16x32 literal falloff x20")
+    raw, op, tau0, _ = _setup(sc, 62, falloff=O.FALLOFF_LITERAL)
+    L0 = _oracle_L0(op)
+    p = O.Params(a=5e-5, b=5e-5, mu=0.1)
+    st = O.run_alg1(tau0, op, p, 20, L0=L0)
+    P = C.Problem(_cfg(sc, model=C.MODEL_OBJECT, max_iters=20, L0=L0, falloff=C.FALLOFF_LITERAL),
+                  sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    P.run()
+    err = rel_l2(to_host(P.volume()), st.u)
+    say(f"  rel L2 u = {err:.3e}")
+    assert err <= TOL_VOL
 
 
 def test_determinism_and_resume():

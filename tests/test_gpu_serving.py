@@ -103,3 +103,84 @@ def test_admission_waits_for_arena_memory():
     # the small requests were admitted only once the large group had drained
     for i in (1, 2):
         assert done[i]["queued_steps"] >= done[0]["served_steps"]
+
+
+def test_group_creation_failure_gives_exactly_one_completion_per_request():
+    """A slot group that cannot be created (failure injected by the library's
+    test hook after its arena range and stream exist): the request that needed
+    it completes once with the error, its arena range comes back, and every
+    other request, queued before or after it, completes once and equals its
+    alone run."""
+    torch = need_gpu()
+    say("serving: injected slot-group creation failure")
+    r = _requests(torch)
+    reqs = [r[0], r[1], r[2], r[4]]      # 16x128 object, 32x256 dual, 16x256 object, 16x128 object
+    S = C.Server(4 << 30, slots=2, rounds=3)
+    outs = [torch.zeros(tuple(q[2].shape), dtype=torch.float32, device="cuda") for q in reqs]
+    S.fail_next_groups(1)
+    for i, (cfg, mask, raw) in enumerate(reqs):
+        S.submit(cfg, mask, raw, outs[i], i)
+    done = {}
+    for step in range(400):
+        S.step()
+        used, groups = S.usage()
+        # the failed group's range was given back: what is in use is exactly
+        # the groups that exist
+        assert used <= 2 * sum(C.workspace_bytes(q[0]) for q in reqs[1:3]) + \
+            2 * C.workspace_bytes(reqs[0][0])
+        for c in S.poll():
+            assert c["id"] not in done, f"second completion for request {c['id']}"
+            done[c["id"]] = c
+        if len(done) == len(reqs):
+            break
+    S.close()
+    assert sorted(done) == [0, 1, 2, 3]
+    assert done[0]["status"] == C.EHIP and done[0]["iters"] == 0
+    for i in (1, 2, 3):
+        assert done[i]["status"] == C.OK, (i, done[i])
+        cfg, mask, raw = reqs[i]
+        assert np.array_equal(outs[i].cpu().numpy(), _alone(torch, cfg, mask, raw)), i
+
+
+def test_served_requests_match_the_oracle():
+    """One object-model and one dual-model request, served beside others, agree
+    with the FP64 oracle to the per-volume tolerance (1e-3 relative L2).  The
+    step constants are the oracle's power estimates, passed in the requests."""
+    import dataclasses
+    from oracle import cnlos_oracle as O
+    from tests.gpu_helpers import f32, rel_l2
+    torch = need_gpu()
+    say("serving: served results against the oracle")
+    reqs = _requests(torch)
+    checks = {}
+    for i in (0, 1):
+        n, m = reqs[i][0].nx, reqs[i][0].nt
+        sc = scenes.scene_custom(n, m, 3000 + i, wall=1.0, bin_ps=32.0 * 128 / m,
+                                 density=0.2 + 0.05 * i, peak=5.0 + 5 * i)
+        raw = f32(synth_measurement(sc, 3100 + i))
+        op = O.make_operator(n, n, m, 1.0, 1.0, sc.bin_ps, O.FALLOFF_COMPENSATED, sc.mask)
+        tau0, _ = O.normalize_measurement(raw, sc.mask, O.FALLOFF_COMPENSATED)
+        L0o = 2 * O.power_norm2(lambda x: O.apply_A(x, op, True),
+                                lambda y: O.apply_AT(y, op, True), tau0.shape)
+        cfg = reqs[i][0]
+        cfg.L0 = L0o
+        if cfg.model == C.MODEL_DUAL:
+            L0d = 2 * O.power_norm2(lambda x: O.apply_A(x, op, False),
+                                    lambda y: O.apply_AT(y, op, False), tau0.shape)
+            cfg.L0_dual = L0d
+            p = O.Params(a=DUAL["warm_a"], b=DUAL["warm_b"], mu=DUAL["mu"], a_u=DUAL["a_u"],
+                         b_u=DUAL["b_u"], a_tau=DUAL["a_tau"], b_tau=DUAL["b_tau"],
+                         lam=DUAL["lam"])
+            _, s2 = O.run_alg2(tau0, op, p, cfg.max_iters, cfg.init_iters, L0_obj=L0o,
+                               L0_dual=L0d)
+            checks[i] = s2.u
+        else:
+            p = O.Params(a=OBJ["a_u"], b=OBJ["b_u"], mu=OBJ["mu"])
+            checks[i] = O.run_alg1(tau0, op, p, cfg.max_iters, L0=L0o).u
+    outs, done, _ = _serve(torch, reqs, 4 << 30, slots=2, rounds=3,
+                           arrivals=[0, 0, 1, 2, 2, 4, 6, 7])
+    for i, ref in checks.items():
+        assert done[i]["status"] == C.OK
+        err = rel_l2(outs[i].double().cpu().numpy(), ref)
+        say(f"  request {i}: rel L2 vs oracle {err:.2e}")
+        assert err <= 1e-3

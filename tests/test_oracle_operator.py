@@ -31,6 +31,13 @@ def test_resample_columns_sum_to_one_and_rows_are_contiguous(m):
     assert abs(S.sum() - m) < 1e-9
 
 
+def test_literal_falloff_weights_match_hand_values():
+    rows, _ = load_golden_matrix("falloff_literal_m4.txt")
+    np.testing.assert_allclose(O.falloff_weights(4, O.FALLOFF_LITERAL), np.array(rows[0]),
+                               rtol=1e-15)
+    np.testing.assert_array_equal(O.falloff_weights(4, O.FALLOFF_COMPENSATED), np.ones(4))
+
+
 def test_kernel_offsets_unit_slope_fixture():
     rows, extra = load_golden_matrix("kernel_offsets_unit_slope.txt")
     n, m, bin_ps = 2, 4, 1000.0
