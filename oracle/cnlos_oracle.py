@@ -585,3 +585,97 @@ def run_alg2(tau0, op: LCTOperator, p: Params, iters: int, init_iters: int,
         if p.eps > 0 and s2.log[-1][5] <= p.eps:
             break
     return s1, s2
+
+
+# ============================================================================
+# Non-confocal model (Section 2), reference only
+# ============================================================================
+#
+# The general model of Section 2 illuminates wall point x_i and detects at
+# wall point x_d; light travels d(x_i, x) + d(x, x_d) = t c.  With unit normals
+# the direction terms reduce, as in the confocal case, to the volumetric albedo
+# weight 1 / (d_i^2 d_d^2).  The oracle discretizes it by direct summation on
+# the confocal grid conventions: detector (i, j) at x_i = (i + 1/2) W / n - W/2,
+# voxel (p, q, k) at the same lateral positions and depth z_k = (k + 1/2) R / m
+# (R = m c dt / 2 as in the confocal model), and time bin b holding path
+# lengths in [b, b + 1) c dt.  The illumination point is one fixed wall point
+# (the detector grid is scanned).  It is not shift-invariant, so no FFT form
+# exists; the midpoint approximation used for the non-confocal experiment of
+# Section 5 maps it to the confocal operator (nonconfocal_midpoint_geometry).
+
+@dataclasses.dataclass
+class NonConfocalGeometry:
+    n: int                 # detector grid n x n (and voxel grid laterally)
+    m: int                 # time bins (and depth bins)
+    wall: float            # wall extent W (m), square
+    bin_ps: float          # time-bin width (ps)
+    illum: tuple           # (x, y) of the illumination point on the wall (m)
+
+    def lateral(self) -> np.ndarray:
+        return (np.arange(self.n) + 0.5) * self.wall / self.n - self.wall / 2.0
+
+    def depth(self) -> np.ndarray:
+        R = range_metres(self.m, self.bin_ps)
+        return (np.arange(self.m) + 0.5) * R / self.m
+
+    def bin_length(self) -> float:
+        """Path length per time bin, c dt."""
+        return C_LIGHT * self.bin_ps * 1e-12
+
+
+def _nc_paths(g: NonConfocalGeometry, literal: bool = True):
+    """For every (detector, voxel): time bin of d_i + d_d (-1 beyond the
+    window) and the albedo weight 1 / (d_i^2 d_d^2) (1 when not literal).
+    Shapes [n, n, n, n, m] (detector i, j; voxel p, q, k)."""
+    x = g.lateral()
+    z = g.depth()
+    X = x[None, None, :, None, None]
+    Y = x[None, None, None, :, None]
+    Z = z[None, None, None, None, :]
+    di = np.sqrt((X - g.illum[0]) ** 2 + (Y - g.illum[1]) ** 2 + Z ** 2)
+    dd = np.sqrt((X - x[:, None, None, None, None]) ** 2
+                 + (Y - x[None, :, None, None, None]) ** 2 + Z ** 2)
+    L = di + dd
+    b = np.floor(L / g.bin_length()).astype(np.int64)
+    b = np.where(b < g.m, b, -1)
+    w = 1.0 / (di * di * dd * dd) if literal else np.ones_like(L)
+    return b, w
+
+
+def apply_nonconfocal(u: np.ndarray, g: NonConfocalGeometry, literal: bool = True) -> np.ndarray:
+    """tau[i, j, b] = sum over voxels of u w, where the voxel's path length
+    falls in bin b (direct summation; small grids only)."""
+    b, w = _nc_paths(g, literal)
+    n, m = g.n, g.m
+    tau = np.zeros((n, n, m))
+    contrib = w * u[None, None, :, :, :]
+    for i in range(n):
+        for j in range(n):
+            bb = b[i, j].ravel()
+            ok = bb >= 0
+            tau[i, j] = np.bincount(bb[ok], weights=contrib[i, j].ravel()[ok], minlength=m)[:m]
+    return tau
+
+
+def apply_nonconfocal_T(tau: np.ndarray, g: NonConfocalGeometry, literal: bool = True) -> np.ndarray:
+    """The transpose: u[p, q, k] = sum over detectors of w tau[i, j, bin]."""
+    b, w = _nc_paths(g, literal)
+    n, m = g.n, g.m
+    u = np.zeros((n, n, m))
+    for i in range(n):
+        for j in range(n):
+            bb = b[i, j]
+            ok = bb >= 0
+            u += np.where(ok, w[i, j] * tau[i, j][np.where(ok, bb, 0)], 0.0)
+    return u
+
+
+def nonconfocal_midpoint_geometry(g: NonConfocalGeometry):
+    """Midpoint approximation: detector x_d with illumination x_i reads as a
+    confocal measurement at x_m = (x_i + x_d) / 2, the path length d_i + d_d
+    standing in for 2 d(x_m, x).  The midpoints of a fixed illumination point
+    and an n x n detector grid of extent W form an n x n grid of extent W / 2
+    centred at (x_i + wall centre) / 2, so the transient array is reused as is
+    with the confocal operator of that grid.  Returns (wall extent, (x, y) of
+    the grid centre)."""
+    return g.wall / 2.0, (g.illum[0] / 2.0, g.illum[1] / 2.0)
