@@ -199,6 +199,22 @@ cnlos_status cnlos_set_measurement(cnlos_problem* p, const float* tau0_dev);
  * u_dev and tau_dev are [nx][ny][nt]; they may not alias.  Asynchronous. */
 cnlos_status cnlos_apply_A(cnlos_problem* p, const float* u_dev, float* tau_dev, int32_t masked);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tau = A u,
+ * or D A u when masked != 0, for a configuration without a problem handle or
+ * workspace.  Equal to cnlos_create (any model; the operator part is used) +
+ * cnlos_apply_A.  The operator's tables, H^ and convolution spectrum live in
+ * a static device array of 96 MiB (one per device, held until the process
+ * ends), which admits shapes up to 64x64x512 and 32x32x1024; larger shapes
+ * return CNLOS_EINVAL before any device work.  Allocates no device or pinned
+ * memory (the small host tables are built in ordinary host memory and copied
+ * in).  Runs on the current device; hip_stream must belong to it.  Every call
+ * on a device rebuilds the scratch from scratch, so calls that overlap on one
+ * device (other threads, other streams) race.  Synchronizes the stream. */
+cnlos_status cnlos_apply_A_noalloc(const cnlos_config* cfg, const uint8_t* mask_host,
+                                   const float* u_dev, float* tau_dev, int32_t masked,
+                                   void* hip_stream);
+
 /* u = A^T tau, or A^T D tau when masked != 0 (the adjoint used in the gradient
  * of the data term, Section 3.1).  May not alias.  Asynchronous. */
 cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev, int32_t masked);

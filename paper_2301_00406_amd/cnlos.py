@@ -99,6 +99,7 @@ def load() -> ctypes.CDLL:
         "cnlos_set_measurement": ([P, P], c_int32),
         "cnlos_apply_A": ([P, P, P, c_int32], c_int32),
         "cnlos_apply_AT": ([P, P, P, c_int32], c_int32),
+        "cnlos_apply_A_noalloc": ([POINTER(Config), POINTER(c_uint8), P, P, c_int32, P], c_int32),
         "cnlos_run": ([P, c_int32, POINTER(Report)], c_int32),
         "cnlos_reset": ([P], c_int32),
         "cnlos_get_volume": ([P, P], c_int32),
@@ -166,6 +167,25 @@ def workspace_bytes(cfg: Config) -> int:
     n = c_uint64()
     check(load().cnlos_workspace_bytes(byref(cfg), byref(n)))
     return int(n.value)
+
+
+def apply_A_noalloc(cfg: Config, mask, u, out, masked=False, stream=None):
+    """tau = A u (or D A u) for a configuration, with no handle and no
+    workspace: the library's static scratch holds the operator (the entry
+    point for callers that cannot allocate).  u and out are contiguous float32
+    [nx][ny][nt] tensors on the current device."""
+    import torch
+    lib = load()
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    shape = (cfg.nx, cfg.ny, cfg.nt)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    _dev_f32(u, shape, dev)
+    _dev_f32(out, shape, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    check(lib.cnlos_apply_A_noalloc(byref(cfg), m.ctypes.data_as(POINTER(c_uint8)),
+                                    c_void_p(u.data_ptr()), c_void_p(out.data_ptr()),
+                                    int(bool(masked)), c_void_p(st.cuda_stream)))
+    return out
 
 
 def _dev_f32(t, shape, device):

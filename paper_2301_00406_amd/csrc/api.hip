@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1310,6 +1311,84 @@ cnlos_status cnlos_apply_AT(cnlos_problem* p, const float* tau_dev, float* u_dev
   e.au = fixed(nullptr);
   e.au_prev = fixed(nullptr);
   HIPCHK(conv(p, s, true, EPI_PLAIN, e, nullptr));
+  return CNLOS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------- the forward operator without a workspace
+namespace {
+
+// Scratch of cnlos_apply_A_noalloc: the operator's tables, H^ and convolution
+// spectrum, laid out as an operator-only workspace.  Each device that runs the
+// entry point holds one copy for the life of the process.  In host code the
+// array's name is only a stand-in for the device symbol: its device address
+// comes from hipGetSymbolAddress, once per device.
+constexpr uint64_t kScratchBytes = 96ull << 20;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kScratchDevices] = {};
+
+// device address of the current device's scratch (looked up on first use)
+cnlos_status scratch_of_current_device(uint8_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CNLOS_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(CNLOS_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CNLOS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<uint8_t*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return CNLOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cnlos_status cnlos_apply_A_noalloc(const cnlos_config* cfg, const uint8_t* mask_host,
+                                   const float* u_dev, float* tau_dev, int32_t masked,
+                                   void* hip_stream) {
+  if (!cfg) return fail(CNLOS_EINVAL, "config is NULL");
+  if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
+  if (!u_dev || !tau_dev) return fail(CNLOS_EINVAL, "NULL volume");
+  if ((const void*)u_dev == (const void*)tau_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
+  cnlos_config oc = *cfg;
+  oc.model = CNLOS_MODEL_OPERATOR;
+  cnlos_status s = cnlos_validate(&oc, mask_host);
+  if (s != CNLOS_OK) return s;
+  const size_t need = carve(nullptr, oc, nullptr);
+  if (need > kScratchBytes)
+    return fail(CNLOS_EINVAL, "this shape needs " + std::to_string(need) +
+                                  " bytes of operator scratch; the static scratch holds " +
+                                  std::to_string(kScratchBytes));
+  uint8_t* base = nullptr;
+  s = scratch_of_current_device(&base);
+  if (s != CNLOS_OK) return s;
+  cnlos_problem prob;
+  cnlos_problem* p = &prob;
+  layout_problem(p, oc, base, kScratchBytes, (hipStream_t)hip_stream);
+  s = build_tables(p, &oc, mask_host);
+  if (s != CNLOS_OK) return s;
+  ConvSrc src{};
+  src.a = fixed(u_dev);
+  src.b = fixed(nullptr);
+  ConvEpi e{};
+  e.out = fixed(tau_dev);
+  e.au = fixed(nullptr);
+  e.au_prev = fixed(nullptr);
+  e.w = p->wk;
+  e.mask = masked ? p->mask : nullptr;
+  HIPCHK(conv(p, src, false, EPI_PLAIN, e, nullptr));
+  HIPCHK(hipStreamSynchronize(p->st));
   return CNLOS_OK;
 }
 
