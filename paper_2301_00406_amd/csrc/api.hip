@@ -50,7 +50,8 @@ struct Carver {
 };
 
 cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
-                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out);
+                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out,
+                         float2* shared_hq = nullptr, bool own_hq = true);
 cnlos_status destroy_problem(cnlos_problem* p);
 
 }  // namespace
@@ -68,6 +69,7 @@ struct cnlos_batch {
   std::vector<cnlos_problem*> mem;
   size_t stride = 0;
   hipStream_t st = nullptr;
+  bool hq_shared = false;     // one geometry: every member reads member 0's H^
 };
 
 // ------------------------------------------------------------ serving state
@@ -117,7 +119,10 @@ struct SrvGroup {
   cnlos_config proto;
   size_t stride = 0;
   int K = 0;
-  uint64_t off = 0;
+  uint64_t off = 0;            // arena range: [off, off + bytes)
+  uint64_t bytes = 0;
+  float2* hq = nullptr;        // the group's H^, at the start of its range
+  uint64_t slots_off = 0;      // slot i's workspace at slots_off + i * stride
   hipStream_t st = nullptr;
   cnlos_problem* layout = nullptr;       // buffer layout of slot 0 (no device state of its own)
   std::vector<cnlos_problem*> slot;      // occupant per slot, or null
@@ -162,6 +167,7 @@ struct cnlos_problem {
   double* logbuf = nullptr;
   float2* spec = nullptr;
   float2* hq = nullptr;
+  bool hq_shared = false;     // hq belongs to the batch or slot group, built once
   float2* tw_t = nullptr;
   float2* tw_xy = nullptr;
   float2* twc_t = nullptr;
@@ -253,7 +259,14 @@ int resample_nnz(int m) {
   return 3 * m + 64;
 }
 
-size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
+// bytes of one lane-ordered H^ (every kt plane's full 2n x 2n spectrum)
+size_t hq_bytes(const cnlos_config& c) {
+  return align_up((size_t)(c.nt + 1) * 4 * c.nx * c.nx * sizeof(float2));
+}
+
+// With own_hq == false the problem reads an H^ held elsewhere (a slot group
+// of one geometry keeps one copy) and its workspace has no room for one.
+size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base, bool own_hq = true) {
   Carver cv{base};
   const int n = c.nx, m = c.nt;
   const size_t V = (size_t)n * n * m;
@@ -265,7 +278,7 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
   double* partials = cv.take<double>((size_t)SL_COUNT * kMaxBlocks);
   double* logbuf = cv.take<double>((size_t)kLogRows * kLogCols);
   float2* spec = cv.take<float2>(nspec);
-  float2* hq = cv.take<float2>(nhq);
+  float2* hq = own_hq ? cv.take<float2>(nhq) : nullptr;
   float2* tw_t = cv.take<float2>(m);
   float2* tw_xy = cv.take<float2>(n);
   float2* twc_t = cv.take<float2>(m);
@@ -284,7 +297,7 @@ size_t carve(cnlos_problem* p, const cnlos_config& c, uint8_t* base) {
     p->partials = partials;
     p->logbuf = logbuf;
     p->spec = spec;
-    p->hq = hq;
+    if (own_hq) p->hq = hq;
     p->tw_t = tw_t;
     p->tw_xy = tw_xy;
     p->twc_t = twc_t;
@@ -438,6 +451,12 @@ bool same_shared(const cnlos_config& b, const cnlos_config& a) {
          b.b_tau == a.b_tau && b.warm_a == a.warm_a && b.warm_b == a.warm_b && b.mu == a.mu &&
          b.mu1 == a.mu1 && b.mu2 == a.mu2 && b.mu3 == a.mu3 && b.lambda == a.lambda &&
          b.eta_curv == a.eta_curv && b.backtracking == a.backtracking;
+}
+
+// equal H^ (eq. (3) depends on the shape, the wall extent and the bin width)
+bool same_geometry(const cnlos_config& b, const cnlos_config& a) {
+  return b.nx == a.nx && b.ny == a.ny && b.nt == a.nt && b.wall_w_m == a.wall_w_m &&
+         b.wall_h_m == a.wall_h_m && b.bin_ps == a.bin_ps;
 }
 
 // the rotating-role operand r of problem p (its candidate buffers and role)
@@ -1019,8 +1038,11 @@ namespace {
 
 // Sizes, buffer addresses and launch geometry of a problem whose workspace
 // starts at ws.
+// shared_hq: an H^ of this geometry held elsewhere; with own_hq false the
+// workspace has no room of its own for one (slot groups), with own_hq true it
+// keeps the room unused so that every slice of a batch has one layout.
 void layout_problem(cnlos_problem* p, const cnlos_config& cfg, uint8_t* ws, uint64_t ws_bytes,
-                    hipStream_t st) {
+                    hipStream_t st, float2* shared_hq = nullptr, bool own_hq = true) {
   p->cfg = cfg;
   p->logn = ilog2(cfg.nx);
   p->logm = ilog2(cfg.nt);
@@ -1029,7 +1051,11 @@ void layout_problem(cnlos_problem* p, const cnlos_config& cfg, uint8_t* ws, uint
   p->st = st;
   p->ws = ws;
   p->ws_bytes = ws_bytes;
-  p->carve_bytes = carve(p, cfg, ws);
+  p->carve_bytes = carve(p, cfg, ws, own_hq);
+  if (shared_hq) {
+    p->hq = shared_hq;
+    p->hq_shared = true;
+  }
   p->nb_conv = conv_blocks(p->logn, p->logm);
   p->nb_solve = solve_blocks(p->logn, p->logm);
   p->nb_step = fused_solve_blocks(p->logn, p->logm);
@@ -1167,10 +1193,12 @@ cnlos_status build_tables(cnlos_problem* p, const cnlos_config* cfg, const uint8
   HIPCHK(h2d(p->sig_xy, sig_xy.data(), n * sizeof(float)));
   HIPCHK(h2d(p->sig_t, sig_t.data(), (m / 2 + 1) * sizeof(float)));
   HIPCHK(h2d(p->mask, mk.data(), mk.size()));
-  HIPCHK(h2d(d_dq, dq.data(), dq.size() * sizeof(int)));
-  HIPCHK(h2d(d_etab, etab.data(), etab.size() * sizeof(double2)));
-  HIPCHK(h2d(d_cosn, cosn.data(), cosn.size() * sizeof(double)));
-  HIPCHK(launch_build_hq(p->logn, p->logm, p->hq, d_dq, d_etab, d_cosn, 1.0 / (double)Z, p->st));
+  if (!p->hq_shared) {      // a shared H^ is built once, by its owner
+    HIPCHK(h2d(d_dq, dq.data(), dq.size() * sizeof(int)));
+    HIPCHK(h2d(d_etab, etab.data(), etab.size() * sizeof(double2)));
+    HIPCHK(h2d(d_cosn, cosn.data(), cosn.size() * sizeof(double)));
+    HIPCHK(launch_build_hq(p->logn, p->logm, p->hq, d_dq, d_etab, d_cosn, 1.0 / (double)Z, p->st));
+  }
 
   p->tb.tw_t = p->tw_t;
   p->tb.tw_xy = p->tw_xy;
@@ -1188,13 +1216,14 @@ cnlos_status build_tables(cnlos_problem* p, const cnlos_config* cfg, const uint8
 }
 
 cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
-                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out) {
+                         uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out,
+                         float2* shared_hq, bool own_hq) {
   if (!out) return fail(CNLOS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
   cnlos_status s = cnlos_validate(cfg, mask_host);
   if (s != CNLOS_OK) return s;
-  const size_t need = carve(nullptr, *cfg, nullptr);
+  const size_t need = carve(nullptr, *cfg, nullptr, own_hq);
   if (!workspace_dev) return fail(CNLOS_EINVAL, "workspace is NULL");
   if (((uintptr_t)workspace_dev) % kAlign) return fail(CNLOS_EINVAL, "workspace must be 256-byte aligned");
   if (workspace_bytes < need)
@@ -1202,7 +1231,8 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
 
   cnlos_problem* p = new (std::nothrow) cnlos_problem();
   if (!p) return fail(CNLOS_ENOMEM, "host allocation failed");
-  layout_problem(p, *cfg, (uint8_t*)workspace_dev, workspace_bytes, (hipStream_t)hip_stream);
+  layout_problem(p, *cfg, (uint8_t*)workspace_dev, workspace_bytes, (hipStream_t)hip_stream,
+                 shared_hq, own_hq);
   *out = p;   // from here on errors leave a handle the caller must destroy
 
   if (hipHostMalloc((void**)&p->ctl_host, sizeof(DevCtl), hipHostMallocDefault) != hipSuccess) {
@@ -1594,11 +1624,16 @@ cnlos_status cnlos_batch_create(const cnlos_config* cfgs, int32_t count,
   if (!b) return fail(CNLOS_ENOMEM, "host allocation failed");
   b->stride = stride;
   b->st = (hipStream_t)hip_stream;
+  // members of one geometry read member 0's H^ (built once); their own room
+  // for it stays unused so that every slice has the same layout
+  b->hq_shared = true;
+  for (int i = 1; i < count; ++i) b->hq_shared = b->hq_shared && same_geometry(cfgs[i], a);
   *out = b;
   for (int i = 0; i < count; ++i) {
     cnlos_problem* m = nullptr;
+    float2* shared = (b->hq_shared && i > 0) ? b->mem[0]->hq : nullptr;
     cnlos_status s = create_into(&cfgs[i], masks_host[i], (uint8_t*)workspace_dev + stride * i, stride,
-                                 hip_stream, &m);
+                                 hip_stream, &m, shared, true);
     if (m) {
       m->in_batch = true;
       b->mem.push_back(m);
@@ -1623,7 +1658,7 @@ static cnlos_status batch_group(cnlos_batch* b, Group* g) {
   }
   g->lead = b->mem[0];
   g->mem = b->mem;
-  g->bt = Batch{(int)b->mem.size(), b->stride, G_NONE};
+  g->bt = Batch{(int)b->mem.size(), b->stride, G_NONE, b->hq_shared};
   return CNLOS_OK;
 }
 
@@ -1668,21 +1703,28 @@ namespace {
 cnlos_status srv_fail(cnlos_status st, const std::string& msg) { return fail(st, msg); }
 void srv_group_free(cnlos_server* sv, SrvGroup* g);
 
-// a group's device state starts parked: every slot's controller halted
+// a group's device state starts parked: every slot's controller halted.  Its
+// arena range holds one H^ of the group's geometry, then the K slots, whose
+// workspaces have no H^ of their own.
 cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup** out) {
   *out = nullptr;
-  const size_t stride = carve(nullptr, cfg, nullptr);
+  const size_t stride = carve(nullptr, cfg, nullptr, false);
+  const size_t hqb = hq_bytes(cfg);
+  const uint64_t bytes = (uint64_t)stride * sv->K + hqb;
   uint64_t off = 0;
-  if (!sv->arena.take((uint64_t)stride * sv->K, &off)) return CNLOS_ENOMEM;
+  if (!sv->arena.take(bytes, &off)) return CNLOS_ENOMEM;
   SrvGroup* g = new (std::nothrow) SrvGroup();
   if (!g) {
-    sv->arena.give(off, (uint64_t)stride * sv->K);
+    sv->arena.give(off, bytes);
     return srv_fail(CNLOS_ENOMEM, "host allocation failed");
   }
   g->proto = cfg;
   g->stride = stride;
   g->K = sv->K;
   g->off = off;
+  g->bytes = bytes;
+  g->hq = reinterpret_cast<float2*>(sv->arena.base + off);
+  g->slots_off = off + hqb;
   g->slot.assign(g->K, nullptr);
   g->req.resize(g->K);
   g->run.resize(g->K);
@@ -1690,23 +1732,12 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
   cnlos_problem* p = new (std::nothrow) cnlos_problem();
   if (!p || hipStreamCreate(&g->st) != hipSuccess) {
     delete p;
-    sv->arena.give(off, (uint64_t)stride * sv->K);
+    sv->arena.give(off, bytes);
     delete g;
     return srv_fail(CNLOS_EHIP, "stream creation failed");
   }
-  uint8_t* ws = sv->arena.base + off;
-  layout_problem(p, cfg, ws, stride, g->st);
-  p->tb.tw_t = p->tw_t;
-  p->tb.tw_xy = p->tw_xy;
-  p->tb.twc_t = p->twc_t;
-  p->tb.twc_xy = p->twc_xy;
-  p->tb.S.rows = p->srows;
-  p->tb.S.rvals = p->srvals;
-  p->tb.S.cols = p->scols;
-  p->tb.S.cvals = p->scvals;
-  p->tb.sig_xy = p->sig_xy;
-  p->tb.sig_t = p->sig_t;
-  p->tb.hq = p->hq;
+  uint8_t* ws = sv->arena.base + g->slots_off;
+  layout_problem(p, cfg, ws, stride, g->st, g->hq, false);
   g->layout = p;
   // from here on a failure gives back the arena range, the stream and the
   // host objects (srv_group_free on a group that is not yet listed)
@@ -1714,6 +1745,18 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
     --sv->fail_next_groups;
     srv_group_free(sv, g);
     return srv_fail(CNLOS_EHIP, "slot-group creation failed (injected by the test hook)");
+  }
+  // the group's H^ (built once; the tables this writes into slot 0 are
+  // rebuilt by each admission), then every slot parked
+  {
+    std::vector<uint8_t> all((size_t)cfg.nx * cfg.ny, 1);
+    p->hq_shared = false;
+    const cnlos_status bs = build_tables(p, &cfg, all.data());
+    p->hq_shared = true;
+    if (bs != CNLOS_OK) {
+      srv_group_free(sv, g);
+      return bs;
+    }
   }
   DevCtl parked;
   memset(&parked, 0, sizeof(parked));
@@ -1741,7 +1784,7 @@ void srv_group_free(cnlos_server* sv, SrvGroup* g) {
     (void)hipStreamDestroy(g->st);
   }
   delete g->layout;
-  sv->arena.give(g->off, (uint64_t)g->stride * g->K);
+  sv->arena.give(g->off, g->bytes);
   delete g;
 }
 
@@ -1777,8 +1820,9 @@ cnlos_status srv_admit(cnlos_server* sv, SrvGroup* g, int i, SrvReq& q) {
   cnlos_problem* m = nullptr;
   g->req[i] = q;
   g->admitted[i] = sv->step_no;
-  cnlos_status st = create_into(&q.r.cfg, q.mask.data(), sv->arena.base + g->off + (size_t)i * g->stride,
-                                g->stride, g->st, &m);
+  cnlos_status st = create_into(&q.r.cfg, q.mask.data(),
+                                sv->arena.base + g->slots_off + (size_t)i * g->stride, g->stride,
+                                g->st, &m, g->hq, false);
   if (m) m->in_batch = true;
   g->slot[i] = m;
   if (st == CNLOS_OK) st = cnlos_set_measurement(m, q.r.tau0_dev);
@@ -1830,7 +1874,7 @@ cnlos_status cnlos_server_submit(cnlos_server* sv, const cnlos_request* r) {
   if (st != CNLOS_OK) return st;
   if (!r->mask_host || !r->tau0_dev || !r->out_dev) return fail(CNLOS_EINVAL, "mask, measurement and output are required");
   if (r->cfg.model == CNLOS_MODEL_OPERATOR) return fail(CNLOS_EINVAL, "a request needs a solver model");
-  if ((uint64_t)carve(nullptr, r->cfg, nullptr) * sv->K > sv->arena.bytes)
+  if ((uint64_t)carve(nullptr, r->cfg, nullptr, false) * sv->K + hq_bytes(r->cfg) > sv->arena.bytes)
     return fail(CNLOS_ENOMEM, "a slot group of this shape does not fit the arena");
   SrvReq q;
   q.r = *r;
@@ -1853,7 +1897,7 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
     SrvGroup* g = nullptr;
     int free_slot = -1;
     for (SrvGroup* c : sv->groups) {
-      if (!same_shared(c->proto, q.r.cfg)) continue;
+      if (!same_shared(c->proto, q.r.cfg) || !same_geometry(c->proto, q.r.cfg)) continue;
       for (int i = 0; i < c->K && free_slot < 0; ++i)
         if (!c->slot[i]) free_slot = i;
       if (free_slot >= 0) {
@@ -1897,7 +1941,7 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
     SrvGroup* g = sv->groups[k];
     Group& v = views[k];
     v.lead = g->layout;
-    v.bt = Batch{g->K, g->stride, G_NONE};
+    v.bt = Batch{g->K, g->stride, G_NONE, true};
     for (int i = 0; i < g->K; ++i)
       if (g->slot[i]) {
         v.mem.push_back(g->slot[i]);

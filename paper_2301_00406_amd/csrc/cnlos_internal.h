@@ -311,6 +311,7 @@ struct Batch {
   int nz;
   size_t zs;
   int gate;
+  bool hq_shared = false;   // every scene reads the lead's H^ (one geometry)
 };
 constexpr Batch kSingle{1, 0, G_NONE};
 

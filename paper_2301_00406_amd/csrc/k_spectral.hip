@@ -553,7 +553,7 @@ template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneRegCfg<LOGN>::NT)
 k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
                  const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
-                 size_t zs, int gate) {
+                 size_t zs, size_t hzs, int gate) {
   using PC = PlaneRegCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, NT = PC::NT;
   constexpr int RE = PC::RE, YS = PC::YS;
@@ -565,7 +565,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   ctl = zsh(ctl, zo);
   if (gated_off(ctl, gate)) return;
   spec = zsh(spec, zo);
-  hq = zsh(hq, zo);
+  hq = zsh(hq, (size_t)blockIdx.z * hzs);   // 0: one H^ for every scene
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   const int tid = threadIdx.x;
@@ -717,7 +717,7 @@ template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneHalfCfg<LOGN>::NT)
 k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
                   const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
-                  size_t zs, int gate) {
+                  size_t zs, size_t hzs, int gate) {
   using PC = PlaneHalfCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, RN = PC::RN, YS = PC::YS;
   static_assert(2 * G == N, "two rows per lane group");
@@ -728,7 +728,7 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
   ctl = zsh(ctl, zo);
   if (gated_off(ctl, gate)) return;
   spec = zsh(spec, zo);
-  hq = zsh(hq, zo);
+  hq = zsh(hq, (size_t)blockIdx.z * hzs);   // 0: one H^ for every scene
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
   const int tid = threadIdx.x, g = tid >> 3, s = tid & 7;
@@ -1571,7 +1571,7 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   using TG = TGeo<LOGM>;
   const int nb = NN / TG::J;
   const int nz = bt.nz, g = bt.gate;
-  const size_t zs = bt.zs;
+  const size_t zs = bt.zs, hzs = bt.hq_shared ? 0 : zs;
   if (!tfwd_done)
     CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
                 hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, st,
@@ -1582,23 +1582,23 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
                   hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M, 1, nz),
                                      dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, g));
+                                     tb.twc_xy, ctl, zs, hzs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
                   hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M, 1, nz),
                                      dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, g));
+                                     tb.twc_xy, ctl, zs, hzs, g));
   } else {
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
                   hipLaunchKernelGGL((k_plane_conv_half<LOGN, true>), dim3(M + 1, 1, nz),
                                      dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, g));
+                                     tb.twc_xy, ctl, zs, hzs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
                   hipLaunchKernelGGL((k_plane_conv_half<LOGN, false>), dim3(M + 1, 1, nz),
                                      dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, g));
+                                     tb.twc_xy, ctl, zs, hzs, g));
   }
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
   if (rhs_next) {

@@ -38,6 +38,19 @@ def _requests(torch):
     return out
 
 
+def _hq_bytes(cfg):
+    """One lane-ordered H^: every kt plane's full 2n x 2n spectrum, complex64,
+    in a 256-byte aligned block."""
+    b = (cfg.nt + 1) * 4 * cfg.nx * cfg.nx * 8
+    return (b + 255) // 256 * 256
+
+
+def _group_bytes(cfg, slots):
+    """Arena bytes of a slot group: one H^ for the group's geometry, and slots
+    whose workspaces hold everything else."""
+    return slots * (C.workspace_bytes(cfg) - _hq_bytes(cfg)) + _hq_bytes(cfg)
+
+
 def _alone(torch, cfg, mask, raw):
     P = C.Problem(cfg, mask)
     P.set_measurement(raw)
@@ -93,9 +106,9 @@ def test_admission_waits_for_arena_memory():
     say("serving: arena for one large group at a time")
     r = _requests(torch)
     reqs = [r[1], r[0], r[2]]            # 32x256 dual first, then 16x128 and 16x256 object
-    large = C.workspace_bytes(reqs[0][0])
-    arena = 2 * large + (1 << 20)        # two slots of the large shape, no room for another group
-    assert all(2 * C.workspace_bytes(q[0]) > (1 << 20) for q in reqs[1:])
+    # room for the slot group of the large shape and nothing beside it
+    arena = _group_bytes(reqs[0][0], 2) + (1 << 20)
+    assert all(_group_bytes(q[0], 2) > (1 << 20) for q in reqs[1:])
     outs, done, groups = _serve(torch, reqs, arena, slots=2, rounds=4, arrivals=[0, 0, 0])
     for i, (cfg, mask, raw) in enumerate(reqs):
         assert done[i]["status"] == C.OK
@@ -184,3 +197,39 @@ def test_served_requests_match_the_oracle():
         err = rel_l2(outs[i].double().cpu().numpy(), ref)
         say(f"  request {i}: rel L2 vs oracle {err:.2e}")
         assert err <= 1e-3
+
+
+def test_a_slot_group_holds_one_kernel_spectrum():
+    """H^ depends only on the geometry (eq. (3)): a slot group keeps one copy
+    for all its slots, so its arena footprint is one H^ plus the slots'
+    workspaces without theirs, and requests of another wall extent get a group
+    of their own."""
+    torch = need_gpu()
+    say("serving: one H^ per slot group")
+    reqs = _requests(torch)
+    cfg, mask, raw = reqs[1]                       # 32x256 dual
+    S = C.Server(4 << 30, slots=4, rounds=2)
+    out = [torch.zeros(tuple(raw.shape), dtype=torch.float32, device="cuda") for _ in range(3)]
+    S.submit(cfg, mask, raw, out[0], 0)
+    S.submit(cfg, mask, raw, out[1], 1)
+    S.step()
+    used, groups = S.usage()
+    assert groups == 1 and used == _group_bytes(cfg, 4)
+    other = C.default_config(**{f: getattr(cfg, f) for f, _ in C.Config._fields_})
+    other.wall_w_m = other.wall_h_m = 0.9
+    S.submit(other, mask, raw, out[2], 2)
+    S.step()
+    used, groups = S.usage()
+    assert groups == 2 and used == 2 * _group_bytes(cfg, 4)
+    done = {}
+    for _ in range(400):
+        for c in S.poll():
+            done[c["id"]] = c
+        if len(done) == 3:
+            break
+        S.step()
+    S.close()
+    assert all(done[i]["status"] == C.OK for i in range(3))
+    ref = _alone(torch, cfg, mask, raw)
+    assert np.array_equal(out[0].cpu().numpy(), ref) and np.array_equal(out[1].cpu().numpy(), ref)
+    assert np.array_equal(out[2].cpu().numpy(), _alone(torch, other, mask, raw))
