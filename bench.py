@@ -296,11 +296,13 @@ def ablation(torch, C, scenes, n_scenes=4, seed=7000):
             "seconds": time.perf_counter() - t0, "table": table}
 
 
-def serve_workload(torch, C, scenes, n_req, rate, seed=5000):
+def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
     """Poisson arrivals of requests drawn from the uneven size mix, each with
     its own mask, photon level U{1..50} and iteration budget U{100..300},
     served by the library's continuous-batching engine; latency is arrival to
-    completion on the host clock."""
+    completion on the host clock.  With baseline: the same stream one request
+    at a time through the plain solver, both forms' capacity (all requests
+    present at the start), and both at 80 % of the engine's capacity."""
     dev = torch.device("cuda", 0)
     rng = np.random.Generator(np.random.PCG64(seed))
     # a few base scenes per shape; requests vary mask, noise and budget
@@ -339,43 +341,91 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000):
         else:
             cfg.max_iters = budget
         reqs.append((cfg, mask, raw, n * n * m * budget))
-    gaps = rng.exponential(1.0 / rate, size=n_req)
-    arrive = np.cumsum(gaps) - gaps[0]
+    gaps = rng.exponential(1.0, size=n_req)       # unit-rate gaps, scaled per run
     outs = [torch.empty(tuple(r[2].shape), dtype=torch.float32, device=dev) for r in reqs]
-    S = C.Server(200 << 30, slots=8, rounds=4, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nxt, done, lat = 0, 0, []
-    while done < n_req:
-        now = time.perf_counter() - t0
-        while nxt < n_req and arrive[nxt] <= now:
-            cfg, mask, raw, _ = reqs[nxt]
-            S.submit(cfg, mask, raw, outs[nxt], nxt)
-            nxt += 1
-        active, queued = S.step()
-        t = time.perf_counter() - t0
-        for c in S.poll():
-            if c["status"] != C.OK:
-                raise RuntimeError(f"request {c['id']} failed: {c['status']}")
-            lat.append(1e3 * (t - arrive[c["id"]]))
-            done += 1
-            if done % 16 == 0:
-                print(f"serve: {done}/{n_req} done at {t:.1f} s", file=sys.stderr, flush=True)
-        if active == 0 and queued == 0 and nxt < n_req:
-            time.sleep(max(0.0, arrive[nxt] - (time.perf_counter() - t0)))
-    makespan = time.perf_counter() - t0
-    S.close()
     vox = sum(r[3] for r in reqs)
-    return {
-        "requests": n_req, "rate_per_s": rate,
-        "mix": "scan grids 32/64/128, time bins 256/512/1024, masks 10-50%, both models, "
-               "photons U{1..50}, iteration budget U{100..300}",
-        "makespan_s": makespan,
-        "reconstructions_per_s": n_req / makespan,
-        "voxel_iters_per_s": vox / makespan,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "arena_bytes": 200 << 30, "slots_per_group": 8,
-    }
+
+    def arrivals(r):
+        a = np.cumsum(gaps / r) if r > 0 else np.zeros(n_req)
+        return a - a[0]
+
+    def served(arrive, tag):
+        """The stream through the continuous-batching engine."""
+        S = C.Server(200 << 30, slots=8, rounds=4, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nxt, done, lat = 0, 0, []
+        while done < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arrive[nxt] <= now:
+                cfg, mask, raw, _ = reqs[nxt]
+                S.submit(cfg, mask, raw, outs[nxt], nxt)
+                nxt += 1
+            active, queued = S.step()
+            t = time.perf_counter() - t0
+            for c in S.poll():
+                if c["status"] != C.OK:
+                    raise RuntimeError(f"request {c['id']} failed: {c['status']}")
+                lat.append(1e3 * (t - arrive[c["id"]]))
+                done += 1
+                if done % 32 == 0:
+                    print(f"serve ({tag}): {done}/{n_req} done at {t:.1f} s", file=sys.stderr,
+                          flush=True)
+            if active == 0 and queued == 0 and nxt < n_req:
+                time.sleep(max(0.0, arrive[nxt] - (time.perf_counter() - t0)))
+        makespan = time.perf_counter() - t0
+        S.close()
+        return makespan, lat
+
+    def one_at_a_time(arrive, tag):
+        """The same stream through the plain solver, first come first served:
+        each request runs alone (create + set_measurement + run + read) once it
+        has arrived and the one before it has finished."""
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat = []
+        for i, (cfg, mask, raw, _) in enumerate(reqs):
+            wait = arrive[i] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            P = C.Problem(cfg, mask, device=dev)
+            P.set_measurement(raw)
+            P.run()
+            outs[i].copy_(P.volume())
+            P.close()
+            torch.cuda.synchronize()
+            lat.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
+            if (i + 1) % 32 == 0:
+                print(f"one at a time ({tag}): {i + 1}/{n_req} done", file=sys.stderr, flush=True)
+        return time.perf_counter() - t0, lat
+
+    def stats(makespan, lat, r):
+        return {"arrival_rate_per_s": r, "makespan_s": makespan,
+                "reconstructions_per_s": n_req / makespan, "voxel_iters_per_s": vox / makespan,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99))}}
+
+    out = {"requests": n_req, "rate_per_s": rate,
+           "mix": "scan grids 32/64/128, time bins 256/512/1024, masks 10-50%, both models, "
+                  "photons U{1..50}, iteration budget U{100..300}",
+           "arena_bytes": 200 << 30, "slots_per_group": 8}
+    out["served"] = stats(*served(arrivals(rate), f"{rate:g}/s"), rate)
+    if baseline:
+        out["one_at_a_time"] = stats(*one_at_a_time(arrivals(rate), f"{rate:g}/s"), rate)
+        # capacity: every request present at the start, so service is never idle
+        cap_s = stats(*served(arrivals(0.0), "saturated"), None)
+        cap_1 = stats(*one_at_a_time(arrivals(0.0), "saturated"), None)
+        out["capacity_rec_per_s"] = {"served": cap_s["reconstructions_per_s"],
+                                     "one_at_a_time": cap_1["reconstructions_per_s"]}
+        # latency where the engine keeps up: arrivals at 80 % of its capacity
+        r = 0.8 * cap_s["reconstructions_per_s"]
+        out["at_sustainable_rate"] = {"served": stats(*served(arrivals(r), f"{r:.1f}/s"), r),
+                                      "one_at_a_time": stats(*one_at_a_time(arrivals(r),
+                                                                            f"{r:.1f}/s"), r)}
+    # headline figures of the served run at the requested rate
+    out.update({k: out["served"][k] for k in ("makespan_s", "reconstructions_per_s",
+                                               "voxel_iters_per_s", "latency_ms")})
+    return out
 
 
 def hq_bytes(n, m, layout=False):
@@ -693,6 +743,7 @@ def main():
         rep, _ = reconstruct()
     assert rep["total_iters"] == iters_per_rec, rep
 
+    print(f"bench: {args.workload} warm-up done", file=sys.stderr, flush=True)
     # one untimed profiled reconstruction picks the dominant kernel
     rep, prof_all = reconstruct(kinds=C.KERNEL_KINDS)
     dominant = max(prof_all, key=lambda k: prof_all[k][0])
@@ -778,6 +829,8 @@ def main():
         "roofline": roof,
         "context": {"paper_titan_rtx_alg2_seconds_64x64x512": 15.0},
     }
+    print(f"bench: timed region done ({ms_per_step:.1f} ms per reconstruction)", file=sys.stderr,
+          flush=True)
     if not args.no_other_workloads:
         # the other single-scene configurations, rates only
         result["other_workloads"] = {}
@@ -785,9 +838,11 @@ def main():
             if name != args.workload:
                 result["other_workloads"][name] = Workload(torch, C, scenes, name).summary(steps, 1)
                 torch.cuda.empty_cache()
+                print(f"bench: {name} workload done", file=sys.stderr, flush=True)
     if not args.no_batch:
         result["batched"] = batched_comparison(torch, C, scenes, MIX_SMALL)
     if not args.no_cpu_baseline:
+        print("bench: CPU baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(sc, wl, args.cpu_iters)
     print(json.dumps(result))
 
