@@ -114,6 +114,14 @@ struct SrvReq {
   long long submitted = 0;
 };
 
+// A group of scenes advanced by the same launches (one scene, or a batch at
+// a workspace stride), on the stream of its first scene.
+struct Group {
+  cnlos_problem* lead = nullptr;
+  std::vector<cnlos_problem*> mem;
+  Batch bt = kSingle;
+};
+
 // A slot group: a batch whose members change while it runs.
 struct SrvGroup {
   cnlos_config proto;
@@ -129,6 +137,14 @@ struct SrvGroup {
   std::vector<SrvReq> req;
   std::vector<SceneRun> run;
   std::vector<long long> admitted;
+  // rounds in flight: the members and runs they advance, and the event
+  // recorded after them on the group's stream
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  long long busy_since = 0;
+  Group view;
+  std::vector<SceneRun> vruns;
+  std::vector<int> vidx;
   int occupied() const {
     int k = 0;
     for (cnlos_problem* m : slot) k += m != nullptr;
@@ -142,6 +158,7 @@ struct cnlos_server {
   Arena arena;
   int K = 8, rounds = 8;
   long long step_no = 0;
+  long long enqueues = 0;     // order of the groups' rounds in flight
   int fail_next_groups = 0;   // test hook: slot-group creations to fail on purpose
   std::vector<SrvReq> queue;
   std::vector<SrvGroup*> groups;
@@ -763,13 +780,6 @@ float* field_ptr(cnlos_problem* p, int field, size_t* count) {
   }
 }
 
-// A group of scenes advanced by the same launches (one scene, or a batch at
-// a workspace stride), on the stream of its first scene.
-struct Group {
-  cnlos_problem* lead = nullptr;
-  std::vector<cnlos_problem*> mem;
-  Batch bt = kSingle;
-};
 
 // pull every member's controller with one stream synchronization
 cnlos_status group_pull(Group& g) {
@@ -1730,11 +1740,13 @@ cnlos_status srv_group_new(cnlos_server* sv, const cnlos_config& cfg, SrvGroup**
   g->run.resize(g->K);
   g->admitted.assign(g->K, 0);
   cnlos_problem* p = new (std::nothrow) cnlos_problem();
-  if (!p || hipStreamCreate(&g->st) != hipSuccess) {
+  if (!p || hipStreamCreate(&g->st) != hipSuccess ||
+      hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess) {
     delete p;
+    if (g->st) (void)hipStreamDestroy(g->st);
     sv->arena.give(off, bytes);
     delete g;
-    return srv_fail(CNLOS_EHIP, "stream creation failed");
+    return srv_fail(CNLOS_EHIP, "stream or event creation failed");
   }
   uint8_t* ws = sv->arena.base + g->slots_off;
   layout_problem(p, cfg, ws, stride, g->st, g->hq, false);
@@ -1783,6 +1795,7 @@ void srv_group_free(cnlos_server* sv, SrvGroup* g) {
     (void)hipStreamSynchronize(g->st);
     (void)hipStreamDestroy(g->st);
   }
+  if (g->done) (void)hipEventDestroy(g->done);
   delete g->layout;
   sv->arena.give(g->off, g->bytes);
   delete g;
@@ -1887,7 +1900,43 @@ cnlos_status cnlos_server_submit(cnlos_server* sv, const cnlos_request* r) {
 
 cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queued) {
   if (!sv) return fail(CNLOS_EINVAL, "server is NULL");
-  // admission, first come first served within each shape.  The queue is
+  // Groups advance independently: a group whose rounds have finished is
+  // absorbed, its finished requests retired, its free slots refilled and its
+  // next rounds enqueued, while the other groups' rounds keep running.
+  auto absorb = [&](SrvGroup* g) -> cnlos_status {
+    g->busy = false;
+    cnlos_status st = group_absorb(g->view, g->vruns);
+    if (st != CNLOS_OK) return st;
+    for (size_t j = 0; j < g->vidx.size(); ++j) g->run[g->vidx[j]] = g->vruns[j];
+    return CNLOS_OK;
+  };
+  bool progressed = false;
+  for (SrvGroup* g : sv->groups) {
+    if (!g->busy) continue;
+    const hipError_t q = hipEventQuery(g->done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(CNLOS_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    cnlos_status st = absorb(g);
+    if (st != CNLOS_OK) return st;
+    progressed = true;
+  }
+  // retire finished requests of idle groups: copy the volume out, free the slot
+  auto retire = [&]() {
+    for (SrvGroup* g : sv->groups) {
+      if (g->busy) continue;
+      for (int i = 0; i < g->K; ++i) {
+        cnlos_problem* m = g->slot[i];
+        if (!m || g->run[i].active) continue;
+        cnlos_status st = g->run[i].status;
+        if (st == CNLOS_OK) st = cnlos_get_volume(m, g->req[i].r.out_dev);
+        if (hipStreamSynchronize(g->st) != hipSuccess && st == CNLOS_OK) st = fail(CNLOS_EHIP, "stream failed");
+        srv_complete(sv, g, i, st);
+      }
+    }
+  };
+  retire();
+  // admission, first come first served within each shape, into idle groups
+  // (a request whose group is busy waits for its next step).  The queue is
   // rebuilt from the requests that keep waiting, so no exit path leaves an
   // admitted or moved-from request in it, and every request gets exactly one
   // completion.
@@ -1896,8 +1945,13 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
   for (SrvReq& q : pending) {
     SrvGroup* g = nullptr;
     int free_slot = -1;
+    bool shape_busy = false;
     for (SrvGroup* c : sv->groups) {
       if (!same_shared(c->proto, q.r.cfg) || !same_geometry(c->proto, q.r.cfg)) continue;
+      if (c->busy) {
+        shape_busy = true;
+        continue;
+      }
       for (int i = 0; i < c->K && free_slot < 0; ++i)
         if (!c->slot[i]) free_slot = i;
       if (free_slot >= 0) {
@@ -1905,12 +1959,16 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
         break;
       }
     }
+    if (!g && shape_busy) {
+      sv->queue.push_back(std::move(q));
+      continue;
+    }
     if (!g) {
       cnlos_status st = srv_group_new(sv, q.r.cfg, &g);
       if (st == CNLOS_ENOMEM && !g) {
-        // give back the arena of idle groups and try once more
+        // give back the arena of idle empty groups and try once more
         for (size_t k = 0; k < sv->groups.size();) {
-          if (sv->groups[k]->occupied() == 0) {
+          if (!sv->groups[k]->busy && sv->groups[k]->occupied() == 0) {
             srv_group_free(sv, sv->groups[k]);
             sv->groups.erase(sv->groups.begin() + k);
           } else {
@@ -1932,52 +1990,45 @@ cnlos_status cnlos_server_step(cnlos_server* sv, int32_t* active, int32_t* queue
     }
     srv_admit(sv, g, free_slot, q);
   }
-  // advance every group with occupants; all groups are enqueued before any wait
-  std::vector<Group> views(sv->groups.size());
-  std::vector<std::vector<SceneRun>> runs(sv->groups.size());
-  std::vector<std::vector<int>> idx(sv->groups.size());
-  std::vector<char> busy(sv->groups.size(), 0);
-  for (size_t k = 0; k < sv->groups.size(); ++k) {
-    SrvGroup* g = sv->groups[k];
-    Group& v = views[k];
+  // enqueue the next rounds of every idle group with occupants
+  for (SrvGroup* g : sv->groups) {
+    if (g->busy) continue;
+    Group& v = g->view;
     v.lead = g->layout;
     v.bt = Batch{g->K, g->stride, G_NONE, true};
+    v.mem.clear();
+    g->vruns.clear();
+    g->vidx.clear();
     for (int i = 0; i < g->K; ++i)
-      if (g->slot[i]) {
+      if (g->slot[i] && g->run[i].active) {
         v.mem.push_back(g->slot[i]);
-        runs[k].push_back(g->run[i]);
-        idx[k].push_back(i);
+        g->vruns.push_back(g->run[i]);
+        g->vidx.push_back(i);
       }
     if (v.mem.empty()) continue;
     bool e = false;
-    cnlos_status st = group_enqueue(v, runs[k], sv->rounds, &e);
+    cnlos_status st = group_enqueue(v, g->vruns, sv->rounds, &e);
     if (st != CNLOS_OK) return st;
-    busy[k] = 1;
+    if (hipEventRecord(g->done, g->st) != hipSuccess) return fail(CNLOS_EHIP, "hipEventRecord failed");
+    g->busy = true;
+    g->busy_since = ++sv->enqueues;
+    progressed = true;
   }
-  for (size_t k = 0; k < sv->groups.size(); ++k) {
-    if (!busy[k]) continue;
-    SrvGroup* g = sv->groups[k];
-    cnlos_status st = group_absorb(views[k], runs[k]);
-    if (st != CNLOS_OK) return st;
-    for (size_t j = 0; j < idx[k].size(); ++j) g->run[idx[k][j]] = runs[k][j];
-  }
-  ++sv->step_no;
-  // retire finished requests: copy the volume out, free the slot
-  int act = 0;
-  for (SrvGroup* g : sv->groups) {
-    for (int i = 0; i < g->K; ++i) {
-      cnlos_problem* m = g->slot[i];
-      if (!m) continue;
-      if (g->run[i].active) {
-        ++act;
-        continue;
-      }
-      cnlos_status st = g->run[i].status;
-      if (st == CNLOS_OK) st = cnlos_get_volume(m, g->req[i].r.out_dev);
-      if (hipStreamSynchronize(g->st) != hipSuccess && st == CNLOS_OK) st = fail(CNLOS_EHIP, "stream failed");
-      srv_complete(sv, g, i, st);
+  // nothing finished and nothing could start: wait for the oldest rounds
+  if (!progressed) {
+    SrvGroup* oldest = nullptr;
+    for (SrvGroup* g : sv->groups)
+      if (g->busy && (!oldest || g->busy_since < oldest->busy_since)) oldest = g;
+    if (oldest) {
+      if (hipEventSynchronize(oldest->done) != hipSuccess) return fail(CNLOS_EHIP, "hipEventSynchronize failed");
+      cnlos_status st = absorb(oldest);
+      if (st != CNLOS_OK) return st;
+      retire();
     }
   }
+  ++sv->step_no;
+  int act = 0;
+  for (SrvGroup* g : sv->groups) act += g->occupied();
   if (active) *active = act;
   if (queued) *queued = (int32_t)sv->queue.size();
   return CNLOS_OK;
