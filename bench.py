@@ -45,6 +45,8 @@ def parse():
                     choices=["small", "medium", "large", "batch", "serve", "ablation"])
     ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: Poisson arrival rate (1/s)")
+    ap.add_argument("--no-serve-baseline", action="store_true",
+                    help="serve: the stream through the engine only (no one-at-a-time runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=1)
     ap.add_argument("--profile-all", action="store_true",
@@ -302,7 +304,12 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
     served by the library's continuous-batching engine; latency is arrival to
     completion on the host clock.  With baseline: the same stream one request
     at a time through the plain solver, both forms' capacity (all requests
-    present at the start), and both at 80 % of the engine's capacity."""
+    present at the start), and both at 80 % of the engine's capacity.
+
+    A request's measurement is drawn on the device when it arrives (up to 256
+    requests: before the run) and dropped with its output when it completes;
+    arrived requests wait on the host until the engine's own queue is short,
+    so a long stream needs device memory only for what is in flight."""
     dev = torch.device("cuda", 0)
     rng = np.random.Generator(np.random.PCG64(seed))
     # a few base scenes per shape; requests vary mask, noise and budget
@@ -325,25 +332,29 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
             # empty near-wall bins; like scenes.poisson_counts, rates are clipped at 0
             clean = torch.clamp(clean, min=0.0)
             base[key] = (sc, clean / clean.max())
-        sc, clean = base[key]
+        sc, _ = base[key]
         mask = scenes.density_mask(n, float(rng.uniform(0.1, 0.5)), rng)
         photons = float(rng.integers(1, 51))
         budget = int(rng.integers(100, 301))
-        g = torch.Generator(device=dev)
-        g.manual_seed(int(seed * 7 + i))
-        lam = clean * photons + 0.01 * photons
-        assert float(lam.min()) >= 0.0
-        raw = torch.poisson(lam, generator=g)
         cfg = mix_config(C, sc, model)
         if model == "dual":
             cfg.init_iters = min(50, budget // 3)
             cfg.max_iters = budget - cfg.init_iters
         else:
             cfg.max_iters = budget
-        reqs.append((cfg, mask, raw, n * n * m * budget))
+        reqs.append((cfg, mask, key, photons, n * n * m * budget))
     gaps = rng.exponential(1.0, size=n_req)       # unit-rate gaps, scaled per run
-    outs = [torch.empty(tuple(r[2].shape), dtype=torch.float32, device=dev) for r in reqs]
-    vox = sum(r[3] for r in reqs)
+    vox = sum(r[4] for r in reqs)
+    pre = n_req <= 256
+
+    def measurement(i):
+        _, _, key, photons, _ = reqs[i]
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(seed * 7 + i))
+        lam = base[key][1] * photons + 0.01 * photons
+        return torch.poisson(lam, generator=g)
+
+    raws = [measurement(i) for i in range(n_req)] if pre else None
 
     def arrivals(r):
         a = np.cumsum(gaps / r) if r > 0 else np.zeros(n_req)
@@ -352,14 +363,20 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
     def served(arrive, tag):
         """The stream through the continuous-batching engine."""
         S = C.Server(200 << 30, slots=8, rounds=4, device=dev)
+        live = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        nxt, done, lat = 0, 0, []
+        nxt, done, lat, queued = 0, 0, [], 0
+        last = t0
         while done < n_req:
             now = time.perf_counter() - t0
-            while nxt < n_req and arrive[nxt] <= now:
-                cfg, mask, raw, _ = reqs[nxt]
-                S.submit(cfg, mask, raw, outs[nxt], nxt)
+            while nxt < n_req and arrive[nxt] <= now and queued < 32:
+                cfg, mask, _, _, _ = reqs[nxt]
+                raw = raws[nxt] if pre else measurement(nxt)
+                out = torch.empty(tuple(raw.shape), dtype=torch.float32, device=dev)
+                live[nxt] = (raw, out)
+                S.submit(cfg, mask, raw, out, nxt)
+                queued += 1
                 nxt += 1
             active, queued = S.step()
             t = time.perf_counter() - t0
@@ -367,10 +384,12 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
                 if c["status"] != C.OK:
                     raise RuntimeError(f"request {c['id']} failed: {c['status']}")
                 lat.append(1e3 * (t - arrive[c["id"]]))
+                live.pop(c["id"], None)
                 done += 1
-                if done % 32 == 0:
-                    print(f"serve ({tag}): {done}/{n_req} done at {t:.1f} s", file=sys.stderr,
-                          flush=True)
+            if time.perf_counter() - last > 20.0 or done == n_req:
+                last = time.perf_counter()
+                print(f"serve ({tag}): {done}/{n_req} done at {t:.1f} s", file=sys.stderr,
+                      flush=True)
             if active == 0 and queued == 0 and nxt < n_req:
                 time.sleep(max(0.0, arrive[nxt] - (time.perf_counter() - t0)))
         makespan = time.perf_counter() - t0
@@ -384,18 +403,22 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lat = []
-        for i, (cfg, mask, raw, _) in enumerate(reqs):
+        last = t0
+        for i, (cfg, mask, _, _, _) in enumerate(reqs):
             wait = arrive[i] - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(wait)
+            raw = raws[i] if pre else measurement(i)
             P = C.Problem(cfg, mask, device=dev)
             P.set_measurement(raw)
             P.run()
-            outs[i].copy_(P.volume())
+            out = P.volume()
             P.close()
+            del out, raw
             torch.cuda.synchronize()
             lat.append(1e3 * (time.perf_counter() - t0 - arrive[i]))
-            if (i + 1) % 32 == 0:
+            if time.perf_counter() - last > 20.0 or i + 1 == n_req:
+                last = time.perf_counter()
                 print(f"one at a time ({tag}): {i + 1}/{n_req} done", file=sys.stderr, flush=True)
         return time.perf_counter() - t0, lat
 
@@ -426,14 +449,6 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
     out.update({k: out["served"][k] for k in ("makespan_s", "reconstructions_per_s",
                                                "voxel_iters_per_s", "latency_ms")})
     return out
-
-
-def hq_bytes(n, m, layout=False):
-    """Bytes of the kernel spectrum H^ per convolution: the quarter (n + 1)^2
-    of each kt plane that its evenness in kx and ky determines (the method's
-    own bytes), or the full 2n x 2n plane the plane kernel reads, lane-ordered
-    so that its loads coalesce (the layout's bytes)."""
-    return (m + 1) * (4 * n * n if layout else (n + 1) * (n + 1)) * 8
 
 
 def algorithmic_bytes(kind, n, m, dual):
@@ -712,7 +727,8 @@ def main():
         }))
         return
     if args.workload == "serve":
-        sv = serve_workload(torch, C, scenes, args.requests, args.rate)
+        sv = serve_workload(torch, C, scenes, args.requests, args.rate,
+                            baseline=not args.no_serve_baseline)
         print(json.dumps({
             "metric": "voxel-ADMM-iters/s at 64^2x512 + reconstructions/s, p50/p99 latency",
             "value": sv["voxel_iters_per_s"], "unit": "voxel-ADMM-iters/s",
