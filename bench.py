@@ -451,6 +451,14 @@ def serve_workload(torch, C, scenes, n_req, rate, seed=5000, baseline=True):
     return out
 
 
+def hq_bytes(n, m, layout=False):
+    """Bytes of the kernel spectrum H^ per convolution: the quarter (n + 1)^2
+    of each kt plane that its evenness in kx and ky determines (the method's
+    own bytes), or the full 2n x 2n plane the plane kernel reads, lane-ordered
+    so that its loads coalesce (the layout's bytes)."""
+    return (m + 1) * (4 * n * n if layout else (n + 1) * (n + 1)) * 8
+
+
 def algorithmic_bytes(kind, n, m, dual):
     """Bytes a kernel kind must move per launch (inputs read once, outputs
     written once), averaged over its launches in one ADMM iteration."""

@@ -237,6 +237,27 @@ def test_algorithm1_literal_falloff_matches_oracle():
     assert err <= TOL_VOL
 
 
+def test_algorithm2_literal_falloff_matches_oracle():
+    """Algorithm 2 on the literal radiometric weight of eq. (3) (m = 32), with
+    a warm start: u and tau after 5 + 10 iterations."""
+    torch = need_gpu()
+    sc = scenes.scene_custom(16, 32, 63, wall=1.0, bin_ps=128.0, density=0.5, peak=40.0,
+                             background=0.5)
+    say("alg2 16x16x32 literal falloff 5+10")
+    raw, op, tau0, _ = _setup(sc, 64, falloff=O.FALLOFF_LITERAL)
+    L0o, L0d = _oracle_L0(op, True), _oracle_L0(op, False)
+    p = O.Params(**ALG2_P)
+    s1, s2 = O.run_alg2(tau0, op, p, 10, 5, L0_obj=L0o, L0_dual=L0d)
+    P = C.Problem(_alg2_cfg(sc, p, 10, 5, L0=L0o, L0_dual=L0d, falloff=C.FALLOFF_LITERAL),
+                  sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    P.run()
+    eu = rel_l2(to_host(P.volume()), s2.u)
+    et = rel_l2(to_host(P.signal()), s2.tau)
+    say(f"  rel L2 u = {eu:.3e}, tau = {et:.3e}")
+    assert eu <= TOL_VOL and et <= TOL_VOL
+
+
 def test_determinism_and_resume():
     torch = need_gpu()
     sc = scenes.scene_small()
