@@ -68,3 +68,43 @@ def test_benchmark_configuration_matches_the_stored_oracle_run():
     np.testing.assert_array_equal(log[:, 4], trials)        # rejections per iteration
     P.close()
 
+
+
+def test_large_configuration_first_iterations_match_the_stored_oracle_run():
+    """128x128x1024 (the large workload), one warm-start and one Algorithm-2
+    iteration against the stored full-size oracle run: 64 sampled scan
+    columns of u and tau within 1e-3 relative L2 (over the sample), the
+    volumes' norms and both logged energies within 1e-3, the step constants
+    identical."""
+    torch = need_gpu()
+    ref = np.load(golden_path("alg2_128x128x1024.npz"))
+    sc = scenes.scene_large()
+    say("alg2 128x128x1024 1+1 against the stored oracle run")
+    raw = _raw(sc, int(ref["seed"][0]), str(ref["raw_sha256"]))
+    pr = _params(ref)
+    L0o, L0d = (float(x) for x in ref["L0"])
+    i1, i2 = (int(x) for x in ref["iters"])
+    cfg = C.default_config(nx=sc.n, ny=sc.n, nt=sc.m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
+                           bin_ps=sc.bin_ps, model=C.MODEL_DUAL, max_iters=i2, init_iters=i1,
+                           a_u=pr["a_u"], b_u=pr["b_u"], a_tau=pr["a_tau"], b_tau=pr["b_tau"],
+                           warm_a=pr["a"], warm_b=pr["b"], mu=pr["mu"], lam=pr["lam"],
+                           L0=L0o, L0_dual=L0d)
+    P = C.Problem(cfg, sc.mask)
+    P.set_measurement(to_dev(torch, raw))
+    P.run(i1)
+    u1 = to_host(P.volume())
+    assert abs(np.linalg.norm(u1) - ref["u_norm"][1]) <= TOL_VOL * ref["u_norm"][1]
+    P.run()
+    u, tau = to_host(P.volume()), to_host(P.signal())
+    cols = ref["cols"]
+    eu = rel_l2(u[cols[:, 0], cols[:, 1]], ref["u_cols"])
+    et = rel_l2(tau[cols[:, 0], cols[:, 1]], ref["tau_cols"])
+    say(f"  sampled columns: rel L2 u = {eu:.3e}, tau = {et:.3e}")
+    assert eu <= TOL_VOL and et <= TOL_VOL
+    assert abs(np.linalg.norm(u) - ref["u_norm"][0]) <= TOL_VOL * ref["u_norm"][0]
+    assert abs(np.linalg.norm(tau) - ref["tau_norm"][0]) <= TOL_VOL * ref["tau_norm"][0]
+    log = P.log()
+    E = np.concatenate([ref["log1"][:, 0], ref["log2"][:, 0]])
+    assert np.max(np.abs(log[:, 0] - E) / np.abs(E)) <= TOL_VOL
+    np.testing.assert_array_equal(log[:, 3], np.concatenate([ref["log1"][:, 3], ref["log2"][:, 3]]))
+    P.close()
