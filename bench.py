@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="medium",
-                    choices=["small", "medium", "large", "batch", "serve", "ablation"])
+                    choices=["small", "medium", "large", "batch", "serve", "ablation", "nonconfocal"])
     ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=50.0, help="serve: Poisson arrival rate (1/s)")
     ap.add_argument("--no-serve-baseline", action="store_true",
@@ -702,6 +702,33 @@ class Workload:
         return out
 
 
+def nonconfocal_rates(torch, C):
+    """The non-confocal direct-sum operator (Section 2's general model) and its
+    transpose: milliseconds per application and paths per second at two grid
+    sizes (one application evaluates n^4 m detector-voxel paths)."""
+    out = {}
+    for (n, m) in ((32, 256), (64, 512)):
+        g = C.nc_geometry(n, m, 1.0, 16.0 * 512 / m, (0.2, 0.1), True)
+        gen = torch.Generator(device="cuda").manual_seed(n + m)
+        x = torch.rand((n, n, m), device="cuda", generator=gen)
+        y = torch.empty_like(x)
+        row = {}
+        for name, fn in (("forward", C.nc_apply), ("transpose", C.nc_apply_T)):
+            fn(g, x, y)
+            torch.cuda.synchronize()
+            reps = 5 if n <= 32 else 2
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn(g, x, y)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            row[name] = {"ms": ms, "paths_per_s": n ** 4 * m / (ms * 1e-3)}
+        out[f"{n}x{n}x{m}"] = row
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -748,6 +775,11 @@ def main():
             "reconstructions_per_s": sv["reconstructions_per_s"],
             "latency_ms": sv["latency_ms"], "serving": sv, "roofline": None,
         }))
+        return
+    if args.workload == "nonconfocal":
+        print(json.dumps({"metric": "non-confocal operator by direct summation",
+                          "data": "synthetic (uniform random volumes)",
+                          "nonconfocal": nonconfocal_rates(torch, C)}))
         return
     if args.workload == "ablation":
         ab = ablation(torch, C, scenes)
@@ -865,6 +897,8 @@ def main():
                 print(f"bench: {name} workload done", file=sys.stderr, flush=True)
     if not args.no_batch:
         result["batched"] = batched_comparison(torch, C, scenes, MIX_SMALL)
+    if not args.no_other_workloads:
+        result["nonconfocal"] = nonconfocal_rates(torch, C)
     if not args.no_cpu_baseline:
         print("bench: CPU baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(sc, wl, args.cpu_iters)

@@ -421,6 +421,66 @@ cnlos_status cnlos_server_usage(cnlos_server* s, uint64_t* bytes_used, int32_t* 
  * caller's). */
 cnlos_status cnlos_server_destroy(cnlos_server* s);
 
+/* ------------------------------------------------------------------------
+ * Non-confocal model (Section 2, general form; Section 5's non-confocal
+ * experiment).  One wall point is illuminated and an n x n detector grid is
+ * scanned.  With the wall normals along z the model's direction terms reduce to
+ * the volumetric albedo weight 1 / (d_i^2 d_d^2): d_i runs from the illuminated
+ * point to the voxel and d_d from the voxel to the detector, and the path
+ * d_i + d_d selects the time bin.  The model is not shift-invariant, so it has
+ * no light-cone (FFT) form.  These entry points apply it by direct summation
+ * over all n^4 m (detector, voxel) paths.  That suits small grids; the
+ * reconstruction route of Section 5 is the midpoint approximation below,
+ * followed by the confocal solver.
+ *
+ * Grid conventions (those of the confocal operator):
+ * - detector and voxel column (i, j) sit at x_i = (i + 1/2) W / n - W / 2;
+ * - depth bin k sits at z_k = (k + 1/2) R / m, with R = m c dt / 2;
+ * - time bin b holds path lengths in [b, b + 1) c dt;
+ * - paths beyond bin m - 1 are dropped.
+ *
+ * Volumes u and transients tau are float32 [n][n][m] (time/depth fastest),
+ * device pointers owned by the caller.  Time bins are decided in FP64.  Sums
+ * are FP64 in a fixed order, so results are bitwise reproducible.  The calls
+ * allocate nothing and keep no pointer.  Work is enqueued on hip_stream of the
+ * current device (asynchronous).  Geometry errors return before any device
+ * call.
+ * ------------------------------------------------------------------------ */
+typedef struct cnlos_nc_geometry {
+  int32_t n;              /* detectors (and voxel columns) per side, 1..256               */
+  int32_t m;              /* time bins = depth bins, 1..1024                              */
+  double wall_m;          /* wall extent W (square, centred at 0), metres                 */
+  double bin_ps;          /* time-bin width, picoseconds                                  */
+  double illum_x_m;       /* illuminated wall point, metres                               */
+  double illum_y_m;
+  int32_t literal;        /* 1: weight 1/(d_i^2 d_d^2); 0: weight 1 (paths only)          */
+} cnlos_nc_geometry;
+
+/* Check a geometry (no device work).  EINVAL for bad values, EUNSUPPORTED
+ * beyond the size limits. */
+cnlos_status cnlos_nc_validate(const cnlos_nc_geometry* g);
+
+/* tau = A_nc u: tau[i][j][b] sums w u over the voxels whose path from the
+ * illumination point through the voxel to detector (i, j) falls in bin b.
+ * u and tau may not alias.  Asynchronous. */
+cnlos_status cnlos_nc_apply(const cnlos_nc_geometry* g, const float* u_dev, float* tau_dev,
+                            void* hip_stream);
+
+/* u = A_nc^T tau: u[p][q][k] sums w tau[i][j][bin] over the detectors.  May not
+ * alias.  Asynchronous. */
+cnlos_status cnlos_nc_apply_T(const cnlos_nc_geometry* g, const float* tau_dev, float* u_dev,
+                              void* hip_stream);
+
+/* Midpoint approximation (Section 5's non-confocal experiment).  A detector
+ * at x_d under illumination x_i reads as a confocal measurement at the
+ * midpoint (x_i + x_d) / 2.  The midpoints of the detector grid form an n x n
+ * grid of extent W / 2 centred at half the illumination point.  The transient
+ * array is then reconstructed unchanged by the confocal solver, with
+ * wall_w_m = wall_h_m = *wall_m.  The confocal operator is shift-invariant, so
+ * the centre only places the result.  Host only. */
+cnlos_status cnlos_nc_midpoint(const cnlos_nc_geometry* g, double* wall_m, double* centre_x_m,
+                               double* centre_y_m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libcnlos.so")
-SOURCES = ["k_spectral.hip", "k_admm.hip", "api.hip"]
+SOURCES = ["k_spectral.hip", "k_admm.hip", "k_nonconfocal.hip", "api.hip"]
 ARCH = os.environ.get("CNLOS_OFFLOAD_ARCH", "gfx950")
 
 

@@ -70,6 +70,11 @@ class Completion(ctypes.Structure):
                 ("energy", c_double), ("queued_steps", c_double), ("served_steps", c_double)]
 
 
+class NcGeometry(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("m", c_int32), ("wall_m", c_double), ("bin_ps", c_double),
+                ("illum_x_m", c_double), ("illum_y_m", c_double), ("literal", c_int32)]
+
+
 class CnlosError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
@@ -126,6 +131,11 @@ def load() -> ctypes.CDLL:
         "cnlos_server_fail_next_groups": ([P, c_int32], c_int32),
         "cnlos_server_usage": ([P, POINTER(c_uint64), POINTER(c_int32)], c_int32),
         "cnlos_server_destroy": ([P], c_int32),
+        "cnlos_nc_validate": ([POINTER(NcGeometry)], c_int32),
+        "cnlos_nc_apply": ([POINTER(NcGeometry), P, P, P], c_int32),
+        "cnlos_nc_apply_T": ([POINTER(NcGeometry), P, P, P], c_int32),
+        "cnlos_nc_midpoint": ([POINTER(NcGeometry), POINTER(c_double), POINTER(c_double),
+                               POINTER(c_double)], c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -186,6 +196,54 @@ def apply_A_noalloc(cfg: Config, mask, u, out, masked=False, stream=None):
                                     c_void_p(u.data_ptr()), c_void_p(out.data_ptr()),
                                     int(bool(masked)), c_void_p(st.cuda_stream)))
     return out
+
+
+def nc_geometry(n, m, wall_m, bin_ps, illum, literal=True) -> NcGeometry:
+    """Geometry of the non-confocal operator: n x n detectors, m bins, a square
+    wall of extent wall_m, bin width bin_ps, illuminated wall point illum."""
+    return NcGeometry(int(n), int(m), float(wall_m), float(bin_ps), float(illum[0]),
+                      float(illum[1]), int(bool(literal)))
+
+
+def nc_validate(g: NcGeometry) -> int:
+    return load().cnlos_nc_validate(byref(g))
+
+
+def _nc_call(fn, g, src, out, stream):
+    import torch
+    shape = (g.n, g.n, g.m)
+    dev = src.device if isinstance(src, torch.Tensor) else None
+    if dev is None or dev.type != "cuda":
+        raise ValueError("expected CUDA tensors")
+    a = _dev_f32(src, shape, dev)
+    b = _dev_f32(out, shape, dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        check(fn(byref(g), a, b, c_void_p(st.cuda_stream)))
+    return out
+
+
+def nc_apply(g: NcGeometry, u, out=None, stream=None):
+    """tau = A_nc u (non-confocal model by direct summation); u and out are
+    contiguous float32 [n][n][m] device tensors.  Asynchronous on the stream."""
+    import torch
+    out = torch.empty_like(u) if out is None else out
+    return _nc_call(load().cnlos_nc_apply, g, u, out, stream)
+
+
+def nc_apply_T(g: NcGeometry, tau, out=None, stream=None):
+    """u = A_nc^T tau (the transpose)."""
+    import torch
+    out = torch.empty_like(tau) if out is None else out
+    return _nc_call(load().cnlos_nc_apply_T, g, tau, out, stream)
+
+
+def nc_midpoint(g: NcGeometry):
+    """Midpoint approximation: (wall extent of the confocal grid, (x, y) of its
+    centre) for reconstructing the transients with the confocal solver."""
+    w, cx, cy = c_double(), c_double(), c_double()
+    check(load().cnlos_nc_midpoint(byref(g), byref(w), byref(cx), byref(cy)))
+    return w.value, (cx.value, cy.value)
 
 
 def _dev_f32(t, shape, device):

@@ -17,6 +17,8 @@ using namespace cnlos;
 namespace {
 
 constexpr double kC = 299792458.0;
+constexpr int kNcMaxGrid = 256;     // non-confocal operator: detectors per side
+constexpr int kNcMaxBins = 1024;    // and time bins (the forward kernel's LDS histograms)
 thread_local std::string g_err;
 
 cnlos_status fail(cnlos_status s, const std::string& msg) {
@@ -1429,6 +1431,78 @@ cnlos_status cnlos_apply_A_noalloc(const cnlos_config* cfg, const uint8_t* mask_
   e.mask = masked ? p->mask : nullptr;
   HIPCHK(conv(p, src, false, EPI_PLAIN, e, nullptr));
   HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+// ------------------------------------------------ non-confocal operator
+}  // extern "C"
+
+namespace {
+
+cnlos_status nc_geo(const cnlos_nc_geometry* g, NcGeo* out) {
+  if (!g) return fail(CNLOS_EINVAL, "geometry is NULL");
+  if (g->n < 1 || g->m < 1) return fail(CNLOS_EINVAL, "n and m must be positive");
+  if (g->n > kNcMaxGrid) return fail(CNLOS_EUNSUPPORTED, "n must be at most " + std::to_string(kNcMaxGrid));
+  if (g->m > kNcMaxBins) return fail(CNLOS_EUNSUPPORTED, "m must be at most " + std::to_string(kNcMaxBins));
+  if (!finite_pos(g->wall_m)) return fail(CNLOS_EINVAL, "wall extent must be positive");
+  if (!finite_pos(g->bin_ps)) return fail(CNLOS_EINVAL, "bin_ps must be positive");
+  if (!isfinite(g->illum_x_m) || !isfinite(g->illum_y_m)) return fail(CNLOS_EINVAL, "illumination point must be finite");
+  if (g->literal != 0 && g->literal != 1) return fail(CNLOS_EINVAL, "literal must be 0 or 1");
+  out->n = g->n;
+  out->m = g->m;
+  out->wall = g->wall_m;
+  out->range = g->m * kC * (g->bin_ps * 1e-12) / 2.0;
+  out->cdt = kC * g->bin_ps * 1e-12;
+  out->ix = g->illum_x_m;
+  out->iy = g->illum_y_m;
+  out->literal = g->literal;
+  return CNLOS_OK;
+}
+
+cnlos_status nc_launch(const cnlos_nc_geometry* g, const float* in_dev, float* out_dev,
+                       void* hip_stream, bool transpose) {
+  NcGeo ng{};
+  cnlos_status s = nc_geo(g, &ng);
+  if (s != CNLOS_OK) return s;
+  if (!in_dev || !out_dev) return fail(CNLOS_EINVAL, "NULL volume");
+  if ((const void*)in_dev == (const void*)out_dev) return fail(CNLOS_EINVAL, "input and output may not alias");
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const hipError_t e = transpose ? launch_nc_transpose(ng, in_dev, out_dev, st)
+                                 : launch_nc_forward(ng, in_dev, out_dev, st);
+  if (e != hipSuccess)
+    return fail(CNLOS_EHIP, std::string(transpose ? "k_nc_transpose" : "k_nc_forward") + ": " +
+                                hipGetErrorString(e));
+  return CNLOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cnlos_status cnlos_nc_validate(const cnlos_nc_geometry* g) {
+  NcGeo ng{};
+  return nc_geo(g, &ng);
+}
+
+cnlos_status cnlos_nc_apply(const cnlos_nc_geometry* g, const float* u_dev, float* tau_dev,
+                            void* hip_stream) {
+  return nc_launch(g, u_dev, tau_dev, hip_stream, false);
+}
+
+cnlos_status cnlos_nc_apply_T(const cnlos_nc_geometry* g, const float* tau_dev, float* u_dev,
+                              void* hip_stream) {
+  return nc_launch(g, tau_dev, u_dev, hip_stream, true);
+}
+
+cnlos_status cnlos_nc_midpoint(const cnlos_nc_geometry* g, double* wall_m, double* centre_x_m,
+                               double* centre_y_m) {
+  NcGeo ng{};
+  cnlos_status s = nc_geo(g, &ng);
+  if (s != CNLOS_OK) return s;
+  if (!wall_m || !centre_x_m || !centre_y_m) return fail(CNLOS_EINVAL, "NULL output");
+  *wall_m = g->wall_m / 2.0;
+  *centre_x_m = g->illum_x_m / 2.0;
+  *centre_y_m = g->illum_y_m / 2.0;
   return CNLOS_OK;
 }
 

@@ -393,4 +393,16 @@ hipError_t launch_meas_finish(int logn, int logm, float* out, DevCtl* ctl, doubl
 hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, hipStream_t st);
 hipError_t launch_ctl_clear_halt(DevCtl* ctl, hipStream_t st);
 
+// Non-confocal direct-sum operator (k_nonconfocal.hip): n x n detectors and
+// voxel columns, m time/depth bins, wall extent W, depth range R = m c dt / 2,
+// path length per bin c dt, illumination point (ix, iy) on the wall.
+struct NcGeo {
+  int n, m;
+  double wall, range, cdt, ix, iy;
+  int literal;
+};
+size_t nc_forward_lds_bytes(int m);
+hipError_t launch_nc_forward(const NcGeo& g, const float* u, float* tau, hipStream_t st);
+hipError_t launch_nc_transpose(const NcGeo& g, const float* tau, float* u, hipStream_t st);
+
 }  // namespace cnlos

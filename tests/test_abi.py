@@ -23,7 +23,7 @@ def header_functions():
 def test_library_exports_every_declared_function():
     lib = C.load()
     names = header_functions()
-    assert len(names) == 35
+    assert len(names) == 39
     for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
@@ -38,10 +38,11 @@ def test_struct_layout_matches_header():
 #include <stdio.h>
 #include "cnlos.h"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
          offsetof(cnlos_config, power_iters), sizeof(cnlos_report), sizeof(cnlos_info),
          offsetof(cnlos_info, iter), offsetof(cnlos_config, eps_stop),
-         offsetof(cnlos_config, fista_restart));
+         offsetof(cnlos_config, fista_restart), sizeof(cnlos_nc_geometry),
+         offsetof(cnlos_nc_geometry, literal));
   return 0;
 }}
 """
@@ -54,7 +55,8 @@ int main(void) {{
         vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     assert vals == [ctypes.sizeof(C.Config), C.Config.lambda_.offset, C.Config.power_iters.offset,
                     ctypes.sizeof(C.Report), ctypes.sizeof(C.Info), C.Info.iter.offset,
-                    C.Config.eps_stop.offset, C.Config.fista_restart.offset]
+                    C.Config.eps_stop.offset, C.Config.fista_restart.offset,
+                    ctypes.sizeof(C.NcGeometry), C.NcGeometry.literal.offset]
 
 
 def test_defaults_follow_paper_parameters():
@@ -214,3 +216,34 @@ def test_server_submit_validates_without_a_device_call():
     assert lib.cnlos_server_destroy(h) == C.OK
     assert lib.cnlos_server_create(ctypes.c_void_p(1 << 20), ctypes.c_uint64(1 << 30), 0, 4,
                                    ctypes.byref(h)) == C.EINVAL
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n", 0, C.EINVAL), ("m", 0, C.EINVAL), ("n", 257, C.EUNSUPPORTED), ("m", 1025, C.EUNSUPPORTED),
+    ("wall_m", 0.0, C.EINVAL), ("wall_m", float("nan"), C.EINVAL), ("bin_ps", -1.0, C.EINVAL),
+    ("illum_x_m", float("inf"), C.EINVAL), ("literal", 2, C.EINVAL)])
+def test_nonconfocal_geometry_validation(field, value, status):
+    g = C.nc_geometry(8, 64, 0.8, 32.0, (0.1, -0.2))
+    assert C.nc_validate(g) == C.OK
+    setattr(g, field, value)
+    assert C.nc_validate(g) == status
+
+
+def test_nonconfocal_calls_validate_before_any_device_call():
+    lib = C.load()
+    g = C.nc_geometry(8, 64, 0.8, 32.0, (0.1, -0.2))
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.cnlos_nc_apply(ctypes.byref(g), None, fake, None) == C.EINVAL
+    assert lib.cnlos_nc_apply_T(ctypes.byref(g), fake, fake, None) == C.EINVAL   # aliasing
+    g.m = 0
+    assert lib.cnlos_nc_apply(ctypes.byref(g), fake, ctypes.c_void_p(1 << 21), None) == C.EINVAL
+
+
+def test_nonconfocal_midpoint_is_the_half_scale_grid():
+    """The midpoint helper gives W/2 and half the illumination point (Section 5's
+    midpoint approximation), the values the oracle's own helper gives."""
+    from oracle import cnlos_oracle as O
+    g = C.nc_geometry(8, 64, 0.8, 32.0, (0.2, -0.1))
+    wall, centre = C.nc_midpoint(g)
+    ow, oc = O.nonconfocal_midpoint_geometry(O.NonConfocalGeometry(8, 64, 0.8, 32.0, (0.2, -0.1)))
+    assert wall == ow and centre == oc
