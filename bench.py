@@ -463,7 +463,8 @@ def algorithmic_bytes(kind, n, m, dual):
     """Bytes a kernel kind must move per launch (inputs read once, outputs
     written once), averaged over its launches in one ADMM iteration."""
     V = n * n * m
-    spec_c = (m + 1) * n * n * 8          # convolution spectrum, complex64
+    spec_c = m * n * n * 8                # convolution spectrum, complex64: kt = 1 .. m - 1
+                                          # and the real planes kt = 0, m packed in one
     spec_s = (m // 2 + 1) * n * n * 8     # solve spectrum
     f = 4 * V
     if kind == "plane_conv":

@@ -10,7 +10,7 @@
 //   t pass   : per scan column, complex-to-real inverse FFT along t, crop,
 //              R_t^{-1} (S^T and the falloff weight), fused epilogue.
 // The t axis of the convolution is padded to 2m and the real input makes only
-// kt = 0..m necessary (the two real bins kt = 0, m share one plane for n <= 64);
+// kt = 0..m necessary (the two real bins kt = 0, m share one plane);
 // the (x, y) padding to 2n x 2n lives only inside the plane kernel: rows and
 // columns are transformed with their zero halves folded into twists, and the
 // n x n crop is taken before anything leaves the CU (n = 128 splits the plane
@@ -500,9 +500,10 @@ __device__ __forceinline__ void col_inv(float2 (&c)[PlaneRegCfg<LOGN>::RE], int 
 // forward column spectra Z^ of all 2n columns go to LDS (2n rows), then each
 // position combines its own value with the partner at (-kx, -ky):
 //   Y(k) = Z^(k) (H_0 + H_m)/2 + conj(Z^(-k)) (H_0 - H_m)/2,
-// the spectrum of conv(P_0) + i conv(P_m) (H_0, H_m real and even).
+// the spectrum of conv(P_0) + i conv(P_m) (H_0, H_m real and even).  Plane 0
+// of H^ holds the two factors as one pair (k_hq_pack_real).
 template <int LOGN>
-__device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* H0, const float2* Hm,
+__device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* Hab,
                                                        const float2* tws, const float2* twc,
                                                        int tid) {
   using PC = PlaneRegCfg<LOGN>;
@@ -533,10 +534,8 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
       const int fx = kxs + brev(r, LOGL - 3);
       const int pp = brev((L - fx) & (L - 1), LOGL);
       const float2 own = Y[p * YS + col], par = Y[pp * YS + colp];
-      const int q = (r * L + col) * 8 + s;                // lane-ordered H^
-      const float h0 = H0[q].x, hm = Hm[q].x;
-      const float a = 0.5f * (h0 + hm), b = 0.5f * (h0 - hm);
-      w[half][r] = make_float2(a * own.x + b * par.x, a * own.y - b * par.y);
+      const float2 ab = Hab[(r * L + col) * 8 + s];      // lane-ordered H^ plane 0
+      w[half][r] = make_float2(ab.x * own.x + ab.y * par.x, ab.x * own.y - ab.y * par.y);
     }
   }
   __syncthreads();                                 // every partner read before write-back
@@ -588,7 +587,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    plane_conv_cols_packed<LOGN>(Y, hq, hq + (size_t)gridDim.x * L * L, tws, twc, tid);
+    plane_conv_cols_packed<LOGN>(Y, hq, tws, twc, tid);
   } else {
     // 2n spectrum columns, 8 lanes each, two columns per lane group
     const int s = tid & 7;
@@ -635,7 +634,9 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
 //            conjugate), inverse, keep the first n rows
 //   rows:    n-point DIT back (untwisted for h = 1), accumulated in registers
 // and the sum over both halves is the cropped padded convolution.  A lane
-// group of 8 handles two rows / columns in turn.
+// group of 8 handles two rows / columns in turn.  Block 0 holds the packed
+// real planes kt = 0 and kt = m (half_cols_packed), so the launch has m
+// blocks, whole rounds of one block per CU.
 template <int LOGN>
 struct PlaneHalfCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 4 * N, G = NT / 8;
@@ -696,6 +697,126 @@ __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, co
   }
 }
 
+// bits of x reversed within `bits` (a constant after unrolling)
+__device__ __forceinline__ constexpr int rev_bits(int x, int bits) {
+  int y = 0;
+  for (int i = 0; i < bits; ++i) y |= ((x >> i) & 1) << (bits - 1 - i);
+  return y;
+}
+
+// Columns of block 0 of the half-split plane kernel, which holds the two real
+// planes kt = 0 and kt = m packed as Z = P_0 + i P_m.  As in
+// plane_conv_cols_packed, each spectrum position combines its own value with
+// the partner at (-kx, -ky):
+//   Y(k) = Z^(k) (H_0 + H_m)/2 + conj(Z^(-k)) (H_0 - H_m)/2
+// (the two factors as one pair in plane 0 of H^).  Negating ky keeps its
+// parity, so the partner column lies in the same half; a lane group takes a
+// column A and its partner B (ky_h and n - ky_h for h = 0, n - 1 - ky_h for
+// h = 1; group 0 of the even half the two self-partnered columns 0 and n/2).
+// In a column, position 8r + s holds kx = brev(8r + s); -kx sits at register
+// r' = brev(2^b - brev(r)) (b bits of r; r' = 0 for r = 0) and lane 7 - s, or
+// for r = 0 at the lane whose reversed index is -brev3(s) mod 8.  r and r'
+// share their highest set bit, so the lower and the upper half of the
+// registers pair only within themselves.
+// Registers hold one column spectrum per transform: A's spectrum (2n
+// entries) waits in the n LDS slots of A and the n of B while B is
+// transformed, and A's combined spectrum again while B is transformed back.
+template <int LOGN>
+__device__ __forceinline__ void half_cols_packed(int h, float2* Y, const float2* Hab,
+                                                 const float2* tws, const float2* twc, int g,
+                                                 int s) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int N = PC::N, YS = PC::YS;
+  constexpr int RE = PlaneRegCfg<LOGN>::RE, RH = RE / 2, LR = LOGN + 1 - 3;
+  const bool self = h == 0 && g == 0;
+  const int ka = g, kb = self ? N / 2 : (h == 0 ? N - g : N - 1 - g);
+  const int colA = brev(ka, LOGN), colB = brev(kb, LOGN);
+  auto slot = [&](int r, int col) -> float2& { return Y[(8 * r + s) * YS + col]; };
+  // A forward: upper half to A's slots; lower half to B's once B is loaded
+  float2 c[RE];
+  {
+    float2 a[RE];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) a[r] = slot(r, colA);
+    col_fwd<LOGN>(a, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RH; ++r) slot(r, colA) = a[r + RH];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) c[r] = slot(r, colB);
+#pragma unroll
+    for (int r = 0; r < RH; ++r) slot(r, colB) = a[r];
+  }
+  col_fwd<LOGN>(c, s, tws, twc);                   // B's spectrum in registers
+  const float2* HA = Hab + ((size_t)h * RE * N + colA) * 8 + s;
+  const float2* HB = Hab + ((size_t)h * RE * N + colB) * 8 + s;
+  const int lane = threadIdx.x & 63, base = lane & ~7;
+  const int s0 = brev((8 - brev(s, 3)) & 7, 3);            // partner lane of register 0
+  // value of the partner position of register r: lane s ^ 7, or s0 for r = 0
+  auto par = [&](float2 v, int r) {
+    const int src = base | (r == 0 ? s0 : (s ^ 7));
+    return make_float2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+  };
+  auto comb = [&](float2 own, float2 pv, float2 ab) {
+    return make_float2(ab.x * own.x + ab.y * pv.x, ab.x * own.y - ab.y * pv.y);
+  };
+  // combine the registers r0 .. r0 + RH - 1 of A (aa) and B (c) in place,
+  // pair by pair; the partner column of A is B, of B is A (each itself in
+  // group 0 of the even half)
+  float2 ua[RH], la[RH];
+  auto combine = [&](float2 (&aa)[RH], int r0) {
+#pragma unroll
+    for (int i = 0; i < RH; ++i) {
+      const int r = r0 + i;
+      const int rp = r == 0 ? 0 : rev_bits((RE - rev_bits(r, LR)) & (RE - 1), LR);
+      const int ip = rp - r0;
+      if (ip < i) continue;                        // the pair was done at r' (static)
+      const float2 pA_r = par(self ? aa[ip] : c[rp], r), pA_rp = par(self ? aa[i] : c[r], rp);
+      const float2 pB_r = par(self ? c[rp] : aa[ip], r), pB_rp = par(self ? c[r] : aa[i], rp);
+      const float2 nA_r = comb(aa[i], pA_r, HA[r * N * 8]);
+      const float2 nB_r = comb(c[r], pB_r, HB[r * N * 8]);
+      if (ip != i) {
+        const float2 nA_rp = comb(aa[ip], pA_rp, HA[rp * N * 8]);
+        const float2 nB_rp = comb(c[rp], pB_rp, HB[rp * N * 8]);
+        aa[ip] = nA_rp;
+        c[rp] = nB_rp;
+      }
+      aa[i] = nA_r;
+      c[r] = nB_r;
+      // one pair's H^ loads and shuffles at a time (no hoisting of all of them)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+#pragma unroll
+  for (int r = 0; r < RH; ++r) ua[r] = slot(r, colA);
+  combine(ua, RH);
+#pragma unroll
+  for (int r = 0; r < RH; ++r) la[r] = slot(r, colB);
+  combine(la, 0);
+  // A's combined spectrum to the slots, B back, then A back
+#pragma unroll
+  for (int r = 0; r < RH; ++r) {
+    slot(r, colA) = la[r];
+    slot(r, colB) = ua[r];
+  }
+  col_inv<LOGN>(c, s, tws, twc);
+  float2 ob[RH];
+#pragma unroll
+  for (int r = 0; r < RH; ++r) ob[r] = c[r];
+  {
+    float2 a[RE];
+#pragma unroll
+    for (int r = 0; r < RH; ++r) {
+      a[r] = slot(r, colA);
+      a[r + RH] = slot(r, colB);
+    }
+#pragma unroll
+    for (int r = 0; r < RH; ++r) slot(r, colB) = ob[r];
+    col_inv<LOGN>(a, s, tws, twc);
+#pragma unroll
+    for (int r = 0; r < RH; ++r) slot(r, colA) = a[r];
+  }
+}
+
 // inverse rows: n-point DIT of a row from LDS (untwisted for the odd half)
 template <int LOGN>
 __device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN], int h, int x,
@@ -713,13 +834,63 @@ __device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN]
   }
 }
 
+// One plane through the half-split transform: per ky half, rows forward,
+// columns (PACKED: block 0's pairs of partner columns, else the H^ product),
+// rows back, the odd half accumulated onto the even one.
+template <int LOGN, bool ADJ, bool PACKED>
+__device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const float2* Hp,
+                                                float2* Y, const float2* tws, const float2* twc,
+                                                int g, int s) {
+  using PC = PlaneHalfCfg<LOGN>;
+  constexpr int N = PC::N, G = PC::G, RN = PC::RN;
+  // even ky half; each thread owns plane elements (g + G i, 8 r + s) throughout
+  float2 v[2][RN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
+  half_rows_fwd<LOGN>(v, 0, Y, tws, twc, g, s);
+  __syncthreads();
+  if constexpr (PACKED) half_cols_packed<LOGN>(0, Y, Hp, tws, twc, g, s);
+  else half_cols<LOGN, ADJ>(0, Y, Hp, tws, twc, g, s);
+  __syncthreads();
+  // the odd half's input, then the even half's output in its place
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    float2 o[RN];
+    half_row_inv<LOGN>(o, 0, g + G * i, Y, tws, twc, s);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) P[(g + G * i) * N + 8 * r + s] = o[r];
+  }
+  __syncthreads();                                 // Y is rewritten by the odd half
+  half_rows_fwd<LOGN>(v, 1, Y, tws, twc, g, s);
+  __syncthreads();
+  if constexpr (PACKED) half_cols_packed<LOGN>(1, Y, Hp, tws, twc, g, s);
+  else half_cols<LOGN, ADJ>(1, Y, Hp, tws, twc, g, s);
+  __syncthreads();
+#pragma unroll 1
+  for (int i = 0; i < 2; ++i) {
+    float2 o[RN];
+    half_row_inv<LOGN>(o, 1, g + G * i, Y, tws, twc, s);
+#pragma unroll
+    for (int r = 0; r < RN; ++r) {
+      float2* q = P + (g + G * i) * N + 8 * r + s;
+      *q = cadd(*q, o[r]);
+    }
+  }
+}
+
 template <int LOGN, bool ADJ>
 __global__ void __launch_bounds__(PlaneHalfCfg<LOGN>::NT)
 k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
                   const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
                   size_t zs, size_t hzs, int gate) {
   using PC = PlaneHalfCfg<LOGN>;
-  constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, RN = PC::RN, YS = PC::YS;
+  constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, YS = PC::YS;
   static_assert(2 * G == N, "two rows per lane group");
   __shared__ float2 Y[N * YS];
   __shared__ float2 tws[N];
@@ -737,43 +908,10 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
   for (int i = tid; i < N; i += NT) tws[i] = tw[i];
   for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
   __syncthreads();
-  // even ky half; each thread owns plane elements (g + G i, 8 r + s) throughout
-  float2 v[2][RN];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
-  half_rows_fwd<LOGN>(v, 0, Y, tws, twc, g, s);
-  __syncthreads();
-  half_cols<LOGN, ADJ>(0, Y, Hp, tws, twc, g, s);
-  __syncthreads();
-  // the odd half's input, then the even half's output in its place
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
-#pragma unroll 1
-  for (int i = 0; i < 2; ++i) {
-    float2 o[RN];
-    half_row_inv<LOGN>(o, 0, g + G * i, Y, tws, twc, s);
-#pragma unroll
-    for (int r = 0; r < RN; ++r) P[(g + G * i) * N + 8 * r + s] = o[r];
-  }
-  __syncthreads();                                 // Y is rewritten by the odd half
-  half_rows_fwd<LOGN>(v, 1, Y, tws, twc, g, s);
-  __syncthreads();
-  half_cols<LOGN, ADJ>(1, Y, Hp, tws, twc, g, s);
-  __syncthreads();
-#pragma unroll 1
-  for (int i = 0; i < 2; ++i) {
-    float2 o[RN];
-    half_row_inv<LOGN>(o, 1, g + G * i, Y, tws, twc, s);
-#pragma unroll
-    for (int r = 0; r < RN; ++r) {
-      float2* q = P + (g + G * i) * N + 8 * r + s;
-      *q = cadd(*q, o[r]);
-    }
-  }
+  // block 0: the packed real planes kt = 0 and kt = m, a separate path so that
+  // its register demand does not weigh on the other blocks' code
+  if (blockIdx.x == 0) plane_half_body<LOGN, ADJ, true>(P, Hp, Y, tws, twc, g, s);
+  else plane_half_body<LOGN, ADJ, false>(P, Hp, Y, tws, twc, g, s);
 }
 
 // Register-resident plane kernel of the diagonal solve (n <= 128): rows and
@@ -1566,8 +1704,8 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
                             int epi, const ConvEpi& ep, const DevCtl* ctl, const Batch& bt,
                             hipStream_t st, Prof* prof, bool tfwd_done, const RhsSrc* rhs_next) {
   constexpr int N = 1 << LOGN, M = 1 << LOGM, NN = N * N;
-  // the register plane kernel takes the real planes kt = 0, m packed in one
-  constexpr bool PK = LOGN <= 6;
+  // the plane kernels take the real planes kt = 0, m packed in one (block 0)
+  constexpr bool PK = true;
   using TG = TGeo<LOGM>;
   const int nb = NN / TG::J;
   const int nz = bt.nz, g = bt.gate;
@@ -1591,12 +1729,12 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
   } else {
     if (adjoint)
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, true>), dim3(M + 1, 1, nz),
+                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, true>), dim3(M, 1, nz),
                                      dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
                                      tb.twc_xy, ctl, zs, hzs, g));
     else
       CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, false>), dim3(M + 1, 1, nz),
+                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, false>), dim3(M, 1, nz),
                                      dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
                                      tb.twc_xy, ctl, zs, hzs, g));
   }
@@ -1668,7 +1806,7 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& r
   if (fwd_next) {
     // with the forward t pass of the convolution of the result
     using TC = TGeo<LOGM>;
-    constexpr bool PK = LOGN <= 6;
+    constexpr bool PK = true;
     CNLOS_TIMED(prof, KK_T_INV_SOLVE, st,
                 hipLaunchKernelGGL((k_tinv_solve_fwd<LOGM, PK>), dim3(NN / TC::J, 1, nz),
                                    dim3(TC::NT), 0, st, spec, NN, tb.S, tb.tw_t, tb.twc_t, ep,
@@ -1720,6 +1858,18 @@ hipError_t launch_solve(int logn, int logm, const Tables& tb, const float* rhs, 
                     fwd_next, tfwd_done)
 }
 
+// The real planes kt = 0 and kt = m are transformed together (packed as
+// P_0 + i P_m), and the product with H^ separates into (H_0 + H_m)/2 times the
+// value plus (H_0 - H_m)/2 times the partner's conjugate (both H^ planes are
+// real).  Plane 0 of H^ therefore holds that pair of real factors,
+// ((H_0 + H_m)/2, (H_0 - H_m)/2), one load per position; plane m is not read.
+__global__ void __launch_bounds__(256) k_hq_pack_real(float2* __restrict__ hq, int m, int plane) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= plane) return;
+  const float h0 = hq[q].x, hm = hq[(size_t)m * plane + q].x;
+  hq[q] = make_float2(0.5f * (h0 + hm), 0.5f * (h0 - hm));
+}
+
 hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const double2* etab,
                            const double* cosn, double invZ, hipStream_t st) {
   const int m = 1 << logm, n1 = (1 << logn) + 1;
@@ -1744,6 +1894,10 @@ hipError_t launch_build_hq(int logn, int logm, float2* hq, const int* dq, const 
     default: return hipErrorInvalidValue;
   }
 #undef CNLOS_HQ
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int plane = 4 << (2 * logn);
+  hipLaunchKernelGGL(k_hq_pack_real, dim3((plane + 255) / 256), dim3(256), 0, st, hq, m, plane);
   return hipGetLastError();
 }
 
