@@ -18,6 +18,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -108,8 +109,9 @@ def mix_config(C, sc, model):
 def batched_comparison(torch, C, scenes, mix):
     """Reconstructions/s of an uneven scene mix, one scene at a time against
     the batched form (scenes grouped by shape and model, one launch per kernel
-    per group, groups overlapping on their own streams).  Both include create
-    (H^, step constants), set_measurement, the run and the read-back."""
+    per group, groups set up from their own host threads and overlapping on
+    their own streams).  Both include create (H^, step constants),
+    set_measurement, the run and the read-back."""
     dev = torch.device("cuda", 0)
     items = make_mix(mix)
     # measurements: literal-falloff forward model of the library + seeded Poisson noise
@@ -145,15 +147,20 @@ def batched_comparison(torch, C, scenes, mix):
         groups = {}
         for i, ((sc, model), c) in enumerate(zip(items, cfgs)):
             groups.setdefault((sc.n, sc.m, model), []).append(i)
-        bs = []
-        for idx in groups.values():
+
+        # every group is set up from its own host thread on its own stream, so
+        # the groups' set-up launches overlap on the device
+        def make(idx):
             st = torch.cuda.Stream(device=dev)
             B = C.Batch([cfgs[i] for i in idx], [items[i][0].mask for i in idx], device=dev,
                         stream=st)
             with torch.cuda.stream(st):
                 for mem, i in zip(B.members, idx):
                     mem.set_measurement(raws[i])
-            bs.append((B, idx, st))
+            return B, idx, st
+
+        with ThreadPoolExecutor(max_workers=len(groups)) as ex:
+            bs = list(ex.map(make, list(groups.values())))
         status, _ = C.run_many([b for b, _, _ in bs])
         if status != C.OK:
             raise RuntimeError(C.last_error())

@@ -51,9 +51,13 @@ struct Carver {
   }
 };
 
+// defer_steps: return once the tables and H^ are built; the caller estimates
+// the step constants (possibly for several problems at once) and calls
+// finish_create
 cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
                          uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out,
-                         float2* shared_hq = nullptr, bool own_hq = true);
+                         float2* shared_hq = nullptr, bool own_hq = true, bool defer_steps = false);
+cnlos_status finish_create(cnlos_problem* p, double est_masked, double est_unmasked);
 cnlos_status destroy_problem(cnlos_problem* p);
 
 }  // namespace
@@ -503,6 +507,7 @@ Vol role_of(const cnlos_problem* p, int r) {
 }
 
 inline Vol fixed(const float* q) { return Vol{{const_cast<float*>(q), nullptr, nullptr}, -1}; }
+inline float* zsh_host(float* q, size_t off) { return reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(q) + off); }
 
 // One padded convolution of the problem (forward or adjoint).
 hipError_t conv(cnlos_problem* p, const ConvSrc& src, bool adjoint, int epi, const ConvEpi& ep,
@@ -511,11 +516,16 @@ hipError_t conv(cnlos_problem* p, const ConvSrc& src, bool adjoint, int epi, con
                      &p->prof);
 }
 
-// ||B||^2 by power iteration (B = A_D when masked, else A), from the ones vector.
-cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
+// ||B||^2 by power iteration (B = A_D when masked, else A), from the ones
+// vector, for the bt.nz problems mem[0..nz) of one layout that follow p = mem[0]
+// at the workspace stride bt.zs (one launch per step for all of them, each
+// with its own mask and estimate); est[i] receives member i's estimate.
+cnlos_status power_estimate(cnlos_problem* p, const Batch& bt, cnlos_problem* const* mem,
+                            bool masked, double* est) {
   float* X = p->AU[0];
   float* Y = p->AU[1];
-  HIPCHK(launch_fill(X, p->V, (float)(1.0 / sqrt((double)p->V)), p->st));
+  for (int i = 0; i < bt.nz; ++i)
+    HIPCHK(launch_fill(zsh_host(X, i * bt.zs), p->V, (float)(1.0 / sqrt((double)p->V)), p->st));
   for (int it = 0; it < p->cfg.power_iters; ++it) {
     ConvSrc s1{};
     s1.a = fixed(X);
@@ -527,7 +537,8 @@ cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
     e1.au_prev = fixed(nullptr);
     e1.w = p->wk;
     e1.mask = masked ? p->mask : nullptr;
-    HIPCHK(conv(p, s1, false, EPI_PLAIN, e1, nullptr));
+    HIPCHK(launch_conv(p->logn, p->logm, p->tb, s1, p->spec, false, EPI_PLAIN, e1, nullptr, bt,
+                       p->st, &p->prof));
     ConvSrc s2{};
     s2.a = fixed(Y);
     s2.b = fixed(nullptr);
@@ -538,14 +549,21 @@ cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
     e2.au = fixed(nullptr);
     e2.au_prev = fixed(nullptr);
     e2.partials = p->partials;
-    HIPCHK(conv(p, s2, true, EPI_NORM, e2, nullptr));
-    HIPCHK(launch_pow_finalize(p->ctl, p->partials, p->nb_conv, p->st));
+    HIPCHK(launch_conv(p->logn, p->logm, p->tb, s2, p->spec, true, EPI_NORM, e2, nullptr, bt,
+                       p->st, &p->prof));
+    HIPCHK(launch_pow_finalize(p->ctl, p->partials, p->nb_conv, bt, p->st));
   }
-  cnlos_status s = ctl_pull(p);
-  if (s != CNLOS_OK) return s;
-  *est = p->ctl_host->pow_est;
-  if (!isfinite(*est) || *est <= 0.0) return fail(CNLOS_ENONFINITE, "power iteration gave no positive norm estimate");
+  for (int i = 0; i < bt.nz; ++i) {
+    cnlos_status s = ctl_pull(mem[i]);
+    if (s != CNLOS_OK) return s;
+    est[i] = mem[i]->ctl_host->pow_est;
+    if (!isfinite(est[i]) || est[i] <= 0.0)
+      return fail(CNLOS_ENONFINITE, "power iteration gave no positive norm estimate");
+  }
   return CNLOS_OK;
+}
+cnlos_status power_estimate(cnlos_problem* p, bool masked, double* est) {
+  return power_estimate(p, kSingle, &p, masked, est);
 }
 
 cnlos_status reset_state(cnlos_problem* p) {
@@ -1229,7 +1247,7 @@ cnlos_status build_tables(cnlos_problem* p, const cnlos_config* cfg, const uint8
 
 cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void* workspace_dev,
                          uint64_t workspace_bytes, void* hip_stream, cnlos_problem** out,
-                         float2* shared_hq, bool own_hq) {
+                         float2* shared_hq, bool own_hq, bool defer_steps) {
   if (!out) return fail(CNLOS_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mask_host) return fail(CNLOS_EINVAL, "mask is NULL");
@@ -1271,24 +1289,29 @@ cnlos_status create_into(const cnlos_config* cfg, const uint8_t* mask_host, void
   c.meas_scale = 0.0;
   s = ctl_push(p);   // also waits for the tables and H^
   if (s != CNLOS_OK) return s;
-  if (cfg->model == CNLOS_MODEL_OPERATOR) return CNLOS_OK;
+  if (cfg->model == CNLOS_MODEL_OPERATOR || defer_steps) return CNLOS_OK;
 
-  double L0o = cfg->L0, L0d = cfg->L0_dual;
+  double em = 0.0, eu = 0.0;
   if (cfg->L0 <= 0.0) {
-    double est = 0.0;
-    s = power_estimate(p, true, &est);
+    s = power_estimate(p, true, &em);
     if (s != CNLOS_OK) return s;
-    L0o = 2.0 * est;
   }
-  if (cfg->model != CNLOS_MODEL_DUAL) {
-    L0d = L0o;
-  } else if (cfg->L0_dual <= 0.0) {
-    double est = 0.0;
-    s = power_estimate(p, false, &est);
+  if (cfg->model == CNLOS_MODEL_DUAL && cfg->L0_dual <= 0.0) {
+    s = power_estimate(p, false, &eu);
     if (s != CNLOS_OK) return s;
-    L0d = 2.0 * est;
   }
-  s = ctl_pull(p);
+  return finish_create(p, em, eu);
+}
+
+// Step constants L0 = 2 est ||A_D||^2 (masked) and, for the dual model,
+// 2 est ||A||^2 (unmasked), unless the configuration gives them; then the
+// initial state.
+cnlos_status finish_create(cnlos_problem* p, double est_masked, double est_unmasked) {
+  const cnlos_config* cfg = &p->cfg;
+  const double L0o = cfg->L0 > 0.0 ? cfg->L0 : 2.0 * est_masked;
+  const double L0d = cfg->model != CNLOS_MODEL_DUAL ? L0o
+                     : (cfg->L0_dual > 0.0 ? cfg->L0_dual : 2.0 * est_unmasked);
+  cnlos_status s = ctl_pull(p);
   if (s != CNLOS_OK) return s;
   p->ctl_host->L0_obj = L0o;
   p->ctl_host->L0_dual = L0d;
@@ -1674,6 +1697,60 @@ cnlos_status cnlos_destroy(cnlos_problem* p) {
 }
 
 // ---------------------------------------------------------------- batches
+}  // extern "C"
+
+namespace {
+
+// Step constants of a batch's members with the batch's launches: the masked
+// estimates of all members at once (each with its own mask), and the
+// unmasked one (dual model) once when the members share the geometry, since
+// it depends on nothing else.  Members that give their constants, or that
+// differ in power_iters, estimate alone.  Every estimate is the same
+// fixed-order computation as for a problem created alone, so the constants
+// are bitwise the same.
+cnlos_status batch_step_constants(cnlos_batch* b) {
+  const int K = (int)b->mem.size();
+  cnlos_problem* lead = b->mem[0];
+  const Batch bt{K, b->stride, G_NONE, b->hq_shared};
+  std::vector<double> em(K, 0.0), eu(K, 0.0);
+  bool all_m = true, all_u = true, same_iters = true;
+  const bool dual = lead->cfg.model == CNLOS_MODEL_DUAL;
+  for (cnlos_problem* m : b->mem) {
+    all_m = all_m && m->cfg.L0 <= 0.0;
+    all_u = all_u && dual && m->cfg.L0_dual <= 0.0;
+    same_iters = same_iters && m->cfg.power_iters == lead->cfg.power_iters;
+  }
+  cnlos_status s = CNLOS_OK;
+  if (all_m && same_iters) {
+    s = power_estimate(lead, bt, b->mem.data(), true, em.data());
+  } else {
+    for (int i = 0; i < K && s == CNLOS_OK; ++i)
+      if (b->mem[i]->cfg.L0 <= 0.0) s = power_estimate(b->mem[i], true, &em[i]);
+  }
+  if (s != CNLOS_OK) return s;
+  if (dual) {
+    if (all_u && same_iters && b->hq_shared) {
+      s = power_estimate(lead, false, &eu[0]);
+      for (int i = 1; i < K; ++i) eu[i] = eu[0];
+    } else if (all_u && same_iters) {
+      s = power_estimate(lead, bt, b->mem.data(), false, eu.data());
+    } else {
+      for (int i = 0; i < K && s == CNLOS_OK; ++i)
+        if (b->mem[i]->cfg.L0_dual <= 0.0) s = power_estimate(b->mem[i], false, &eu[i]);
+    }
+    if (s != CNLOS_OK) return s;
+  }
+  for (int i = 0; i < K; ++i) {
+    s = finish_create(b->mem[i], em[i], eu[i]);
+    if (s != CNLOS_OK) return s;
+  }
+  return CNLOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 cnlos_status cnlos_batch_workspace_bytes(const cnlos_config* cfg, int32_t count, uint64_t* bytes) {
   if (!bytes) return fail(CNLOS_EINVAL, "bytes is NULL");
   if (count < 1) return fail(CNLOS_EINVAL, "count must be >= 1");
@@ -1717,14 +1794,14 @@ cnlos_status cnlos_batch_create(const cnlos_config* cfgs, int32_t count,
     cnlos_problem* m = nullptr;
     float2* shared = (b->hq_shared && i > 0) ? b->mem[0]->hq : nullptr;
     cnlos_status s = create_into(&cfgs[i], masks_host[i], (uint8_t*)workspace_dev + stride * i, stride,
-                                 hip_stream, &m, shared, true);
+                                 hip_stream, &m, shared, true, true);
     if (m) {
       m->in_batch = true;
       b->mem.push_back(m);
     }
     if (s != CNLOS_OK) return s;
   }
-  return CNLOS_OK;
+  return batch_step_constants(b);
 }
 
 cnlos_status cnlos_batch_member(cnlos_batch* b, int32_t i, cnlos_problem** out) {

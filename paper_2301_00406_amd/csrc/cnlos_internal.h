@@ -390,7 +390,8 @@ hipError_t launch_meas_prep(int logn, int logm, const float* raw, const uint8_t*
                             const float* r3, float* out, double* partials, hipStream_t st);
 hipError_t launch_meas_finish(int logn, int logm, float* out, DevCtl* ctl, double* partials,
                               hipStream_t st);
-hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, hipStream_t st);
+hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, const Batch& bt,
+                               hipStream_t st);
 hipError_t launch_ctl_clear_halt(DevCtl* ctl, hipStream_t st);
 
 // Non-confocal direct-sum operator (k_nonconfocal.hip): n x n detectors and

@@ -582,7 +582,11 @@ k_meas_scale(float* __restrict__ out, const DevCtl* ctl, int logn, int logm) {
     out[g] *= inv;
 }
 
-__global__ void __launch_bounds__(256) k_pow_finalize(DevCtl* ctl, const double* __restrict__ partials, int nb) {
+__global__ void __launch_bounds__(256) k_pow_finalize(DevCtl* ctl, const double* __restrict__ partials,
+                                                      int nb, size_t zs) {
+  const size_t zo = (size_t)blockIdx.z * zs;
+  ctl = zsh(ctl, zo);
+  partials = zsh(partials, zo);
   const double s = block_sum_partials(partials, SL_NORM, nb, kMaxBlocks);
   if (threadIdx.x == 0) ctl->pow_est = sqrt(s);
 }
@@ -695,8 +699,9 @@ hipError_t launch_meas_finish(int logn, int logm, float* out, DevCtl* ctl, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_pow_finalize, dim3(1), dim3(256), 0, st, ctl, partials, nb);
+hipError_t launch_pow_finalize(DevCtl* ctl, const double* partials, int nb, const Batch& bt,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_pow_finalize, dim3(1, 1, bt.nz), dim3(256), 0, st, ctl, partials, nb, bt.zs);
   return hipGetLastError();
 }
 
