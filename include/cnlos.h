@@ -310,6 +310,41 @@ cnlos_status cnlos_destroy(cnlos_problem* p);
 const char* cnlos_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Launch plans (autotuning).  A plan holds layout choices of the plane
+ * kernels of the zero-padded 3-D FFT: the LDS row pads of their transposes.
+ * The pads decide only where values sit in LDS (bank conflicts), never a
+ * result: every plan gives bitwise the same results.  A problem starts with
+ * the plan that cnlos_tune last measured for its shape on the current device
+ * (in this process), or with the defaults (convolution pad 2; solve pad 2 at
+ * nx = 64, 4 at nx = 128, 8 otherwise).  A batch runs with its first member's
+ * plan; a serving slot group with the plan of its shape when it is created.
+ * ------------------------------------------------------------------------ */
+typedef struct cnlos_plan {
+  int32_t conv_row_pad;       /* plane kernel of the convolution: 1, 2 or 4                  */
+  int32_t solve_row_pad;      /* plane kernel of the diagonal solve: 2, 4 or 8               */
+  int32_t tuned;              /* 1 when these figures were measured by the call              */
+  int32_t reserved;
+  double conv_plane_us[3];    /* measured plane pass of one convolution, pads 1, 2, 4 (us)  */
+  double solve_plane_us[3];   /* measured plane pass of one solve, pads 2, 4, 8 (us)        */
+} cnlos_plan;
+
+/* Measure every candidate pad on this problem's workspace (a few convolutions
+ * and solves each, timed with HIP events on its stream), keep the fastest for
+ * the problem and for later problems of its shape (a candidate replaces the
+ * default only when it is more than 2% faster), and fill *out (may be
+ * NULL).  Overwrites the A u buffers, so a solver problem's iteration state
+ * is reset (the measurement is kept).  Not for batch members (ESTATE).
+ * Synchronizes the stream. */
+cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out);
+
+/* The problem's current plan (tuned = 0, no timings). */
+cnlos_status cnlos_get_plan(cnlos_problem* p, cnlos_plan* out);
+
+/* Use the given pads for this problem (EINVAL for other values; ESTATE for
+ * batch members). */
+cnlos_status cnlos_set_plan(cnlos_problem* p, const cnlos_plan* plan);
+
+/* ------------------------------------------------------------------------
  * Batches: several problems that advance together, one kernel launch per
  * step of the iteration for all of them (launch grid z = problem).  The
  * scenes are independent reconstructions (Sections 3 and 4.1 per scene); the

@@ -70,6 +70,18 @@ class Completion(ctypes.Structure):
                 ("energy", c_double), ("queued_steps", c_double), ("served_steps", c_double)]
 
 
+class Plan(ctypes.Structure):
+    _fields_ = [("conv_row_pad", c_int32), ("solve_row_pad", c_int32), ("tuned", c_int32),
+                ("reserved", c_int32), ("conv_plane_us", c_double * 3),
+                ("solve_plane_us", c_double * 3)]
+
+
+def _plan_dict(pl):
+    return {"conv_row_pad": pl.conv_row_pad, "solve_row_pad": pl.solve_row_pad,
+            "tuned": bool(pl.tuned), "conv_plane_us": list(pl.conv_plane_us),
+            "solve_plane_us": list(pl.solve_plane_us)}
+
+
 class NcGeometry(ctypes.Structure):
     _fields_ = [("n", c_int32), ("m", c_int32), ("wall_m", c_double), ("bin_ps", c_double),
                 ("illum_x_m", c_double), ("illum_y_m", c_double), ("literal", c_int32)]
@@ -131,6 +143,9 @@ def load() -> ctypes.CDLL:
         "cnlos_server_fail_next_groups": ([P, c_int32], c_int32),
         "cnlos_server_usage": ([P, POINTER(c_uint64), POINTER(c_int32)], c_int32),
         "cnlos_server_destroy": ([P], c_int32),
+        "cnlos_tune": ([P, POINTER(Plan)], c_int32),
+        "cnlos_get_plan": ([P, POINTER(Plan)], c_int32),
+        "cnlos_set_plan": ([P, POINTER(Plan)], c_int32),
         "cnlos_nc_validate": ([POINTER(NcGeometry)], c_int32),
         "cnlos_nc_apply": ([POINTER(NcGeometry), P, P, P], c_int32),
         "cnlos_nc_apply_T": ([POINTER(NcGeometry), P, P, P], c_int32),
@@ -387,6 +402,24 @@ class Problem:
             if f in d:
                 setattr(inf, f, d[f])
         check(self._lib.cnlos_set_info(self._h, byref(inf)))
+
+    def tune(self):
+        """Measure the plane kernels' candidate layouts on this problem, keep the
+        fastest (also for later problems of this shape) and return the plan
+        with the measured times.  Resets the iteration state."""
+        pl = Plan()
+        check(self._lib.cnlos_tune(self._h, byref(pl)))
+        return _plan_dict(pl)
+
+    def plan(self):
+        pl = Plan()
+        check(self._lib.cnlos_get_plan(self._h, byref(pl)))
+        return _plan_dict(pl)
+
+    def set_plan(self, conv_row_pad, solve_row_pad):
+        pl = Plan()
+        pl.conv_row_pad, pl.solve_row_pad = int(conv_row_pad), int(solve_row_pad)
+        check(self._lib.cnlos_set_plan(self._h, byref(pl)))
 
     def profile_enable(self, kinds):
         """Time every later launch of the named kernel kinds with HIP events."""

@@ -4,7 +4,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +22,19 @@ constexpr double kC = 299792458.0;
 constexpr int kNcMaxGrid = 256;     // non-confocal operator: detectors per side
 constexpr int kNcMaxBins = 1024;    // and time bins (the forward kernel's LDS histograms)
 thread_local std::string g_err;
+
+// Launch plans measured by cnlos_tune, per device and shape; problems
+// created later on that device with that shape start with the plan.
+std::mutex g_plan_mu;
+std::map<std::tuple<int, int, int>, Plan> g_plans;
+
+Plan plan_for(int logn, int logm) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  auto it = g_plans.find(std::make_tuple(dev, logn, logm));
+  return it == g_plans.end() ? Plan{} : it->second;
+}
 
 cnlos_status fail(cnlos_status s, const std::string& msg) {
   g_err = msg;
@@ -1241,6 +1256,7 @@ cnlos_status build_tables(cnlos_problem* p, const cnlos_config* cfg, const uint8
   p->tb.sig_xy = p->sig_xy;
   p->tb.sig_t = p->sig_t;
   p->tb.hq = p->hq;
+  p->tb.plan = plan_for(p->logn, p->logm);
   HIPCHK(hipStreamSynchronize(p->st));
   return CNLOS_OK;
 }
@@ -1454,6 +1470,133 @@ cnlos_status cnlos_apply_A_noalloc(const cnlos_config* cfg, const uint8_t* mask_
   e.mask = masked ? p->mask : nullptr;
   HIPCHK(conv(p, src, false, EPI_PLAIN, e, nullptr));
   HIPCHK(hipStreamSynchronize(p->st));
+  return CNLOS_OK;
+}
+
+// ------------------------------------------------------------ launch plans
+}  // extern "C"
+
+namespace {
+
+void plan_out(const Plan& pl, int logn, bool tuned, const double* conv_us, const double* solve_us,
+              cnlos_plan* out) {
+  out->conv_row_pad = pl.conv_pad;
+  out->solve_row_pad = pl.solve_pad > 0 ? pl.solve_pad : default_solve_pad(logn);
+  out->tuned = tuned ? 1 : 0;
+  out->reserved = 0;
+  for (int i = 0; i < 3; ++i) {
+    out->conv_plane_us[i] = conv_us ? conv_us[i] : 0.0;
+    out->solve_plane_us[i] = solve_us ? solve_us[i] : 0.0;
+  }
+}
+
+int pad_index(const int (&pads)[3], int v) {
+  for (int i = 0; i < 3; ++i)
+    if (pads[i] == v) return i;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out) {
+  CHECK_HANDLE(p);
+  if (p->in_batch) return fail(CNLOS_ESTATE, "tune a standalone problem; batch members keep the batch's plan");
+  // every candidate runs on this problem's buffers: a plain forward
+  // convolution (A u[0] -> A u[1]) and a diagonal solve of A u[0]; their plane
+  // kernels are timed with HIP events
+  constexpr int kReps = 4;
+  Prof tp;
+  tp.mask = (1u << KK_PLANE_CONV) | (1u << KK_PLANE_SOLVE);
+  double conv_us[3] = {0, 0, 0}, solve_us[3] = {0, 0, 0};
+  const Plan keep = p->tb.plan;
+  HIPCHK(launch_fill(p->AU[0], p->V, 1.0f, p->st));
+  ConvSrc src{};
+  src.a = fixed(p->AU[0]);
+  src.b = fixed(nullptr);
+  ConvEpi ep{};
+  ep.out = fixed(p->AU[1]);
+  ep.au = fixed(nullptr);
+  ep.au_prev = fixed(nullptr);
+  RhsSrc rs;
+  SolveEpi se{};
+  se.out = fixed(p->AU[1]);
+  se.ref = fixed(nullptr);
+  se.partials = p->partials;
+  for (int i = 0; i < 3; ++i) {
+    p->tb.plan.conv_pad = kConvPads[i];
+    p->tb.plan.solve_pad = kSolvePads[i];
+    HIPCHK(launch_conv(p->logn, p->logm, p->tb, src, p->spec, false, EPI_PLAIN, ep, nullptr,
+                       kSingle, p->st, nullptr));   // warm-up of this variant
+    HIPCHK(launch_solve(p->logn, p->logm, p->tb, p->AU[0], rs, p->spec, nullptr, 1.0, 1.0, se,
+                        nullptr, kSingle, p->st, nullptr));
+    for (int r = 0; r < kReps; ++r) {
+      HIPCHK(launch_conv(p->logn, p->logm, p->tb, src, p->spec, false, EPI_PLAIN, ep, nullptr,
+                         kSingle, p->st, &tp));
+      HIPCHK(launch_solve(p->logn, p->logm, p->tb, p->AU[0], rs, p->spec, nullptr, 1.0, 1.0, se,
+                          nullptr, kSingle, p->st, &tp));
+    }
+    const hipError_t e = hipStreamSynchronize(p->st);
+    if (e != hipSuccess) {
+      tp.release();
+      p->tb.plan = keep;
+      HIPCHK(e);
+    }
+    tp.harvest();
+    conv_us[i] = 1e3 * tp.ms[KK_PLANE_CONV] / (double)(tp.launches[KK_PLANE_CONV] ? tp.launches[KK_PLANE_CONV] : 1);
+    solve_us[i] = 1e3 * tp.ms[KK_PLANE_SOLVE] / (double)(tp.launches[KK_PLANE_SOLVE] ? tp.launches[KK_PLANE_SOLVE] : 1);
+    for (int k = 0; k < KK_COUNT; ++k) {
+      tp.ms[k] = 0.0;
+      tp.launches[k] = 0;
+    }
+  }
+  tp.release();
+  // the fastest candidate of each kernel; it replaces the untuned default
+  // only when it is faster by more than the run-to-run spread of the timing
+  constexpr double kMargin = 0.98;
+  Plan best;
+  const int dc = pad_index(kConvPads, Plan{}.conv_pad), ds = pad_index(kSolvePads, default_solve_pad(p->logn));
+  int bc = dc, bs = ds;
+  for (int i = 0; i < 3; ++i) {
+    if (conv_us[i] < conv_us[bc]) bc = i;
+    if (solve_us[i] < solve_us[bs]) bs = i;
+  }
+  if (!(conv_us[bc] < kMargin * conv_us[dc])) bc = dc;
+  if (!(solve_us[bs] < kMargin * solve_us[ds])) bs = ds;
+  best.conv_pad = kConvPads[bc];
+  best.solve_pad = kSolvePads[bs];
+  p->tb.plan = best;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    g_plans[std::make_tuple(dev, p->logn, p->logm)] = best;
+  }
+  // the timing runs used the A u buffers: the solver starts afresh
+  if (p->cfg.model != CNLOS_MODEL_OPERATOR) {
+    cnlos_status s = reset_state(p);
+    if (s != CNLOS_OK) return s;
+  }
+  if (out) plan_out(best, p->logn, true, conv_us, solve_us, out);
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_get_plan(cnlos_problem* p, cnlos_plan* out) {
+  CHECK_HANDLE(p);
+  if (!out) return fail(CNLOS_EINVAL, "out is NULL");
+  plan_out(p->tb.plan, p->logn, false, nullptr, nullptr, out);
+  return CNLOS_OK;
+}
+
+cnlos_status cnlos_set_plan(cnlos_problem* p, const cnlos_plan* plan) {
+  CHECK_HANDLE(p);
+  if (!plan) return fail(CNLOS_EINVAL, "plan is NULL");
+  if (p->in_batch) return fail(CNLOS_ESTATE, "batch members keep the batch's plan");
+  if (pad_index(kConvPads, plan->conv_row_pad) < 0 || pad_index(kSolvePads, plan->solve_row_pad) < 0)
+    return fail(CNLOS_EINVAL, "row pads must be 1, 2 or 4 (convolution) and 2, 4 or 8 (solve)");
+  p->tb.plan.conv_pad = plan->conv_row_pad;
+  p->tb.plan.solve_pad = plan->solve_row_pad;
   return CNLOS_OK;
 }
 

@@ -275,6 +275,17 @@ struct SolveEpi {
   double* partials;
 };
 
+// Launch plan: layout choices of the plane kernels, the LDS row pads of their
+// transposes (bank conflicts only: no choice changes a result), picked per
+// shape from measured timings (cnlos_tune) or the defaults below.
+constexpr int kConvPads[3] = {1, 2, 4};
+constexpr int kSolvePads[3] = {2, 4, 8};
+inline int default_solve_pad(int logn) { return logn == 6 ? 2 : (logn == 7 ? 4 : 8); }
+struct Plan {
+  int conv_pad = 2;
+  int solve_pad = 0;      // 0: default_solve_pad(logn)
+};
+
 struct Tables {
   const float2* tw_t;     // exp(-2 pi i j / (2m)), j < m
   const float2* tw_xy;    // exp(-2 pi i j / (2n)), j < n
@@ -285,6 +296,7 @@ struct Tables {
   const float* sig_t;     // 4 sin^2(pi k / m), k <= m/2
   const float2* hq;       // H^: [m+1] planes of 4 n^2 entries, lane-ordered for the
                           // plane kernel that reads them (hq_lane_index)
+  Plan plan;
 };
 
 // ---------------------------------------------------------------- launchers

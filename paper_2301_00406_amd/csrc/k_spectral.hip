@@ -465,12 +465,13 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
 // separates with the partner frequency -k (see plane_conv_cols_packed); the
 // result is conv(P_0) + i conv(P_m).
 // ---------------------------------------------------------------------------
-// YS: LDS row stride of the transposes; a pad of 2 entries measured faster
-// than 8 (fewer bank conflicts on the column accesses).
+// YS: LDS row stride of the transposes, L + PAD.  The pad changes only where
+// values sit in LDS (bank conflicts of the column accesses), never a result;
+// the plan picks it per shape (1, 2 or 4; 2 when untuned).
 template <int LOGN>
 struct PlaneRegCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 8 * N;
-  static constexpr int RE = L / 8, YS = L + 2;
+  static constexpr int RE = L / 8;
 };
 
 // forward column transform of a zero-padded column whose first n entries are
@@ -502,12 +503,12 @@ __device__ __forceinline__ void col_inv(float2 (&c)[PlaneRegCfg<LOGN>::RE], int 
 //   Y(k) = Z^(k) (H_0 + H_m)/2 + conj(Z^(-k)) (H_0 - H_m)/2,
 // the spectrum of conv(P_0) + i conv(P_m) (H_0, H_m real and even).  Plane 0
 // of H^ holds the two factors as one pair (k_hq_pack_real).
-template <int LOGN>
+template <int LOGN, int PAD>
 __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* Hab,
                                                        const float2* tws, const float2* twc,
                                                        int tid) {
   using PC = PlaneRegCfg<LOGN>;
-  constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, RE = PC::RE, YS = PC::YS;
+  constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, RE = PC::RE, YS = L + PAD;
   const int s = tid & 7;
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
@@ -548,14 +549,14 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
   }
 }
 
-template <int LOGN, bool ADJ>
+template <int LOGN, bool ADJ, int PAD>
 __global__ void __launch_bounds__(PlaneRegCfg<LOGN>::NT)
 k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
                  const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
                  size_t zs, size_t hzs, int gate) {
   using PC = PlaneRegCfg<LOGN>;
   constexpr int N = PC::N, L = PC::L, LOGL = LOGN + 1, NT = PC::NT;
-  constexpr int RE = PC::RE, YS = PC::YS;
+  constexpr int RE = PC::RE, YS = L + PAD;
   // n rows of row spectra; block 0 uses all 2n rows for its column spectra
   __shared__ float2 Y[2 * N * YS];
   __shared__ float2 tws[N];
@@ -587,7 +588,7 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    plane_conv_cols_packed<LOGN>(Y, hq, tws, twc, tid);
+    plane_conv_cols_packed<LOGN, PAD>(Y, hq, tws, twc, tid);
   } else {
     // 2n spectrum columns, 8 lanes each, two columns per lane group
     const int s = tid & 7;
@@ -637,19 +638,19 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
 // group of 8 handles two rows / columns in turn.  Block 0 holds the packed
 // real planes kt = 0 and kt = m (half_cols_packed), so the launch has m
 // blocks, whole rounds of one block per CU.
-template <int LOGN>
+template <int LOGN, int PAD = 2>
 struct PlaneHalfCfg {
   static constexpr int N = 1 << LOGN, L = 2 * N, NT = 4 * N, G = NT / 8;
-  static constexpr int RN = N / 8, YS = N + 2;   // row stride: pad 2 (as PlaneRegCfg)
+  static constexpr int RN = N / 8, YS = N + PAD;   // row stride (pad as in PlaneRegCfg)
 };
 
 // rows of the half-split plane kernel: forward n-point DIF of the two rows
 // of a lane group (twisted by W_2n^y for the odd half) into LDS
-template <int LOGN>
+template <int LOGN, int PAD>
 __device__ __forceinline__ void half_rows_fwd(float2 (&v)[2][PlaneHalfCfg<LOGN>::RN], int h,
                                               float2* Y, const float2* tws, const float2* twc,
                                               int g, int s) {
-  using PC = PlaneHalfCfg<LOGN>;
+  using PC = PlaneHalfCfg<LOGN, PAD>;
   constexpr int RN = PC::RN, YS = PC::YS, G = PC::G;
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -666,10 +667,10 @@ __device__ __forceinline__ void half_rows_fwd(float2 (&v)[2][PlaneHalfCfg<LOGN>:
 
 // columns of the half-split plane kernel: padded 2n-point transform of each
 // ky_h column, H^ product, inverse, first n rows back to LDS
-template <int LOGN, bool ADJ>
+template <int LOGN, bool ADJ, int PAD>
 __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, const float2* tws,
                                           const float2* twc, int g, int s) {
-  using PC = PlaneHalfCfg<LOGN>;
+  using PC = PlaneHalfCfg<LOGN, PAD>;
   constexpr int N = PC::N, YS = PC::YS, G = PC::G;
   constexpr int RE = PlaneRegCfg<LOGN>::RE;
 #pragma unroll 1
@@ -721,11 +722,11 @@ __device__ __forceinline__ constexpr int rev_bits(int x, int bits) {
 // Registers hold one column spectrum per transform: A's spectrum (2n
 // entries) waits in the n LDS slots of A and the n of B while B is
 // transformed, and A's combined spectrum again while B is transformed back.
-template <int LOGN>
+template <int LOGN, int PAD>
 __device__ __forceinline__ void half_cols_packed(int h, float2* Y, const float2* Hab,
                                                  const float2* tws, const float2* twc, int g,
                                                  int s) {
-  using PC = PlaneHalfCfg<LOGN>;
+  using PC = PlaneHalfCfg<LOGN, PAD>;
   constexpr int N = PC::N, YS = PC::YS;
   constexpr int RE = PlaneRegCfg<LOGN>::RE, RH = RE / 2, LR = LOGN + 1 - 3;
   const bool self = h == 0 && g == 0;
@@ -818,11 +819,11 @@ __device__ __forceinline__ void half_cols_packed(int h, float2* Y, const float2*
 }
 
 // inverse rows: n-point DIT of a row from LDS (untwisted for the odd half)
-template <int LOGN>
+template <int LOGN, int PAD>
 __device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN], int h, int x,
                                              const float2* Y, const float2* tws, const float2* twc,
                                              int s) {
-  using PC = PlaneHalfCfg<LOGN>;
+  using PC = PlaneHalfCfg<LOGN, PAD>;
   constexpr int RN = PC::RN, YS = PC::YS;
 #pragma unroll
   for (int r = 0; r < RN; ++r) v[r] = Y[x * YS + 8 * r + s];
@@ -837,7 +838,7 @@ __device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN]
 // One plane through the half-split transform: per ky half, rows forward,
 // columns (PACKED: block 0's pairs of partner columns, else the H^ product),
 // rows back, the odd half accumulated onto the even one.
-template <int LOGN, bool ADJ, bool PACKED>
+template <int LOGN, bool ADJ, bool PACKED, int PAD>
 __device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const float2* Hp,
                                                 float2* Y, const float2* tws, const float2* twc,
                                                 int g, int s) {
@@ -849,10 +850,10 @@ __device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const fl
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
-  half_rows_fwd<LOGN>(v, 0, Y, tws, twc, g, s);
+  half_rows_fwd<LOGN, PAD>(v, 0, Y, tws, twc, g, s);
   __syncthreads();
-  if constexpr (PACKED) half_cols_packed<LOGN>(0, Y, Hp, tws, twc, g, s);
-  else half_cols<LOGN, ADJ>(0, Y, Hp, tws, twc, g, s);
+  if constexpr (PACKED) half_cols_packed<LOGN, PAD>(0, Y, Hp, tws, twc, g, s);
+  else half_cols<LOGN, ADJ, PAD>(0, Y, Hp, tws, twc, g, s);
   __syncthreads();
   // the odd half's input, then the even half's output in its place
 #pragma unroll
@@ -862,20 +863,20 @@ __device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const fl
 #pragma unroll 1
   for (int i = 0; i < 2; ++i) {
     float2 o[RN];
-    half_row_inv<LOGN>(o, 0, g + G * i, Y, tws, twc, s);
+    half_row_inv<LOGN, PAD>(o, 0, g + G * i, Y, tws, twc, s);
 #pragma unroll
     for (int r = 0; r < RN; ++r) P[(g + G * i) * N + 8 * r + s] = o[r];
   }
   __syncthreads();                                 // Y is rewritten by the odd half
-  half_rows_fwd<LOGN>(v, 1, Y, tws, twc, g, s);
+  half_rows_fwd<LOGN, PAD>(v, 1, Y, tws, twc, g, s);
   __syncthreads();
-  if constexpr (PACKED) half_cols_packed<LOGN>(1, Y, Hp, tws, twc, g, s);
-  else half_cols<LOGN, ADJ>(1, Y, Hp, tws, twc, g, s);
+  if constexpr (PACKED) half_cols_packed<LOGN, PAD>(1, Y, Hp, tws, twc, g, s);
+  else half_cols<LOGN, ADJ, PAD>(1, Y, Hp, tws, twc, g, s);
   __syncthreads();
 #pragma unroll 1
   for (int i = 0; i < 2; ++i) {
     float2 o[RN];
-    half_row_inv<LOGN>(o, 1, g + G * i, Y, tws, twc, s);
+    half_row_inv<LOGN, PAD>(o, 1, g + G * i, Y, tws, twc, s);
 #pragma unroll
     for (int r = 0; r < RN; ++r) {
       float2* q = P + (g + G * i) * N + 8 * r + s;
@@ -884,12 +885,12 @@ __device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const fl
   }
 }
 
-template <int LOGN, bool ADJ>
+template <int LOGN, bool ADJ, int PAD>
 __global__ void __launch_bounds__(PlaneHalfCfg<LOGN>::NT)
 k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
                   const float2* __restrict__ tw, const float2* __restrict__ twcg, const DevCtl* ctl,
                   size_t zs, size_t hzs, int gate) {
-  using PC = PlaneHalfCfg<LOGN>;
+  using PC = PlaneHalfCfg<LOGN, PAD>;
   constexpr int N = PC::N, L = PC::L, NT = PC::NT, G = PC::G, YS = PC::YS;
   static_assert(2 * G == N, "two rows per lane group");
   __shared__ float2 Y[N * YS];
@@ -910,28 +911,29 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
   __syncthreads();
   // block 0: the packed real planes kt = 0 and kt = m, a separate path so that
   // its register demand does not weigh on the other blocks' code
-  if (blockIdx.x == 0) plane_half_body<LOGN, ADJ, true>(P, Hp, Y, tws, twc, g, s);
-  else plane_half_body<LOGN, ADJ, false>(P, Hp, Y, tws, twc, g, s);
+  if (blockIdx.x == 0) plane_half_body<LOGN, ADJ, true, PAD>(P, Hp, Y, tws, twc, g, s);
+  else plane_half_body<LOGN, ADJ, false, PAD>(P, Hp, Y, tws, twc, g, s);
 }
 
 // Register-resident plane kernel of the diagonal solve (n <= 128): rows and
 // columns of length n by LN lanes each (16 at n = 64, so that a block has 16
 // waves to hide its phases' latencies; 8 otherwise), divide at the column step.
-// YS is the LDS row stride of the transpose: pads of 2 (n = 64) and 4
-// (n = 128) entries, the fastest of the pads measured.
-template <int LOGN>
+// YS is the LDS row stride of the transpose, N + PAD (a layout choice only;
+// the plan picks 2, 4 or 8 per shape; untuned: 2 at n = 64, 4 at n = 128 and
+// 8 otherwise, the fastest of the pads measured by hand).
+template <int LOGN, int PAD = (LOGN == 6 ? 2 : LOGN == 7 ? 4 : 8)>
 struct PlaneSolveCfg {
   static constexpr int N = 1 << LOGN, LN = LOGN == 6 ? 16 : 8, NT = LN * N, E = N / LN,
-                       YS = N + (LOGN == 6 ? 2 : LOGN == 7 ? 4 : 8);
+                       YS = N + PAD;
 };
 
-template <int LOGN>
+template <int LOGN, int PAD>
 __global__ void __launch_bounds__(PlaneSolveCfg<LOGN>::NT)
 k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
                   const float* __restrict__ sig_xy, const float* __restrict__ sig_t,
                   const double* c_dev, float c_val, float mu, const DevCtl* ctl, size_t zs,
                   int gate) {
-  using PC = PlaneSolveCfg<LOGN>;
+  using PC = PlaneSolveCfg<LOGN, PAD>;
   constexpr int N = PC::N, LN = PC::LN, NT = PC::NT, E = PC::E, YS = PC::YS;
   __shared__ float2 Y[N * YS];
   __shared__ float2 twc[N];
@@ -1699,6 +1701,58 @@ int fused_solve_blocks(int logn, int logm) { return conv_blocks(logn, logm); }
     if (t_) (void)(prof)->end(kind, st);                   \
   } while (0)
 
+// plane pass of a convolution with row pad PAD
+template <int LOGN, int PAD>
+static void plane_conv_pad(bool adjoint, int M, const Tables& tb, float2* spec, const DevCtl* ctl,
+                           size_t zs, size_t hzs, int g, int nz, hipStream_t st) {
+  if constexpr (LOGN <= 6) {
+    if (adjoint)
+      hipLaunchKernelGGL((k_plane_conv_reg<LOGN, true, PAD>), dim3(M, 1, nz),
+                         dim3(PlaneRegCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl,
+                         zs, hzs, g);
+    else
+      hipLaunchKernelGGL((k_plane_conv_reg<LOGN, false, PAD>), dim3(M, 1, nz),
+                         dim3(PlaneRegCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy, ctl,
+                         zs, hzs, g);
+  } else {
+    if (adjoint)
+      hipLaunchKernelGGL((k_plane_conv_half<LOGN, true, PAD>), dim3(M, 1, nz),
+                         dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy,
+                         ctl, zs, hzs, g);
+    else
+      hipLaunchKernelGGL((k_plane_conv_half<LOGN, false, PAD>), dim3(M, 1, nz),
+                         dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy, tb.twc_xy,
+                         ctl, zs, hzs, g);
+  }
+}
+
+template <int LOGN>
+static void plane_conv(bool adjoint, int M, const Tables& tb, float2* spec, const DevCtl* ctl,
+                       size_t zs, size_t hzs, int g, int nz, hipStream_t st) {
+  switch (tb.plan.conv_pad) {
+    case 1: plane_conv_pad<LOGN, 1>(adjoint, M, tb, spec, ctl, zs, hzs, g, nz, st); break;
+    case 4: plane_conv_pad<LOGN, 4>(adjoint, M, tb, spec, ctl, zs, hzs, g, nz, st); break;
+    default: plane_conv_pad<LOGN, 2>(adjoint, M, tb, spec, ctl, zs, hzs, g, nz, st); break;
+  }
+}
+
+// plane pass of a diagonal solve with the plan's row pad
+template <int LOGN>
+static void plane_solve(int M, const Tables& tb, float2* spec, const double* c_dev, float c_val,
+                        float mu, const DevCtl* ctl, size_t zs, int g, int nz, hipStream_t st) {
+  const int pad = tb.plan.solve_pad > 0 ? tb.plan.solve_pad : default_solve_pad(LOGN);
+#define CNLOS_PSOLVE(P)                                                                         \
+  hipLaunchKernelGGL((k_plane_solve_reg<LOGN, P>), dim3(M / 2, 1, nz),                          \
+                     dim3(PlaneSolveCfg<LOGN, P>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy, tb.sig_t, \
+                     c_dev, c_val, mu, ctl, zs, g)
+  switch (pad) {
+    case 2: CNLOS_PSOLVE(2); break;
+    case 4: CNLOS_PSOLVE(4); break;
+    default: CNLOS_PSOLVE(8); break;
+  }
+#undef CNLOS_PSOLVE
+}
+
 template <int LOGN, int LOGM>
 static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, bool adjoint,
                             int epi, const ConvEpi& ep, const DevCtl* ctl, const Batch& bt,
@@ -1714,30 +1768,7 @@ static hipError_t conv_impl(const Tables& tb, const ConvSrc& src, float2* spec, 
     CNLOS_TIMED(prof, KK_T_FWD_CONV, st,
                 hipLaunchKernelGGL((k_tfwd_conv<LOGM, PK>), dim3(nb, 1, nz), dim3(TG::NT), 0, st,
                                    src, tb.S, tb.tw_t, tb.twc_t, spec, NN, ctl, zs, g));
-  if constexpr (LOGN <= 6) {
-    constexpr int LN = LOGN;
-    if (adjoint)
-      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, true>), dim3(M, 1, nz),
-                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, hzs, g));
-    else
-      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_reg<LN, false>), dim3(M, 1, nz),
-                                     dim3(PlaneRegCfg<LN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, hzs, g));
-  } else {
-    if (adjoint)
-      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, true>), dim3(M, 1, nz),
-                                     dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, hzs, g));
-    else
-      CNLOS_TIMED(prof, KK_PLANE_CONV, st,
-                  hipLaunchKernelGGL((k_plane_conv_half<LOGN, false>), dim3(M, 1, nz),
-                                     dim3(PlaneHalfCfg<LOGN>::NT), 0, st, spec, tb.hq, tb.tw_xy,
-                                     tb.twc_xy, ctl, zs, hzs, g));
-  }
+  CNLOS_TIMED(prof, KK_PLANE_CONV, st, plane_conv<LOGN>(adjoint, M, tb, spec, ctl, zs, hzs, g, nz, st));
   const float scale = (float)(1.0 / (4.0 * (double)NN * (double)M));
   if (rhs_next) {
     if (epi == EPI_FWD_DUAL)
@@ -1799,9 +1830,7 @@ static hipError_t solve_impl(const Tables& tb, const float* rhs, const RhsSrc& r
     }
   }
   CNLOS_TIMED(prof, KK_PLANE_SOLVE, st,
-              hipLaunchKernelGGL(k_plane_solve_reg<LOGN>, dim3(M / 2, 1, nz),
-                                 dim3(PlaneSolveCfg<LOGN>::NT), 0, st, spec, tb.twc_xy, tb.sig_xy,
-                                 tb.sig_t, c_dev, (float)c_val, (float)mu, ctl, zs, g));
+              plane_solve<LOGN>(M, tb, spec, c_dev, (float)c_val, (float)mu, ctl, zs, g, nz, st));
   const float scale = (float)(2.0 / ((double)NN * (double)M));
   if (fwd_next) {
     // with the forward t pass of the convolution of the result

@@ -23,7 +23,7 @@ def header_functions():
 def test_library_exports_every_declared_function():
     lib = C.load()
     names = header_functions()
-    assert len(names) == 39
+    assert len(names) == 42
     for name in names:
         assert hasattr(lib, name), name
     out = subprocess.run(["nm", "-D", "--defined-only", C.LIB_PATH], capture_output=True,
@@ -38,11 +38,12 @@ def test_struct_layout_matches_header():
 #include <stdio.h>
 #include "cnlos.h"
 int main(void) {{
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(cnlos_config), offsetof(cnlos_config, lambda),
          offsetof(cnlos_config, power_iters), sizeof(cnlos_report), sizeof(cnlos_info),
          offsetof(cnlos_info, iter), offsetof(cnlos_config, eps_stop),
          offsetof(cnlos_config, fista_restart), sizeof(cnlos_nc_geometry),
-         offsetof(cnlos_nc_geometry, literal));
+         offsetof(cnlos_nc_geometry, literal), sizeof(cnlos_plan),
+         offsetof(cnlos_plan, solve_plane_us));
   return 0;
 }}
 """
@@ -56,7 +57,8 @@ int main(void) {{
     assert vals == [ctypes.sizeof(C.Config), C.Config.lambda_.offset, C.Config.power_iters.offset,
                     ctypes.sizeof(C.Report), ctypes.sizeof(C.Info), C.Info.iter.offset,
                     C.Config.eps_stop.offset, C.Config.fista_restart.offset,
-                    ctypes.sizeof(C.NcGeometry), C.NcGeometry.literal.offset]
+                    ctypes.sizeof(C.NcGeometry), C.NcGeometry.literal.offset,
+                    ctypes.sizeof(C.Plan), C.Plan.solve_plane_us.offset]
 
 
 def test_defaults_follow_paper_parameters():
