@@ -328,10 +328,10 @@ typedef struct cnlos_plan {
   double solve_plane_us[3];   /* measured plane pass of one solve, pads 2, 4, 8 (us)        */
 } cnlos_plan;
 
-/* Measure every candidate pad on this problem's workspace (a few convolutions
+/* Measure every candidate pad on this problem's workspace (eight convolutions
  * and solves each, timed with HIP events on its stream), keep the fastest for
  * the problem and for later problems of its shape (a candidate replaces the
- * default only when it is more than 2% faster), and fill *out (may be
+ * default only when it is more than 3% faster), and fill *out (may be
  * NULL).  Overwrites the A u buffers, so a solver problem's iteration state
  * is reset (the measurement is kept).  Not for batch members (ESTATE).
  * Synchronizes the stream. */

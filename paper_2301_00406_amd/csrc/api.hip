@@ -1504,9 +1504,9 @@ cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out) {
   CHECK_HANDLE(p);
   if (p->in_batch) return fail(CNLOS_ESTATE, "tune a standalone problem; batch members keep the batch's plan");
   // every candidate runs on this problem's buffers: a plain forward
-  // convolution (A u[0] -> A u[1]) and a diagonal solve of A u[0]; their plane
-  // kernels are timed with HIP events
-  constexpr int kReps = 4;
+  // convolution (A u[0] -> A u[1]) and a diagonal solve of A u[0], eight times
+  // each after a warm-up; their plane kernels are timed with HIP events
+  constexpr int kReps = 8;
   Prof tp;
   tp.mask = (1u << KK_PLANE_CONV) | (1u << KK_PLANE_SOLVE);
   double conv_us[3] = {0, 0, 0}, solve_us[3] = {0, 0, 0};
@@ -1554,7 +1554,7 @@ cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out) {
   tp.release();
   // the fastest candidate of each kernel; it replaces the untuned default
   // only when it is faster by more than the run-to-run spread of the timing
-  constexpr double kMargin = 0.98;
+  constexpr double kMargin = 0.97;
   Plan best;
   const int dc = pad_index(kConvPads, Plan{}.conv_pad), ds = pad_index(kSolvePads, default_solve_pad(p->logn));
   int bc = dc, bs = ds;

@@ -35,11 +35,11 @@ def test_tune_measures_every_candidate_and_later_problems_use_the_plan():
     pl = P.tune()
     assert pl["tuned"]
     assert all(t > 0 for t in pl["conv_plane_us"] + pl["solve_plane_us"])
-    # the fastest candidate, unless it beats the default by 2 % or less
+    # the fastest candidate, unless it beats the default by 3 % or less
     for key, pads, default, us in (("conv_row_pad", [1, 2, 4], 2, pl["conv_plane_us"]),
                                    ("solve_row_pad", [2, 4, 8], 8, pl["solve_plane_us"])):
         best = pads[int(np.argmin(us))]
-        exp = best if min(us) < 0.98 * us[pads.index(default)] else default
+        exp = best if min(us) < 0.97 * us[pads.index(default)] else default
         assert pl[key] == exp, (key, pl)
     # the tuned problem still runs from the start with its measurement
     P.run()
