@@ -493,7 +493,7 @@ def algorithmic_bytes(kind, n, m, dual):
         u = spec_s + 2 * f + spec_c  # tau solve (dual): writes tau+
         return (u + spec_s + f) / 2 if dual else u
     # the splitting variables v, w, f are recomputed where they are used
-    if kind == "post_u":           # object: 7 volumes in, 5 out; dual adds the tau side (10 in, 6 out)
+    if kind == "post":           # object: 7 volumes in, 5 out; dual adds the tau side (10 in, 6 out)
         return 28 * f + n * n if dual else 12 * f
     return 0.0
 

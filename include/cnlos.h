@@ -279,17 +279,15 @@ typedef enum {
   CNLOS_KK_PLANE_SOLVE = 4,  /* diagonal solve: (x, y) transform and divide    */
   CNLOS_KK_T_INV_SOLVE = 5,  /* diagonal solve: C2R along t (+ the first pass
                                 of the forward operator of the result)        */
-  CNLOS_KK_VSTEP = 6,        /* reserved (v, w, f are recomputed where used)   */
-  CNLOS_KK_FSTEP = 7,        /* reserved                                       */
-  CNLOS_KK_RHS_U = 8,        /* reserved (formed inside the solve's first pass) */
-  CNLOS_KK_RHS_TAU = 9,      /* reserved (formed inside the solve's first pass) */
-  CNLOS_KK_POST_U = 10,      /* backtracking decision, then multiplier,
+  CNLOS_KK_FIELD = 6,        /* read-back of a splitting variable (v, w, f are
+                                recomputed where the iteration uses them;
+                                cnlos_get_field forms them on request)         */
+  CNLOS_KK_POST = 7,         /* backtracking decision, then multiplier,
                                 extrapolation, curvature: u (object model); u
                                 and tau in one kernel (dual model)             */
-  CNLOS_KK_POST_TAU = 11,    /* reserved (the tau side runs inside POST_U)     */
-  CNLOS_KK_CONTROL = 12,     /* iteration finalize (energy, log, L, FISTA t)   */
-  CNLOS_KK_OTHER = 13,       /* warm-start hand-over                           */
-  CNLOS_KK_COUNT = 14
+  CNLOS_KK_CONTROL = 8,      /* iteration finalize (energy, log, L, FISTA t)   */
+  CNLOS_KK_OTHER = 9,        /* warm-start hand-over                           */
+  CNLOS_KK_COUNT = 10
 } cnlos_kernel_kind;
 
 /* Per-kernel timing for tracing and roofline measurement (not part of the

@@ -21,8 +21,7 @@ FALLOFF_COMPENSATED, FALLOFF_LITERAL = 0, 1
  FIELD_TAU, FIELD_TAUBAR, FIELD_W, FIELD_LAM2, FIELD_F, FIELD_LAM3, FIELD_PHI_TAU) = range(15)
 VECTOR_FIELDS = {FIELD_V, FIELD_LAM, FIELD_W, FIELD_LAM2}
 KERNEL_KINDS = ["t_fwd_conv", "plane_conv", "t_inv_conv", "t_fwd_solve", "plane_solve",
-                "t_inv_solve", "vstep", "fstep", "rhs_u", "rhs_tau", "post_u", "post_tau",
-                "control", "other"]
+                "t_inv_solve", "field", "post", "control", "other"]
 
 _STATUS_NAMES = {OK: "CNLOS_OK", EINVAL: "CNLOS_EINVAL", EUNSUPPORTED: "CNLOS_EUNSUPPORTED",
                  ENOMEM: "CNLOS_ENOMEM", EHIP: "CNLOS_EHIP", ESTATE: "CNLOS_ESTATE",

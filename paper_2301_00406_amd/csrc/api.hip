@@ -151,6 +151,10 @@ struct SrvGroup {
   uint64_t off = 0;            // arena range: [off, off + bytes)
   uint64_t bytes = 0;
   float2* hq = nullptr;        // the group's H^, at the start of its range
+  // ||A||^2 estimate of the group's geometry (unmasked: the dual model's step
+  // constant), measured at the first admission that needs it, for power_iters
+  double est_unmasked = 0.0;
+  int est_unmasked_iters = 0;
   uint64_t slots_off = 0;      // slot i's workspace at slots_off + i * stride
   hipStream_t st = nullptr;
   cnlos_problem* layout = nullptr;       // buffer layout of slot 0 (no device state of its own)
@@ -703,7 +707,7 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     const CheckArgs ck{p->nb_conv, p->nb_step, c.backtracking ? 1 : 0};
     const PostArgs pa{role(R_U_TR), role(R_U_CUR), role(R_UB_CUR), role(R_UB_NEW), p->lam, p->phi,
                       (float)mu, phi_args(p, 1, false)};
-    TIMED(KK_POST_U, launch_post(ln, lm, pa, p->partials, ck, ctl, gated(G), p->st));
+    TIMED(KK_POST, launch_post(ln, lm, pa, p->partials, ck, ctl, gated(G), p->st));
     // the data term of the energy comes from the forward pass (SL_DATA)
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 0, 0.0, mu,
                                       gated(G), p->st));
@@ -781,7 +785,7 @@ cnlos_status enqueue_slot(cnlos_problem* p, Batch bt, int seqs) {
     const PostArgs pt{role(R_T_TR), role(R_T_CUR), role(R_T_CUR), role(R_TB_NEW), p->lam2,
                       p->phi_tau, (float)mu2, phi_args(p, 2, true)};
     const CheckArgs ck{p->nb_conv, p->nb_step, c.backtracking ? 1 : 0};
-    TIMED(KK_POST_U, launch_post_dual(ln, lm, pu, pt, p->lam3, mu3, lam, role(R_AU_TR), p->tau0,
+    TIMED(KK_POST, launch_post_dual(ln, lm, pu, pt, p->lam3, mu3, lam, role(R_AU_TR), p->tau0,
                                       p->mask, p->partials, ck, ctl, gated(G), p->st));
     TIMED(KK_CONTROL, launch_finalize(ctl, p->logbuf, p->partials, p->nb_conv, p->nb_sten, 1, lam, mu1,
                                       gated(G), p->st));
@@ -1709,18 +1713,18 @@ cnlos_status cnlos_get_field(cnlos_problem* p, int32_t field, float* dst_dev) {
   const bool stage2 = dual && h.stage == 2;
   // v, w and f are not stored: computed from the state the next iteration starts from
   if (field == CNLOS_FIELD_V) {
-    HIPCHK(launch_vstep(p->logn, p->logm, p->UB[h.slot[R_UB_CUR]], p->lam, p->phi, dst_dev,
-                        stage2 ? p->cfg.mu1 : p->cfg.mu, p->st));
+    TIMED(KK_FIELD, launch_vstep(p->logn, p->logm, p->UB[h.slot[R_UB_CUR]], p->lam, p->phi,
+                                 dst_dev, stage2 ? p->cfg.mu1 : p->cfg.mu, p->st));
     return CNLOS_OK;
   }
   if (dual && field == CNLOS_FIELD_W) {
-    HIPCHK(launch_vstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam2, p->phi_tau, dst_dev,
-                        p->cfg.mu2, p->st));
+    TIMED(KK_FIELD, launch_vstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam2, p->phi_tau,
+                                 dst_dev, p->cfg.mu2, p->st));
     return CNLOS_OK;
   }
   if (dual && field == CNLOS_FIELD_F) {
-    HIPCHK(launch_fstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam3, p->tau0, p->mask,
-                        dst_dev, p->cfg.lambda, p->cfg.mu3, p->st));
+    TIMED(KK_FIELD, launch_fstep(p->logn, p->logm, p->T[h.slot[R_T_CUR]], p->lam3, p->tau0,
+                                 p->mask, dst_dev, p->cfg.lambda, p->cfg.mu3, p->st));
     return CNLOS_OK;
   }
   size_t n = 0;
@@ -2129,9 +2133,29 @@ cnlos_status srv_admit(cnlos_server* sv, SrvGroup* g, int i, SrvReq& q) {
   g->admitted[i] = sv->step_no;
   cnlos_status st = create_into(&q.r.cfg, q.mask.data(),
                                 sv->arena.base + g->slots_off + (size_t)i * g->stride, g->stride,
-                                g->st, &m, g->hq, false);
+                                g->st, &m, g->hq, false, true);
   if (m) m->in_batch = true;
   g->slot[i] = m;
+  if (st == CNLOS_OK) {
+    // step constants; the unmasked estimate depends only on the group's
+    // geometry, so one measurement serves every admission (the same
+    // fixed-order computation each time, hence the same bits)
+    const cnlos_config& c = q.r.cfg;
+    double em = 0.0, eu = 0.0;
+    if (c.L0 <= 0.0) st = power_estimate(m, true, &em);
+    if (st == CNLOS_OK && c.model == CNLOS_MODEL_DUAL && c.L0_dual <= 0.0) {
+      if (g->est_unmasked_iters == c.power_iters && g->est_unmasked > 0.0) {
+        eu = g->est_unmasked;
+      } else {
+        st = power_estimate(m, false, &eu);
+        if (st == CNLOS_OK) {
+          g->est_unmasked = eu;
+          g->est_unmasked_iters = c.power_iters;
+        }
+      }
+    }
+    if (st == CNLOS_OK) st = finish_create(m, em, eu);
+  }
   if (st == CNLOS_OK) st = cnlos_set_measurement(m, q.r.tau0_dev);
   if (st == CNLOS_OK) {
     Group one;

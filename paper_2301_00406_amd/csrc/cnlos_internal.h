@@ -18,15 +18,11 @@ enum KernelKind : int {
   KK_T_FWD_SOLVE = 3,
   KK_PLANE_SOLVE = 4,
   KK_T_INV_SOLVE = 5,
-  KK_VSTEP = 6,
-  KK_FSTEP = 7,
-  KK_RHS_U = 8,
-  KK_RHS_TAU = 9,
-  KK_POST_U = 10,
-  KK_POST_TAU = 11,
-  KK_CONTROL = 12,
-  KK_OTHER = 13,
-  KK_COUNT = 14
+  KK_FIELD = 6,
+  KK_POST = 7,
+  KK_CONTROL = 8,
+  KK_OTHER = 9,
+  KK_COUNT = 10
 };
 
 // HIP-event timer around launches of selected kernel kinds, on the launch

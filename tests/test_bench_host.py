@@ -105,7 +105,7 @@ def test_plane_pass_flops_count_the_pruned_transforms():
         per_plane = len(schedule) * per_transform + 6 * L * L
         assert bench.algorithmic_flops("plane_conv", n, m) == m * per_plane
     assert bench.algorithmic_flops("plane_conv", 64, 512) == 931135488
-    assert bench.algorithmic_flops("post_u", 64, 512) == 0.0
+    assert bench.algorithmic_flops("post", 64, 512) == 0.0
 
 
 def test_roofline_peaks_and_plane_pass_bytes():
