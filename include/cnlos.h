@@ -331,8 +331,8 @@ typedef struct cnlos_plan {
  * the problem and for later problems of its shape (a candidate replaces the
  * default only when it is more than 3% faster), and fill *out (may be
  * NULL).  Overwrites the A u buffers, so a solver problem's iteration state
- * is reset (the measurement is kept).  Not for batch members (ESTATE).
- * Synchronizes the stream. */
+ * is reset (the measurement is kept).  Not for batch members or
+ * operator-only problems (ESTATE).  Synchronizes the stream. */
 cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out);
 
 /* The problem's current plan (tuned = 0, no timings). */

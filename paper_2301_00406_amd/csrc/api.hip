@@ -1506,6 +1506,10 @@ extern "C" {
 
 cnlos_status cnlos_tune(cnlos_problem* p, cnlos_plan* out) {
   CHECK_HANDLE(p);
+  // the measurement runs on the solver's A u buffers, which an operator-only
+  // workspace does not have
+  if (p->cfg.model == CNLOS_MODEL_OPERATOR)
+    return fail(CNLOS_ESTATE, "tune needs a solver problem (an operator-only workspace has no room for the measurement)");
   if (p->in_batch) return fail(CNLOS_ESTATE, "tune a standalone problem; batch members keep the batch's plan");
   // every candidate runs on this problem's buffers: a plain forward
   // convolution (A u[0] -> A u[1]) and a diagonal solve of A u[0], eight times

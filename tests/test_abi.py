@@ -249,3 +249,11 @@ def test_nonconfocal_midpoint_is_the_half_scale_grid():
     wall, centre = C.nc_midpoint(g)
     ow, oc = O.nonconfocal_midpoint_geometry(O.NonConfocalGeometry(8, 64, 0.8, 32.0, (0.2, -0.1)))
     assert wall == ow and centre == oc
+
+
+def test_plan_calls_reject_null_arguments():
+    lib = C.load()
+    pl = C.Plan()
+    assert lib.cnlos_tune(None, ctypes.byref(pl)) == C.EINVAL
+    assert lib.cnlos_get_plan(None, ctypes.byref(pl)) == C.EINVAL
+    assert lib.cnlos_set_plan(None, ctypes.byref(pl)) == C.EINVAL

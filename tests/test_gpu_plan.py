@@ -51,7 +51,11 @@ def test_tune_measures_every_candidate_and_later_problems_use_the_plan():
     assert (R.plan()["conv_row_pad"], R.plan()["solve_row_pad"]) == (2, 8)
     with pytest.raises(C.CnlosError):
         Q.set_plan(3, 8)
-    for h in (P, Q, R):
+    O = C.Problem(C.default_config(nx=n, ny=n, nt=m, model=C.MODEL_OPERATOR), mask)
+    with pytest.raises(C.CnlosError) as e:
+        O.tune()
+    assert e.value.status == C.ESTATE
+    for h in (P, Q, R, O):
         h.close()
 
 
