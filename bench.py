@@ -200,6 +200,67 @@ def batched_comparison(torch, C, scenes, mix):
     }
 
 
+def batched_metric(torch, C, scenes, count=8):
+    """Batched against one scene at a time at the metric configuration itself:
+    `count` seeded scenes of the 64x64x512 dual workload (50 + 200
+    iterations), every step create + set_measurement + run + read volume."""
+    dev = torch.device("cuda", 0)
+    wl = WORKLOADS["medium"]
+    scs = [scenes.scene_medium(201 + i) for i in range(count)]
+    sc0 = scs[0]
+    oc = C.default_config(nx=sc0.n, ny=sc0.n, nt=sc0.m, wall_w_m=sc0.wall_w, wall_h_m=sc0.wall_h,
+                          bin_ps=sc0.bin_ps, model=C.MODEL_OPERATOR, falloff=C.FALLOFF_LITERAL)
+    op = C.Problem(oc, np.ones((sc0.n, sc0.n), np.uint8), device=dev)
+    raws = []
+    for sc in scs:
+        clean = op.apply_A(torch.tensor(sc.u_true.astype(np.float32), device=dev))
+        r = scenes.poisson_counts(clean.double().cpu().numpy(), sc.peak, sc.background,
+                                  np.random.Generator(np.random.PCG64(sc.seed)))
+        raws.append(torch.tensor(r.astype(np.float32), device=dev))
+    op.close()
+    cfgs = [C.default_config(nx=sc.n, ny=sc.n, nt=sc.m, wall_w_m=sc.wall_w, wall_h_m=sc.wall_h,
+                             bin_ps=sc.bin_ps, model=C.MODEL_DUAL, max_iters=wl["iters"],
+                             init_iters=wl["init"], **wl["params"]) for sc in scs]
+
+    def alone():
+        vols = []
+        for sc, c, raw in zip(scs, cfgs, raws):
+            P = C.Problem(c, sc.mask, device=dev)
+            P.set_measurement(raw)
+            P.run()
+            vols.append(P.volume())
+            P.close()
+        torch.cuda.synchronize()
+        return vols
+
+    def batched():
+        B = C.Batch(cfgs, [sc.mask for sc in scs], device=dev)
+        for mem, raw in zip(B.members, raws):
+            mem.set_measurement(raw)
+        status, _ = B.run()
+        if status != C.OK:
+            raise RuntimeError(C.last_error())
+        vols = [mem.volume() for mem in B.members]
+        torch.cuda.synchronize()
+        B.close()
+        return vols
+
+    alone()                                   # warm-up of both forms
+    batched()
+    t0 = time.perf_counter()
+    va = alone()
+    t_alone = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    vb = batched()
+    t_batch = time.perf_counter() - t0
+    vi = count * sc0.n * sc0.n * sc0.m * (wl["init"] + wl["iters"])
+    return {"scenes": count, "workload": "64x64x512 dual-domain (Algorithm 2), 50 + 200 iterations, "
+                                          "seeded scenes 201..",
+            "one_at_a_time_rec_per_s": count / t_alone, "batched_rec_per_s": count / t_batch,
+            "speedup": t_alone / t_batch, "batched_voxel_iters_per_s": vi / t_batch,
+            "results_bitwise_equal": bool(all(torch.equal(a, b) for a, b in zip(va, vb)))}
+
+
 def _ssim(x, y, sigma=1.5, data_range=1.0):
     """Mean structural similarity of two images (Wang, Bovik, Sheikh and
     Simoncelli 2004): Gaussian window of width sigma (radius 3.5 sigma),
@@ -912,6 +973,7 @@ def main():
                 print(f"bench: {name} workload done", file=sys.stderr, flush=True)
     if not args.no_batch:
         result["batched"] = batched_comparison(torch, C, scenes, MIX_SMALL)
+        result["batched_metric_config"] = batched_metric(torch, C, scenes)
     if not args.no_other_workloads:
         result["nonconfocal"] = nonconfocal_rates(torch, C)
     if not args.no_cpu_baseline:

@@ -40,13 +40,19 @@ __device__ __forceinline__ void zsh_tables(ResampleTables& S, size_t zo) {
 // lives in the registers of a group of G <= 64 lanes, so within one wave
 // (lane s keeps positions G*r + s).  Spectrum planes are exchanged with global
 // memory through an LDS staging tile [kt][J], so every plane access is a
-// J * 8-byte segment (128 bytes up to m = 512).  Fewer lanes per column (more
+// J * 8-byte segment (64 bytes from m = 256 on).  Fewer lanes per column (more
 // elements per lane, fewer cross-lane stages) measured slower: the passes are
 // bound by the latency of their phases, and fewer waves hide less of it.
 // ---------------------------------------------------------------------------
-// Columns per block of a t pass of length 2^logf: 16 (128-byte plane
-// segments) while the staging tile fits LDS next to the tables, then fewer.
-constexpr int t_columns(int logf) { return logf <= 9 ? 16 : (logf == 10 ? 8 : 4); }
+// Columns per block of a t pass of length 2^logf: 8 for lengths 256 to 1024,
+// where a block's 512 threads, about 60 KB of LDS (at 512) and its registers
+// leave room for two blocks per CU, so one block's loads overlap the other's
+// transform (measured faster than 16-column blocks of 1024 threads with
+// 128-byte segments, one per CU: 61.7 against 62.6 ms per 64x64x512
+// reconstruction, 408 against 442 ms for a batch of eight); 16 for shorter
+// transforms (the solve phase of a fused pass needs whole waves), 4 at 2048
+// (LDS).
+constexpr int t_columns(int logf) { return logf <= 7 ? 16 : (logf <= 10 ? 8 : 4); }
 
 template <int LOGF>
 struct TGeo {                                 // transform of length F = 2^LOGF
