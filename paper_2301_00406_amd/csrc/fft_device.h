@@ -229,24 +229,26 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
   __shared__ double red[K][16];
   double acc[K];
   // every load is issued before the first add (fixed trip counts, unrolled):
-  // one memory round trip instead of K
-  // (a load under a per-lane condition compiles to a branch with a wait after
-  // it, so the index is clamped and the value masked instead); chunks of
-  // blockDim partials, only as many as the longest array needs
+  // one memory round trip for all K arrays and all chunks of blockDim
+  // partials (a load under a per-lane condition compiles to a branch with a
+  // wait after it, so the index is clamped and the value masked instead; the
+  // masked zeros leave each sum unchanged)
   constexpr int kPer = 4;   // covers 4 x blockDim >= max_blocks partials (1024 threads)
-  int nbmax = 0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) nbmax = nb[k] > nbmax ? nb[k] : nbmax;
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int j = 0; j < kPer && j * (int)blockDim.x < nbmax; ++j) {
+  double vals[kPer][K];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
     const int i = threadIdx.x + j * (int)blockDim.x;
-    double vals[K];
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      vals[k] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
+      vals[j][k] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
+  }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] += i < nb[k] ? vals[k] : 0.0;
+  for (int j = 0; j < kPer; ++j) {
+    const int i = threadIdx.x + j * (int)blockDim.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] += i < nb[k] ? vals[j][k] : 0.0;
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

@@ -59,18 +59,29 @@ __device__ __forceinline__ int check_decision(const double* __restrict__ partial
   constexpr int NW = kStencilThreads / 64;
   __shared__ double red[2][NW];
   __shared__ int dec;
-  // both slots' loads of a step issue together: index clamped, value masked
-  // (a load under a per-lane condition compiles to a branch with a wait after
-  // it); one step per kStencilThreads partials
+  // both slots' loads of four steps of kStencilThreads partials issue
+  // together: index clamped, value masked (a load under a per-lane condition
+  // compiles to a branch with a wait after it; the masked zeros leave the
+  // sums unchanged)
+  constexpr int kSteps = 4;
   const double* pc = partials + (size_t)SL_CHECK * kMaxBlocks;
   const double* ps = partials + (size_t)SL_STEP * kMaxBlocks;
   const int nmax = ck.nb_conv > ck.nb_step ? ck.nb_conv : ck.nb_step;
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nmax; i += kStencilThreads) {
-    const double va = pc[i < ck.nb_conv ? i : 0];
-    const double vb = ps[i < ck.nb_step ? i : 0];
-    a += i < ck.nb_conv ? va : 0.0;
-    b += i < ck.nb_step ? vb : 0.0;
+  for (int base = 0; base < nmax; base += kSteps * kStencilThreads) {
+    double va[kSteps], vb[kSteps];
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+      const int i = base + j * kStencilThreads + threadIdx.x;
+      va[j] = pc[i < ck.nb_conv ? i : 0];
+      vb[j] = ps[i < ck.nb_step ? i : 0];
+    }
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+      const int i = base + j * kStencilThreads + threadIdx.x;
+      a += i < ck.nb_conv ? va[j] : 0.0;
+      b += i < ck.nb_step ? vb[j] : 0.0;
+    }
   }
   a = wave_sum(a);
   b = wave_sum(b);

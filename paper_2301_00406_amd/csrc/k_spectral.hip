@@ -1305,28 +1305,30 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   }
   dit_xlane<G, E>(x, s, twc);
   dit_inlane<G, E, E / 2>(x, s, twc);
-  double acc = 0.0;
   float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
-  // the reference is read unconditionally (the output column stands in when
-  // there is none), so its loads are not each behind a branch and a wait
-  const bool hr = eref != nullptr;
-  const float2* ref2 = reinterpret_cast<const float2*>(hr ? eref : eout) + (size_t)col * H;
+  if (!eref) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) out2[G * r + s] = cscale(x[r], scale);
+    return;
+  }
+  // with a reference (the same for the whole launch): its loads issue
+  // together, ahead of the stores and the step partial
+  const float2* ref2 = reinterpret_cast<const float2*>(eref) + (size_t)col * H;
   float2 rv[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) rv[r] = ref2[G * r + s];
+  double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int p = G * r + s;
     const float2 y = cscale(x[r], scale);
     out2[p] = y;
     const float d0 = y.x - rv[r].x, d1 = y.y - rv[r].y;
-    acc += hr ? (double)d0 * (double)d0 + (double)d1 * (double)d1 : 0.0;
+    acc += (double)d0 * (double)d0 + (double)d1 * (double)d1;
   }
-  if (eref) {
-    double v[1] = {acc};
-    const int slots[1] = {SL_STEP};
-    block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);
-  }
+  double v[1] = {acc};
+  const int slots[1] = {SL_STEP};
+  block_sum_store<1>(v, ep.partials, slots, kMaxBlocks);
 }
 
 // Inverse t pass of a convolution fused with the forward t pass of the
@@ -1559,7 +1561,8 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
     dit_inlane<GS, ES, ES / 2>(y, ss, twc);
     const int col = col0 + bs;
     float2* out2 = reinterpret_cast<float2*>(eout) + (size_t)col * H;
-    // the reference is read unconditionally (see k_tinv_solve)
+    // the reference is read unconditionally (the output column stands in
+    // when there is none), so its loads are not each behind a branch and a wait
     const bool hr = eref != nullptr;
     const float2* ref2 = reinterpret_cast<const float2*>(hr ? eref : eout) + (size_t)col * H;
     float2* xf2 = lds + bs * ZS;                   // the column's real samples, as pairs
