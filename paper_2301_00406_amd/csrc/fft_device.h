@@ -46,17 +46,29 @@ __device__ __forceinline__ int brev(int x, int bits) {
 // ds_swizzle in bit-mask mode (lane' = lane ^ D within 32-lane halves);
 // D = 32: ds_bpermute.
 template <int D>
-__device__ __forceinline__ float lane_xor(float v) {
-  const int i = __float_as_int(v);
+__device__ __forceinline__ int lane_xor_bits(int i) {
   if constexpr (D == 1) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false));   // [1,0,3,2]
+    return __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);   // [1,0,3,2]
   } else if constexpr (D == 2) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false));   // [2,3,0,1]
+    return __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // [2,3,0,1]
   } else if constexpr (D < 32) {
-    return __int_as_float(__builtin_amdgcn_ds_swizzle(i, 0x1F | (D << 10)));
+    return __builtin_amdgcn_ds_swizzle(i, 0x1F | (D << 10));
   } else {
-    return __shfl_xor(v, D, 64);
+    return __shfl_xor(i, D, 64);
   }
+}
+
+template <int D>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(lane_xor_bits<D>(__float_as_int(v)));
+}
+
+template <int D>
+__device__ __forceinline__ double lane_xor_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)lane_xor_bits<D>((int)(unsigned)b);
+  const unsigned hi = (unsigned)lane_xor_bits<D>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 template <int D>
@@ -191,10 +203,33 @@ __device__ __forceinline__ void dit_inlane(float2 (&x)[E], int s, const float2* 
 // Deterministic FP64 reductions: wave shuffle, then LDS in lane order, then a
 // per-block partial written to partials[slot * max_blocks + blockIdx.x].
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+// Butterfly sums over the 64 lanes, offsets 32, 16, ..., 1 in that order, so
+// every lane ends with the same value and the order of the additions is
+// fixed.  The exchanges of all NV values at one offset issue together (one
+// wait per offset); offsets 1 and 2 are DPP moves, 4 .. 16 swizzles.
+template <int D, int NV>
+__device__ __forceinline__ void wave_xor_add(double (&v)[NV]) {
+  double o[NV];
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  for (int s = 0; s < NV; ++s) o[s] = lane_xor_d<D>(v[s]);
+#pragma unroll
+  for (int s = 0; s < NV; ++s) v[s] += o[s];
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_sum_n(double (&v)[NV]) {
+  wave_xor_add<32>(v);
+  wave_xor_add<16>(v);
+  wave_xor_add<8>(v);
+  wave_xor_add<4>(v);
+  wave_xor_add<2>(v);
+  wave_xor_add<1>(v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  double a[1] = {v};
+  wave_sum_n<1>(a);
+  return a[0];
 }
 
 template <int NV>
@@ -203,10 +238,10 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NV], double* __restr
   __shared__ double red[NV][16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
+  wave_sum_n<NV>(v);
+  if (lane == 0) {
 #pragma unroll
-  for (int s = 0; s < NV; ++s) {
-    const double w = wave_sum(v[s]);
-    if (lane == 0) red[s][wid] = w;
+    for (int s = 0; s < NV; ++s) red[s][wid] = v[s];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -229,20 +264,29 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
   __shared__ double red[K][16];
   double acc[K];
   // every load is issued before the first add (fixed trip counts, unrolled):
-  // one memory round trip for all K arrays and all chunks of blockDim
-  // partials (a load under a per-lane condition compiles to a branch with a
-  // wait after it, so the index is clamped and the value masked instead; the
-  // masked zeros leave each sum unchanged)
+  // one memory round trip for all K arrays and every chunk of blockDim
+  // partials that the longest array reaches (the chunk test is the same for
+  // the whole block; within a chunk a load under a per-lane condition would
+  // compile to a branch with a wait after it, so the index is clamped and the
+  // value masked instead; the masked zeros leave each sum unchanged)
   constexpr int kPer = 4;   // covers 4 x blockDim >= max_blocks partials (1024 threads)
+  int nbmax = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) nbmax = nb[k] > nbmax ? nb[k] : nbmax;
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
   double vals[kPer][K];
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const int i = threadIdx.x + j * (int)blockDim.x;
+    if (j * (int)blockDim.x < nbmax) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      vals[j][k] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
+      for (int k = 0; k < K; ++k)
+        vals[j][k] = partials[(size_t)slot[k] * max_blocks + (i < nb[k] ? i : 0)];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) vals[j][k] = 0.0;
+    }
   }
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
@@ -251,10 +295,10 @@ __device__ __forceinline__ void block_sum_partials_k(const double* __restrict__ 
     for (int k = 0; k < K; ++k) acc[k] += i < nb[k] ? vals[j][k] : 0.0;
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  wave_sum_n<K>(acc);
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double w = wave_sum(acc[k]);
-    if (lane == 0) red[k][wid] = w;
+    for (int k = 0; k < K; ++k) red[k][wid] = acc[k];
   }
   __syncthreads();
   if (threadIdx.x == 0) {

@@ -83,12 +83,12 @@ __device__ __forceinline__ int check_decision(const double* __restrict__ partial
       b += i < ck.nb_step ? vb[j] : 0.0;
     }
   }
-  a = wave_sum(a);
-  b = wave_sum(b);
+  double ab[2] = {a, b};
+  wave_sum_n<2>(ab);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
-    red[0][wid] = a;
-    red[1][wid] = b;
+    red[0][wid] = ab[0];
+    red[1][wid] = ab[1];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
