@@ -90,6 +90,50 @@ __device__ __forceinline__ void table_to_lds(T* dst, const T* __restrict__ src, 
   block_copy<NT, COUNT>(tid, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
 }
 
+// A block-strided copy split into its loads (into registers, indices clamped
+// into range) and its stores.  Copies whose loads are all issued before the
+// first store (copy_together) cost one memory round trip together, where
+// copies done one after the other wait for each in turn.
+template <int NT, int COUNT, typename T, typename Ld, typename St>
+struct SplitCopy {
+  static constexpr int NS = (COUNT + NT - 1) / NT;
+  Ld ld;
+  St st;
+  T v[NS];
+  __device__ __forceinline__ void load(int tid) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int it = tid + j * NT;
+      v[j] = ld(it < COUNT ? it : COUNT - 1);
+    }
+  }
+  // unconditional: a lane past the end stores the last element's value to
+  // the last element, as its owner does (a store under a per-lane condition
+  // lets the compiler sink its load into the branch, behind a wait for every
+  // load before it)
+  __device__ __forceinline__ void store(int tid) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int it = tid + j * NT;
+      st(it < COUNT ? it : COUNT - 1, v[j]);
+    }
+  }
+};
+template <int NT, int COUNT, typename Ld, typename St>
+__device__ __forceinline__ auto split_copy(Ld ld, St st) {
+  using T = decltype(ld(0));
+  return SplitCopy<NT, COUNT, T, Ld, St>{ld, st, {}};
+}
+template <typename... C>
+__device__ __forceinline__ void copy_together(int tid, C&&... c) {
+  (c.load(tid), ...);
+  (c.store(tid), ...);
+}
+template <int NT, int COUNT, typename T>
+__device__ __forceinline__ auto table_copy(T* dst, const T* __restrict__ src) {
+  return split_copy<NT, COUNT>([=](int i) { return src[i]; }, [=](int i, T v) { dst[i] = v; });
+}
+
 // LDS index of staging element (kt, column b): rows of J + 1 plus one extra
 // slot every 8 rows, so that rows kt and kt + 8 (bit-reversed neighbours) and
 // consecutive rows fall into different banks.
@@ -99,11 +143,11 @@ template <int J>
 constexpr int stg_size(int rows) { return rows * (J + 1) + rows / 8 + J; }
 // planes k < NP of the block's J columns <-> the LDS staging tile
 template <int J, int NT, int NP>
-__device__ __forceinline__ void planes_to_lds(float2* lds, const float2* __restrict__ spec, int nn,
-                                              int col0, int tid) {
-  block_copy<NT, NP * J>(
-      tid, [&](int it) { return spec[(size_t)(it / J) * nn + col0 + it % J]; },
-      [&](int it, float2 v) { lds[stg<J>(it / J, it % J)] = v; });
+__device__ __forceinline__ auto planes_copy(float2* lds, const float2* __restrict__ spec, int nn,
+                                            int col0) {
+  return split_copy<NT, NP * J>(
+      [=](int it) { return spec[(size_t)(it / J) * nn + col0 + it % J]; },
+      [=](int it, float2 v) { lds[stg<J>(it / J, it % J)] = v; });
 }
 template <int J, int NT, int NP>
 __device__ __forceinline__ void lds_to_planes(const float2* lds, float2* __restrict__ spec, int nn,
@@ -273,11 +317,17 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
   src.scale_div = zsh(src.scale_div, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, M>(twc, twcg, tid);
+  // the tables' loads issue with the operands' (one round trip for both);
+  // they reach LDS after the operands are loaded
+  auto t_tws = table_copy<NT, M>(tws, tw);
+  auto t_twc = table_copy<NT, M>(twc, twcg);
+  auto t_row = table_copy<NT, STAGE ? M : 1>(srow_l, S.rows);
+  auto t_val = table_copy<NT, NNZ>(sval_l, S.rvals);
+  t_tws.load(tid);
+  t_twc.load(tid);
   if constexpr (STAGE) {
-    table_to_lds<NT, M>(srow_l, S.rows, tid);
-    table_to_lds<NT, NNZ>(sval_l, S.rvals, tid);
+    t_row.load(tid);
+    t_val.load(tid);
   }
   const int4* srow = STAGE ? srow_l : S.rows;
   const float* sval = STAGE ? sval_l : S.rvals;
@@ -307,6 +357,12 @@ k_tfwd_conv(ConvSrc src, ResampleTables S, const float2* __restrict__ tw,
     vb[r] = pb[g];
     vc[r] = pc[g];
     vw[r] = pw[k];
+  }
+  t_tws.store(tid);
+  t_twc.store(tid);
+  if constexpr (STAGE) {
+    t_row.store(tid);
+    t_val.store(tid);
   }
   float xv[E];
 #pragma unroll
@@ -356,15 +412,16 @@ k_tinv_conv(const float2* __restrict__ spec, int nn, ResampleTables S,
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, M>(twc, twcg, tid);
-  if constexpr (STAGE) {
-    table_to_lds<NT, M>(scol_l, S.cols, tid);
-    table_to_lds<NT, NNZ>(sval_l, S.cvals, tid);
-  }
+  // tables and the block's planes: one round trip
+  if constexpr (STAGE)
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  table_copy<NT, M>(scol_l, S.cols), table_copy<NT, NNZ>(sval_l, S.cvals),
+                  planes_copy<J, NT, PK ? M : M + 1>(lds, spec, nn, col0));
+  else
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  planes_copy<J, NT, PK ? M : M + 1>(lds, spec, nn, col0));
   const int4* scol = STAGE ? scol_l : S.cols;
   const float* sval = STAGE ? sval_l : S.cvals;
-  planes_to_lds<J, NT, PK ? M : M + 1>(lds, spec, nn, col0, tid);
   __syncthreads();
   // packed even/odd spectrum at this lane's bit-reversed positions:
   // Z[k] = 1/2 (X_k + conj X_{m-k}) + i/2 conj(W^k) (X_k - conj X_{m-k})
@@ -1236,8 +1293,11 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
   spec = zsh(spec, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, H>(twc, twcg, tid);
+  // the tables' loads issue with the operands' (one round trip for both)
+  auto t_tws = table_copy<NT, M>(tws, tw);
+  auto t_twc = table_copy<NT, H>(twc, twcg);
+  t_tws.load(tid);
+  t_twc.load(tid);
   float2 x[E];
   if constexpr (SRC == RHS_LOAD) {
     src = zsh(src, zo);
@@ -1256,6 +1316,8 @@ k_tfwd_solve(const float* __restrict__ src, RhsSrc rs, const float2* __restrict_
     rhs_pairs<SRC, G, E, J, M, NT>(x, rs, ctl, xb, au, col0, b, s, tid, nn,
                                    reinterpret_cast<float*>(lds));
   }
+  t_tws.store(tid);
+  t_twc.store(tid);
   tfwd_solve_from_regs<LOGM, J, NT>(x, true, lds, tws, twc, tid, col0, spec, nn);
 }
 
@@ -1284,9 +1346,8 @@ k_tinv_solve(const float2* __restrict__ spec, int nn, const float2* __restrict__
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, H>(twc, twcg, tid);
-  planes_to_lds<J, NT, H>(lds, spec, nn, col0, tid);
+  copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, H>(twc, twcg),
+                planes_copy<J, NT, H>(lds, spec, nn, col0));
   __syncthreads();
   float2 x[E];
 #pragma unroll
@@ -1391,15 +1452,16 @@ k_tinv_conv_rhs(float2* __restrict__ spec, int nn, ResampleTables S,
   rs.mask = zsh(rs.mask, zo);
   const int tid = threadIdx.x, b = tid / G, s = tid % G;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J, col = col0 + b;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, M>(twc, twcg, tid);
-  if constexpr (STAGE) {
-    table_to_lds<NT, M>(scol_l, S.cols, tid);
-    table_to_lds<NT, NNZ>(sval_l, S.cvals, tid);
-  }
+  // tables and the block's planes: one round trip
+  if constexpr (STAGE)
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  table_copy<NT, M>(scol_l, S.cols), table_copy<NT, NNZ>(sval_l, S.cvals),
+                  planes_copy<J, NT, PK ? M : M + 1>(lds, spec, nn, col0));
+  else
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  planes_copy<J, NT, PK ? M : M + 1>(lds, spec, nn, col0));
   const int4* scol = STAGE ? scol_l : S.cols;
   const float* sval = STAGE ? sval_l : S.cvals;
-  planes_to_lds<J, NT, PK ? M : M + 1>(lds, spec, nn, col0, tid);
   __syncthreads();
   // adjoint inverse t pass (as k_tinv_conv, plain epilogue)
   float2 x[E];
@@ -1524,15 +1586,16 @@ k_tinv_solve_fwd(float2* __restrict__ spec, int nn, ResampleTables S,
   ep.partials = zsh(ep.partials, zo);
   const int tid = threadIdx.x;
   const int col0 = xcd_block(blockIdx.x, gridDim.x) * J;
-  table_to_lds<NT, M>(tws, tw, tid);
-  table_to_lds<NT, M>(twc, twcg, tid);
-  if constexpr (STAGE) {
-    table_to_lds<NT, M>(srow_l, S.rows, tid);
-    table_to_lds<NT, NNZ>(sval_l, S.rvals, tid);
-  }
+  // tables and the block's planes: one round trip
+  if constexpr (STAGE)
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  table_copy<NT, M>(srow_l, S.rows), table_copy<NT, NNZ>(sval_l, S.rvals),
+                  planes_copy<J, NT, H>(lds, spec, nn, col0));
+  else
+    copy_together(tid, table_copy<NT, M>(tws, tw), table_copy<NT, M>(twc, twcg),
+                  planes_copy<J, NT, H>(lds, spec, nn, col0));
   const int4* srow = STAGE ? srow_l : S.rows;
   const float* sval = STAGE ? sval_l : S.rvals;
-  planes_to_lds<J, NT, H>(lds, spec, nn, col0, tid);
   __syncthreads();
   // solve phase: packed real inverse of length m (as k_tinv_solve)
   const bool sact = tid < J * GS;

@@ -70,6 +70,9 @@ def test_benchmark_configuration_matches_the_stored_oracle_run():
 
 
 
+# builds the 128x128x1024 problem and compares full volumes on the host:
+# more than a minute of host time
+@pytest.mark.timeout(600)
 def test_large_configuration_first_iterations_match_the_stored_oracle_run():
     """128x128x1024 (the large workload), one warm-start and one Algorithm-2
     iteration against the stored full-size oracle run: 64 sampled scan
