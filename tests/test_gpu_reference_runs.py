@@ -69,7 +69,6 @@ def test_benchmark_configuration_matches_the_stored_oracle_run():
     P.close()
 
 
-
 # builds the 128x128x1024 problem and compares full volumes on the host:
 # more than a minute of host time
 @pytest.mark.timeout(600)
