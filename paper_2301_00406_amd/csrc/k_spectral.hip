@@ -566,8 +566,11 @@ __device__ __forceinline__ void col_inv(float2 (&c)[PlaneRegCfg<LOGN>::RE], int 
 //   Y(k) = Z^(k) (H_0 + H_m)/2 + conj(Z^(-k)) (H_0 - H_m)/2,
 // the spectrum of conv(P_0) + i conv(P_m) (H_0, H_m real and even).  Plane 0
 // of H^ holds the two factors as one pair (k_hq_pack_real).
+// h0: plane 0 of H^ at this lane's positions of its first column, loaded by
+// the caller before the column transforms.
 template <int LOGN, int PAD>
 __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* Hab,
+                                                       const float2 (&h0)[PlaneRegCfg<LOGN>::RE],
                                                        const float2* tws, const float2* twc,
                                                        int tid) {
   using PC = PlaneRegCfg<LOGN>;
@@ -598,7 +601,7 @@ __device__ __forceinline__ void plane_conv_cols_packed(float2* Y, const float2* 
       const int fx = kxs + brev(r, LOGL - 3);
       const int pp = brev((L - fx) & (L - 1), LOGL);
       const float2 own = Y[p * YS + col], par = Y[pp * YS + colp];
-      const float2 ab = Hab[(r * L + col) * 8 + s];      // lane-ordered H^ plane 0
+      const float2 ab = half == 0 ? h0[r] : Hab[(r * L + col) * 8 + s];   // lane-ordered H^ plane 0
       w[half][r] = make_float2(ab.x * own.x + ab.y * par.x, ab.x * own.y - ab.y * par.y);
     }
   }
@@ -631,48 +634,52 @@ k_plane_conv_reg(float2* __restrict__ spec, const float2* __restrict__ hq,
   hq = zsh(hq, (size_t)blockIdx.z * hzs);   // 0: one H^ for every scene
   tw = zsh(tw, zo);
   twcg = zsh(twcg, zo);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, row = tid >> 3, s = tid & 7;
   float2* P = spec + (size_t)blockIdx.x * N * N;
   const float2* Hp = hq + (size_t)blockIdx.x * L * L;     // lane-ordered H^ of this plane
-  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
-  for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
+  // the block's rows and both twiddle tables in one round trip (NT >= L >=
+  // N: every thread copies the entry of its index modulo the table size, so
+  // entries are written more than once, always with their own value)
+  float2 x[RE], h0[RE];
+#pragma unroll
+  for (int r = 0; r < RE / 2; ++r) x[r] = P[row * N + 8 * r + s];
+  const float2 tv_s = tw[tid % N];
+  const float2 tv_c = twcg[tid % L];
+  tws[tid % N] = tv_s;
+  twc[tid % L] = tv_c;
   __syncthreads();
-  {
-    const int row = tid >> 3, s = tid & 7;
-    float2 x[RE];
 #pragma unroll
-    for (int r = 0; r < RE / 2; ++r) x[r] = P[row * N + 8 * r + s];
+  for (int r = 0; r < RE / 2; ++r) x[r + RE / 2] = cmul(x[r], tws[8 * r + s]);
+  dif_inlane<8, RE, RE / 4>(x, s, twc);
+  dif_xlane<8, RE>(x, s, twc);
 #pragma unroll
-    for (int r = 0; r < RE / 2; ++r) x[r + RE / 2] = cmul(x[r], tws[8 * r + s]);
-    dif_inlane<8, RE, RE / 4>(x, s, twc);
-    dif_xlane<8, RE>(x, s, twc);
-#pragma unroll
-    for (int r = 0; r < RE; ++r) Y[row * YS + 8 * r + s] = x[r];
-  }
+  for (int r = 0; r < RE; ++r) Y[row * YS + 8 * r + s] = x[r];
   __syncthreads();
+  // H^ at this lane's positions of a spectrum column (a wave's load of
+  // register r reads 64 consecutive entries) is loaded before the column's
+  // transforms, whose work hides its latency
+#pragma unroll
+  for (int r = 0; r < RE; ++r) h0[r] = Hp[(r * L + row) * 8 + s];
   if (blockIdx.x == 0) {
-    plane_conv_cols_packed<LOGN, PAD>(Y, hq, tws, twc, tid);
+    plane_conv_cols_packed<LOGN, PAD>(Y, hq, h0, tws, twc, tid);
   } else {
     // 2n spectrum columns, 8 lanes each, two columns per lane group
-    const int s = tid & 7;
-#pragma unroll 1
-    for (int half = 0; half < 2; ++half) {
-      const int col = (tid >> 3) + half * N;
+    auto column = [&](int col, const float2 (&h)[RE]) {
       float2 c[RE];
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
       col_fwd<LOGN>(c, s, tws, twc);
-      // H^ at this lane's positions: a wave's load of register r reads 64
-      // consecutive entries
 #pragma unroll
-      for (int r = 0; r < RE; ++r) {
-        const float2 h = Hp[(r * L + col) * 8 + s];
-        c[r] = ADJ ? cmulc(c[r], h) : cmul(c[r], h);
-      }
+      for (int r = 0; r < RE; ++r) c[r] = ADJ ? cmulc(c[r], h[r]) : cmul(c[r], h[r]);
       col_inv<LOGN>(c, s, tws, twc);
 #pragma unroll
       for (int r = 0; r < RE / 2; ++r) Y[(8 * r + s) * YS + col] = c[r];
-    }
+    };
+    column(row, h0);
+    float2 h1[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) h1[r] = Hp[(r * L + row + N) * 8 + s];
+    column(row + N, h1);
   }
   __syncthreads();
   {
@@ -1012,15 +1019,16 @@ k_plane_solve_reg(float2* __restrict__ spec, const float2* __restrict__ twcg,
   const int tid = threadIdx.x;
   const int plane = blockIdx.x;
   float2* P = spec + (size_t)plane * N * N;
+  const int g = tid / LN, s = tid % LN;
+  // the plane's loads issue before the tables' copy waits for its own
+  float2 x[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) x[r] = P[g * N + LN * r + s];
   for (int i = tid; i < N; i += NT) {
     twc[i] = twcg[i];
     sg[i] = sig_xy[i];
   }
   __syncthreads();
-  const int g = tid / LN, s = tid % LN;
-  float2 x[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) x[r] = P[g * N + LN * r + s];
   dif_inlane<LN, E, E / 2>(x, s, twc);
   dif_xlane<LN, E>(x, s, twc);
 #pragma unroll
