@@ -746,21 +746,32 @@ __device__ __forceinline__ void half_cols(int h, float2* Y, const float2* Hp, co
 #pragma unroll 1
   for (int i = 0; i < 2; ++i) {
     const int col = g + G * i;
+    // H^ (lane-ordered: a wave's load reads 64 consecutive entries) in chunks
+    // of 8, so that its loads do not all stay live at once; the first chunk
+    // is loaded before the forward transform and each next one before the
+    // products of the current one, so that their latency is hidden
+    const float2* Hh = Hp + ((size_t)h * RE * N + col) * 8 + s;
+    float2 hc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) hc[r] = Hh[r * N * 8];
     float2 c[RE];
 #pragma unroll
     for (int r = 0; r < RE / 2; ++r) c[r] = Y[(8 * r + s) * YS + col];
     col_fwd<LOGN>(c, s, tws, twc);
-    // H^ (lane-ordered: a wave's load reads 64 consecutive entries) in chunks
-    // of 8, so that its loads do not all stay live at once
-    const float2* Hh = Hp + ((size_t)h * RE * N + col) * 8 + s;
 #pragma unroll
     for (int r0 = 0; r0 < RE; r0 += 8) {
+      float2 hn[8];
+      if (r0 + 8 < RE) {
 #pragma unroll
-      for (int r = r0; r < r0 + 8; ++r) {
-        const float2 hv = Hh[r * N * 8];
-        c[r] = ADJ ? cmulc(c[r], hv) : cmul(c[r], hv);
+        for (int r = 0; r < 8; ++r) hn[r] = Hh[(r0 + 8 + r) * N * 8];
       }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) c[r0 + r] = ADJ ? cmulc(c[r0 + r], hc[r]) : cmul(c[r0 + r], hc[r]);
       __builtin_amdgcn_sched_barrier(0);
+      if (r0 + 8 < RE) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) hc[r] = hn[r];
+      }
     }
     col_inv<LOGN>(c, s, tws, twc);
 #pragma unroll
@@ -910,16 +921,22 @@ __device__ __forceinline__ void half_row_inv(float2 (&v)[PlaneHalfCfg<LOGN>::RN]
 // rows back, the odd half accumulated onto the even one.
 template <int LOGN, bool ADJ, bool PACKED, int PAD>
 __device__ __forceinline__ void plane_half_body(float2* __restrict__ P, const float2* Hp,
-                                                float2* Y, const float2* tws, const float2* twc,
-                                                int g, int s) {
+                                                float2* Y, float2* tws, float2* twc, float2 tv_s,
+                                                float2 tv_c, int g, int s) {
   using PC = PlaneHalfCfg<LOGN>;
-  constexpr int N = PC::N, G = PC::G, RN = PC::RN;
+  constexpr int N = PC::N, L = PC::L, G = PC::G, RN = PC::RN;
   // even ky half; each thread owns plane elements (g + G i, 8 r + s) throughout
   float2 v[2][RN];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < RN; ++r) v[i][r] = P[(g + G * i) * N + 8 * r + s];
+  {
+    const int tid = threadIdx.x;
+    tws[tid % N] = tv_s;
+    twc[tid % L] = tv_c;
+  }
+  __syncthreads();
   half_rows_fwd<LOGN, PAD>(v, 0, Y, tws, twc, g, s);
   __syncthreads();
   if constexpr (PACKED) half_cols_packed<LOGN, PAD>(0, Y, Hp, tws, twc, g, s);
@@ -976,13 +993,13 @@ k_plane_conv_half(float2* __restrict__ spec, const float2* __restrict__ hq,
   const int tid = threadIdx.x, g = tid >> 3, s = tid & 7;
   float2* P = spec + (size_t)blockIdx.x * N * N;
   const float2* Hp = hq + (size_t)blockIdx.x * L * L;     // lane-ordered H^ of this plane
-  for (int i = tid; i < N; i += NT) tws[i] = tw[i];
-  for (int i = tid; i < L; i += NT) twc[i] = twcg[i];
-  __syncthreads();
+  // twiddle tables: every thread copies the entry of its index modulo the
+  // table size (NT >= L >= N), in the same round trip as the first rows
+  const float2 tv_s = tw[tid % N], tv_c = twcg[tid % L];
   // block 0: the packed real planes kt = 0 and kt = m, a separate path so that
   // its register demand does not weigh on the other blocks' code
-  if (blockIdx.x == 0) plane_half_body<LOGN, ADJ, true, PAD>(P, Hp, Y, tws, twc, g, s);
-  else plane_half_body<LOGN, ADJ, false, PAD>(P, Hp, Y, tws, twc, g, s);
+  if (blockIdx.x == 0) plane_half_body<LOGN, ADJ, true, PAD>(P, Hp, Y, tws, twc, tv_s, tv_c, g, s);
+  else plane_half_body<LOGN, ADJ, false, PAD>(P, Hp, Y, tws, twc, tv_s, tv_c, g, s);
 }
 
 // Register-resident plane kernel of the diagonal solve (n <= 128): rows and
