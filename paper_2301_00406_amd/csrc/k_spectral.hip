@@ -85,10 +85,6 @@ __device__ __forceinline__ void block_copy(int tid, Ld ld, St st) {
     }
   }
 }
-template <int NT, int COUNT, typename T>
-__device__ __forceinline__ void table_to_lds(T* dst, const T* __restrict__ src, int tid) {
-  block_copy<NT, COUNT>(tid, [&](int i) { return src[i]; }, [&](int i, T v) { dst[i] = v; });
-}
 
 // A block-strided copy split into its loads (into registers, indices clamped
 // into range) and its stores.  Copies whose loads are all issued before the
